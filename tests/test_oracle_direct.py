@@ -1,0 +1,161 @@
+"""Pins of the oracle's direct transforms (Thm. 3.4, Alg. 1, Alg. 2, Sect. 3.4, Table 1)."""
+
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import direct as D, mp_direct, quadrature as Q
+from paper_1604_05140_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load_closed_forms():
+    rows = []
+    with open(os.path.join(GOLDEN, "closed_form_transforms.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, n, l, m, expr = line.split(None, 4)
+            with mp.workdps(30):
+                val = float(eval(expr, {"__builtins__": {}}, {"pi": mp.pi, "sqrt": mp.sqrt}))
+            rows.append((name, int(n), int(l), int(m), val))
+    return rows
+
+
+def _poly(name, x, y, z):
+    return {"1": np.ones_like(x), "z": z, "x+iy": x + 1j * y, "x-iy": x - 1j * y,
+            "r2": x * x + y * y + z * z}[name]
+
+
+@pytest.mark.parametrize("B", [2, 3, 5, 8])
+def test_closed_form_coefficients(B):
+    """Forward transform of low-degree polynomials sampled in Cartesian form."""
+    rows = _load_closed_forms()
+    x, y, z = D.sample_grid_points(B).T
+    for name in sorted({r[0] for r in rows}):
+        f = _poly(name, x, y, z)
+        fh = D.forward(D.scale_raw(f, B), B)
+        ref = np.zeros_like(fh)
+        for (nm, n, l, m, v) in rows:
+            if nm == name:
+                ref[D.omega(n, l, m)] = v
+        assert np.abs(fh - ref).max() < 1e-13 * 4, (B, name)
+
+
+@pytest.mark.parametrize("B", [1, 2, 4, 6])
+def test_sgl_gram_is_identity(B):
+    """Thm. 3.4 applied to products of basis functions: sum_psi w_psi H_w conj(H_w') = delta."""
+    bs = D.get_basis(B)
+    Hs = np.stack([bs.scaled_function(n, l, m).reshape(-1) for (n, l, m) in bs.nlm])
+    w = np.broadcast_to(bs.grid["btilde"][None, :, None], (2 * B,) * 3).reshape(-1)
+    G = (Hs * w) @ Hs.conj().T
+    assert np.abs(G - np.eye(D.num_coeffs(B))).max() < 1e-13
+
+
+def test_index_maps():
+    """omega enumerates (n,l,m) consecutively (Sect. 3.4); Omega and Psi sizes."""
+    for B in (1, 2, 7):
+        lst = D.nlm_list(B)
+        assert [D.omega(*t) for t in lst] == list(range(D.num_coeffs(B)))
+        assert len(lst) == D.num_coeffs(B)
+    assert D.num_coeffs(128) == 707264 and D.num_samples(128) == 16777216
+    assert (synth.degree_of_each_coeff(5) == np.array([n for (n, l, m) in D.nlm_list(5)])).all()
+
+
+@pytest.mark.parametrize("B", [4, 8, 12])
+def test_round_trip_recovers_coefficients(B):
+    """Thm. 3.4: bandlimited coefficients -> synthesis -> analysis is the identity."""
+    c = synth.complex_normal_coeffs(B, 1, seed=synth.BASE_SEED + 1)[0]
+    s = D.inverse(c, B)
+    c2 = D.forward(s, B)
+    assert D.error_metrics(c, c2)["e_inf"] < 1e-13
+
+
+def test_round_trip_error_within_paper_envelope():
+    """The paper's own protocol (Sect. 4: U(-1,1) coefficients, inverse then forward)
+    stays within the FP64 errors printed for the naive transforms in Table 1."""
+    table = {}
+    with open(os.path.join(GOLDEN, "paper_table1_errors.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                p = line.split()
+                table[int(p[0])] = p[1:]
+    for B in (2, 4, 8):
+        errs = []
+        for rep in range(10):
+            c = synth.uniform_coeffs(B, 1, seed=synth.BASE_SEED + 100 + rep)[0]
+            c2 = D.forward(D.inverse(c, B), B)
+            errs.append(np.abs(c2 - c).max())
+        naive_abs = float(table[B][0])
+        assert np.mean(errs) <= 3 * naive_abs, (B, np.mean(errs), naive_abs)
+
+
+def test_subsets_agree_with_full():
+    B = 5
+    c = synth.complex_normal_coeffs(B, 1, seed=3)[0]
+    s = D.inverse(c, B)
+    pts = synth.grid_points(40, B, seed=4)
+    sub = D.inverse(c, B, points=pts)
+    full = s.reshape(2 * B, 2 * B, 2 * B)[pts[:, 0], pts[:, 1], pts[:, 2]]
+    assert np.abs(sub - full).max() < 1e-14
+    x = synth.complex_normal_samples(B, 1, seed=5)[0]
+    oms = synth.subset(30, D.num_coeffs(B), seed=6)
+    np.testing.assert_allclose(D.forward(x, B, omegas=oms), D.forward(x, B)[oms], rtol=0, atol=1e-14)
+
+
+def test_adjoint_identity():
+    """Sect. 3.4: the inverse is the Hermitian transpose of the forward map with the
+    weights removed: <F s, c> = sum_psi b~_j s_psi conj((F^-1 c)_psi)."""
+    B = 5
+    s = synth.complex_normal_samples(B, 1, seed=11)[0]
+    c = synth.complex_normal_coeffs(B, 1, seed=12)[0]
+    lhs = np.vdot(c, D.forward(s, B))
+    w = np.broadcast_to(Q.polar_weights(B)[None, :, None], (2 * B,) * 3).reshape(-1)
+    rhs = np.sum(w * s * np.conj(D.inverse(c, B)))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_raw_and_scaled_forms_agree():
+    B = 6
+    c = synth.complex_normal_coeffs(B, 1, seed=21)[0]
+    f = D.inverse(c, B, raw=True)
+    s = D.inverse(c, B)
+    np.testing.assert_allclose(D.scale_raw(f, B), s, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(D.forward(f, B, raw=True), c, rtol=0, atol=1e-13)
+
+
+def test_impulse():
+    B = 6
+    for om in (0, 7, 50, D.num_coeffs(B) - 1):
+        e = np.zeros(D.num_coeffs(B), dtype=complex)
+        e[om] = 1
+        assert np.abs(D.forward(D.inverse(e, B), B) - e).max() < 1e-13
+
+
+def test_fp64_oracle_matches_50_digit_brute_force():
+    """Alg. 1 and Alg. 2 summed literally at 50 digits (independent nodes, weights and
+    basis routines) agree with the FP64 oracle at B = 2, on raw samples."""
+    B = 2
+    c = synth.complex_normal_coeffs(B, 1, seed=31)[0]
+    with mp.workdps(mp_direct.DPS):
+        f = mp_direct.inverse_raw([mp.mpc(v) for v in c], B)
+    f64 = np.array([[[complex(f[i][j][k]) for k in range(4)] for j in range(4)] for i in range(4)]).reshape(-1)
+    assert np.abs(D.inverse(c, B, raw=True) - f64).max() <= 1e-14 * np.abs(f64).max()
+    x = synth.complex_normal_samples(B, 1, seed=32)[0]
+    xg = x.reshape(4, 4, 4)
+    with mp.workdps(mp_direct.DPS):
+        ch = mp_direct.forward_raw([[[mp.mpc(xg[i, j, k]) for k in range(4)] for j in range(4)] for i in range(4)], B)
+    ch64 = np.array([complex(v) for v in ch])
+    assert np.abs(D.forward(x, B, raw=True) - ch64).max() <= 1e-14 * np.abs(ch64).max()
+
+
+def test_error_metrics():
+    ref = np.array([1.0, 0.5j, -2.0])
+    got = ref + np.array([1e-3, 0, 0])
+    e = D.error_metrics(ref, got)
+    assert abs(e["e_inf"] - 5e-4) < 1e-15 and abs(e["paper"] - 1e-3) < 1e-15 and abs(e["abs"] - 1e-3) < 1e-15
