@@ -1,0 +1,227 @@
+"""Benchmark: SGL forward+inverse transforms/s at B = 128, batch 4 (libsgl on one MI355X).
+
+One step = one forward (Alg. 3) and one inverse (Alg. 4) transform of the whole
+batch: stage (a) azimuthal FFT, stage (b) Legendre projection, stage (c)
+radial projection, and back.  Inputs are resident in HBM before timing:
+complex-normal coefficients times 1/n (seeded), and the samples the plain FP64
+GPU path synthesizes from them, rounded to complex64 for the reduced-precision
+forms.  The headline form is the three-piece split-bf16 MFMA path; the plain
+FP64 GPU path is timed beside it, and the split results are checked against it
+(e_inf = max|delta| / max|ref| per function) before timing.
+
+Prints one JSON line.  Also reports per-stage kernel times (HIP events recorded
+on the launch stream inside the timed region), the roofline position of the
+dominant kernel, and the CPU oracle timed on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+STAGES = ["fwd_a_fft", "fwd_b_legendre", "fwd_c_radial", "inv_c_radial", "inv_b_legendre", "inv_a_fft"]
+PEAK = {"hbm_GBs": 8000.0, "f64": 78.6, "f32": 157.3, "bf16": 2500.0}  # TFLOP/s, MI355X published dense
+
+
+def num_coeffs(B):
+    return B * (B + 1) * (2 * B + 1) // 6
+
+
+def stage_work(B, nf, dtype):
+    """Algorithmic flops and HBM bytes of one launch of each stage (per launch)."""
+    es = 16 if dtype == "f64" else 8
+    Om = num_coeffs(B)
+    samples = 8 * B ** 3 * nf * es
+    F = (2 * B - 1) * 4 * B * B * nf * es
+    g = 2 * B ** 3 * nf * es
+    coef = Om * nf * es
+    tab = B * B * (B + 1) * {"f64": 8, "f32": 4, "split_bf16": 6}[dtype]
+    mult = 6 if dtype == "split_bf16" else 1  # the split form issues six bf16 products per MAC
+    fb = 16 * B ** 4 * nf * mult
+    fc = 8 * B * Om * nf * mult
+    fft_flops = 5 * 2 * B * math.log2(2 * B) * 4 * B * B * nf
+    return {
+        "fwd_a_fft": (fft_flops, samples + F),
+        "fwd_b_legendre": (fb, F + g + tab),
+        "fwd_c_radial": (fc, g + coef + tab),
+        "inv_c_radial": (fc, coef + g + tab),
+        "inv_b_legendre": (fb, g + F + tab),
+        "inv_a_fft": (fft_flops, F + samples),
+    }
+
+
+def run_form(sgl, torch, plan, c_in, s_in, steps, warmup):
+    dev = c_in.device
+    cout = torch.empty(plan.total_coeffs, dtype=plan.complex_dtype, device=dev)
+    sout = torch.empty(plan.total_samples, dtype=plan.complex_dtype, device=dev)
+    for _ in range(warmup):
+        sgl.sgl_forward(plan, s_in, cout)
+        sgl.sgl_inverse(plan, c_in, sout)
+    torch.cuda.synchronize()
+    plan.stage_times()  # reset
+    plan.set_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        sgl.sgl_forward(plan, s_in, cout)
+        sgl.sgl_inverse(plan, c_in, sout)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st_ms, st_cnt = plan.stage_times()
+    plan.set_timing(False)
+    per_stage = {STAGES[q]: (st_ms[q] / st_cnt[q] if st_cnt[q] else None) for q in range(6)}
+    return ms / steps, per_stage, cout, sout
+
+
+def cpu_baseline(B, n_coef, n_pts, seed):
+    """The oracle (plain direct quadrature sums) on a bounded sample, scaled to a full transform."""
+    from oracle import direct as D
+    from paper_1604_05140_amd import synth
+
+    D.get_basis(B)  # nodes, weights and basis tables (set-up, not timed)
+    s = synth.complex_normal_samples(B, 1, seed=seed)[0]
+    c = synth.complex_normal_coeffs(B, 1, seed=seed + 1, decay=1.0)[0]
+    oms = synth.subset(n_coef, D.num_coeffs(B), seed=seed + 2)
+    pts = synth.grid_points(n_pts, B, seed=seed + 3)
+    t0 = time.perf_counter()
+    D.forward(s, B, omegas=oms)
+    t1 = time.perf_counter()
+    D.inverse(c, B, points=pts)
+    t2 = time.perf_counter()
+    t_full = (t1 - t0) / n_coef * D.num_coeffs(B) + (t2 - t1) / n_pts * D.num_samples(B)
+    return {
+        "value": 1.0 / t_full,
+        "unit": "transforms/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"B={B}: forward quadrature sum for {n_coef} seeded coefficients ({t1 - t0:.1f} s) and "
+                   f"inverse synthesis sum at {n_pts} seeded grid points ({t2 - t1:.1f} s), scaled to all "
+                   f"{D.num_coeffs(B)} coefficients and {D.num_samples(B)} points of one forward+inverse pair "
+                   f"(extrapolated {t_full:.3g} s per pair); numpy, single thread"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--B", type=int, default=128)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--dtype", default="split_bf16", choices=["split_bf16", "f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and FP32 side runs")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one MI355X: the SGL transforms are not sharded across GPUs here "
+              "(--gpus must be 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1604_05140_amd import sgl, synth
+
+    dev = torch.device("cuda:0")
+    B, nf = args.B, args.batch
+    ns, nc = 8 * B ** 3, num_coeffs(B)
+    print(f"[bench] B={B} batch={nf} form={args.dtype}: building inputs", file=sys.stderr, flush=True)
+    c = synth.complex_normal_coeffs(B, nf, seed=synth.BASE_SEED + 3, decay=1.0).reshape(-1)
+    c128 = torch.from_numpy(c).to(dev)
+    p64 = sgl.sgl_plan(B, nf, "f64")
+    s128 = torch.empty(p64.total_samples, dtype=torch.complex128, device=dev)
+    sgl.sgl_inverse(p64, c128, s128)
+    c_ref = torch.empty_like(c128)
+    sgl.sgl_forward(p64, s128, c_ref)
+    torch.cuda.synchronize()
+
+    def einf(ref, got, n):
+        ref = ref.reshape(-1, n).to(torch.complex128)
+        got = got.reshape(-1, n).to(torch.complex128)
+        return float(((got - ref).abs().amax(dim=1) / ref.abs().amax(dim=1)).max())
+
+    rt64 = einf(c128, c_ref, nc)
+    forms = {}
+    order = [args.dtype] + ([] if args.no_compare else [d for d in ("f64", "f32") if d != args.dtype])
+    for dtype in order:
+        plan = p64 if dtype == "f64" else sgl.sgl_plan(B, nf, dtype)
+        s_in = s128 if dtype == "f64" else s128.to(torch.complex64)
+        c_in = c128 if dtype == "f64" else c128.to(torch.complex64)
+        steps = args.steps if dtype == args.dtype else max(3, args.steps // 4)
+        warm = args.warmup if dtype == args.dtype else 2
+        print(f"[bench] timing {dtype}: {warm} warmup + {steps} steps", file=sys.stderr, flush=True)
+        ms, per_stage, cout, sout = run_form(sgl, torch, plan, c_in, s_in, steps, warm)
+        forms[dtype] = {
+            "ms_per_step": ms,
+            "transforms_per_s": nf * 1000.0 / ms,
+            "stage_ms": per_stage,
+            "steps": steps,
+            "e_inf_forward_vs_f64": einf(c_ref, cout, nc),
+            "e_inf_inverse_vs_f64": einf(s128, sout, ns),
+        }
+        print(f"[bench] {dtype}: {ms:.3f} ms/step, {nf * 1000.0 / ms:.1f} transforms/s", file=sys.stderr,
+              flush=True)
+        del cout, sout
+        if dtype != "f64":
+            plan.destroy()
+
+    head = forms[args.dtype]
+    # roofline of the dominant kernel of the headline form
+    work = stage_work(B, nf, args.dtype)
+    dom = max((k for k in STAGES if head["stage_ms"][k]), key=lambda k: head["stage_ms"][k])
+    flops, nbytes = work[dom]
+    t_s = head["stage_ms"][dom] / 1000.0
+    if "fft" in dom:
+        roof = {"bound": "hbm", "achieved": nbytes / t_s / 1e9, "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
+    else:
+        pk = {"f64": PEAK["f64"], "f32": PEAK["f32"], "split_bf16": PEAK["bf16"]}[args.dtype]
+        roof = {"bound": "mfma", "achieved": flops / t_s / 1e12, "peak": pk, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = head["stage_ms"][dom]
+
+    out = {
+        "metric": "SGL fwd+inv transforms/s at B=128 (MFMA split vs FP64), rel err <=1e-6",
+        "value": head["transforms_per_s"],
+        "unit": "transforms/s",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"split_bf16": "bf16x3 (fp32 accumulate)", "f32": "f32", "f64": "f64"}[args.dtype],
+        "data": "synthetic",
+        "config": {
+            "workload": f"SGL forward+inverse, B={B}, batch {nf}, complex-normal/n coefficients, "
+                        f"{'complex128' if args.dtype == 'f64' else 'complex64'} scaled samples on the "
+                        f"sampling-theorem grid",
+            "B": B, "batch": nf, "form": args.dtype,
+        },
+        "e_inf_vs_f64": max(head["e_inf_forward_vs_f64"], head["e_inf_inverse_vs_f64"]),
+        "f64_round_trip_e_inf": rt64,
+        "forms": forms,
+        "roofline": roof,
+    }
+    if "f64" in forms and args.dtype != "f64":
+        out["speedup_vs_f64"] = head["transforms_per_s"] / forms["f64"]["transforms_per_s"]
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(B, 16, 200, synth.BASE_SEED + 7)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,159 @@
+/*
+ * libsgl -- fast spherical Gauss-Laguerre (SGL) Fourier transforms on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Prestin & Wuelker, "Fast Fourier Transforms for Spherical
+ * Gauss-Laguerre Basis Functions" (arXiv:1604.05140).
+ *
+ *   Forward (FSGLFT, Alg. 3): samples of a function with bandlimit B on the
+ *   grid of the SGL sampling theorem (Thm. 3.4) -> coefficients fhat_nlm,
+ *   |m| <= l < n <= B, equal to the quadrature sum
+ *       fhat_nlm = sum_{i,j,k<2B} a_i r_i^2 b~_j f(r_i,th_j,ph_k) conj(H_nlm(r_i,th_j,ph_k)).
+ *   Inverse (iFSGLFT, Alg. 4): coefficients -> samples
+ *       f(r_i,th_j,ph_k) = sum_{nlm} fhat_nlm H_nlm(r_i,th_j,ph_k).
+ *   Both are computed in O(B^4) by separation of variables (Sect. 3.3):
+ *   an FFT over the azimuth of every (r_i, th_j) ring, a Legendre projection
+ *   per order m (Eq. DLT), and a radial projection per degree l (Eq. DRT).
+ *
+ * Grid (Thm. 3.4): r_i, a_i = nodes and weights of the 2B-point half-range
+ * Gauss-Hermite rule (Thm. 3.3); th_j = (2j+1) pi / (4B), ph_k = k pi / B
+ * (Thm. 3.1), j, k < 2B.  The polar weight is b~_j = (pi/B) b_j with b_j as
+ * printed in Thm. 3.1: the printed b_j sum to 2 over j, and the double sum
+ * over (j, k) needs the azimuthal step pi/B as well.
+ *
+ * Layouts (Sect. 3.4), all complex values interleaved (re, im):
+ *   samples      f[psi],    psi   = 4B^2 i + 2B j + k          (8 B^3 values)
+ *   coefficients fhat[omega], omega = n(n-1)(2n-1)/6 + l(l+1) + m (B(B+1)(2B+1)/6 values)
+ *   a batch of functions is stored back to back (function b at b * count).
+ *
+ * Sample scaling.  By default samples are "scaled": s_ijk = sigma_i f(r_i,
+ * th_j, ph_k) with sigma_i = sqrt(a_i) r_i.  The forward map then reads
+ * fhat_nlm = sum b~_j s_ijk conj(sigma_i H_nlm), the inverse writes s.  This is
+ * the paper's exp(r^2) weight compensation (Sect. 3.2, Sect. 5) carried to
+ * both sides: raw samples grow like 10^B at the outer radii and leave the FP32
+ * range for B > ~40, scaled samples stay below 1 in magnitude.  With
+ * SGL_SAMPLES_RAW (FP64 plans only) the library takes and returns raw f.
+ *
+ * Precision (dtype):
+ *   SGL_F64         complex128 samples/coefficients; every stage in FP64
+ *                   (stages (b), (c) on FP64 MFMA).
+ *   SGL_F32         complex64; FFT in FP32; stages (b), (c) on FP32 MFMA.
+ *   SGL_SPLIT_BF16  complex64; FFT in FP32; stages (b), (c) as three-piece
+ *                   bfloat16 splits of both operands, the six products of
+ *                   order <= 2 on bf16 MFMA, accumulated in FP32.
+ *   Quadrature nodes/weights and the Legendre/radial basis tables are always
+ *   computed on the GPU in FP64 (three-term recurrences) and rounded once.
+ *
+ * Conventions.
+ *   - The caller allocates and owns every sample/coefficient buffer (device
+ *     memory); the plan owns its tables, workspace and streams.
+ *   - Calls taking a stream are stream-ordered and asynchronous: they enqueue
+ *     kernels and return; they never allocate, free or synchronize.  Plans
+ *     are not thread-safe: one plan must not run two calls at once (its
+ *     workspace is shared by forward and inverse).
+ *   - Input buffers are never written.  Input and output must not overlap
+ *     (SGL_ERR_INVALID_ARG).
+ *   - Errors are returned as status codes; sgl_last_error() gives a message.
+ *     Plan creation is all-or-nothing: on failure *out is NULL and nothing
+ *     is leaked.
+ */
+#ifndef SGL_H
+#define SGL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgl_plan_s* sgl_plan_t;
+
+typedef enum {
+  SGL_OK = 0,
+  SGL_ERR_INVALID_ARG = 1, /* bad size, null pointer, aliasing, unknown flag   */
+  SGL_ERR_UNSUPPORTED = 2, /* valid request this build does not support        */
+  SGL_ERR_HIP = 3,         /* a HIP runtime call failed (see sgl_last_error)  */
+  SGL_ERR_OOM = 4,         /* device allocation failed                         */
+  SGL_ERR_NUMERIC = 5      /* plan-time FP64 quadrature failed a self-check    */
+} sgl_status_t;
+
+typedef enum { SGL_F64 = 0, SGL_F32 = 1, SGL_SPLIT_BF16 = 2 } sgl_dtype_t;
+
+/* plan flags */
+#define SGL_SAMPLES_RAW 1u /* raw f instead of sigma_i f (SGL_F64 only) */
+
+#define SGL_MAX_B 256 /* largest supported bandlimit */
+
+/* Create a plan for `batch` functions of bandlimit B (1 <= B <= SGL_MAX_B,
+ * batch >= 1) in precision `dtype` (an sgl_dtype_t).  Builds, on the current
+ * HIP device, the FP64 grid (Thm. 3.1, Thm. 3.3), the basis tables (Eq.
+ * legendre_recurrence, Lemma 3.5) and the workspace; synchronizes before
+ * returning.  *out receives the plan (NULL on failure). */
+sgl_status_t sgl_plan(sgl_plan_t* out, int B, int batch, int dtype);
+
+/* Like sgl_plan for nfunc functions with their own bandlimits B_list[f]
+ * (host array).  Functions are packed back to back in the caller's buffers
+ * at the offsets reported by sgl_offsets.  Functions of equal bandlimit share
+ * tables; every stage runs as one persistent launch over a work list keyed by
+ * (order, bandlimit).  flags: 0 or SGL_SAMPLES_RAW. */
+sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtype, unsigned flags);
+
+/* Forward transform (Alg. 3) of every function of the plan.
+ * d_samples: device, const, total_samples complex values (complex128 for
+ *            SGL_F64, complex64 otherwise), psi order per function.
+ * d_coeffs:  device, written, total_coeffs complex values, omega order.
+ * stream:    hipStream_t (NULL = default stream). */
+sgl_status_t sgl_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs, void* stream);
+
+/* Inverse transform (Alg. 4): d_coeffs (const) -> d_samples (written). */
+sgl_status_t sgl_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
+
+/* Free everything the plan owns (NULL is accepted). */
+sgl_status_t sgl_plan_destroy(sgl_plan_t plan);
+
+/* Sizes and index map (Sect. 3.4).  Return -1 for out-of-range arguments. */
+int64_t sgl_num_samples(int B);             /* 8 B^3 */
+int64_t sgl_num_coeffs(int B);              /* B(B+1)(2B+1)/6 */
+int64_t sgl_coeff_index(int n, int l, int m); /* omega(n,l,m), needs |m| <= l < n */
+
+/* Plan totals: complex values in the sample/coefficient buffers and the number
+ * of functions.  Any pointer may be NULL. */
+sgl_status_t sgl_plan_info(sgl_plan_t plan, int64_t* total_samples, int64_t* total_coeffs, int* nfunc);
+
+/* Host arrays of nfunc entries: complex-value offsets of each function in the
+ * sample and coefficient buffers (either may be NULL). */
+sgl_status_t sgl_offsets(sgl_plan_t plan, int64_t* sample_off, int64_t* coeff_off);
+
+/* Copy the plan's FP64 grid for bandlimit B (which the plan must contain)
+ * into host arrays (any may be NULL): r, ln a, ln sigma (length 2B) from the
+ * radial rule of order 2B; theta, b~ (length 2B). */
+sgl_status_t sgl_grid(sgl_plan_t plan, int B, double* r, double* log_a, double* log_sigma,
+                      double* theta, double* btilde);
+
+/* Copy one FP64 basis table for bandlimit B into a host array of B^2 (B+1)
+ * doubles.  which = 0: Legendre table, for m = 0..B-1 the (B-m) x 2B block
+ * Pbar_lm(cos th_j), rows l = m..B-1, block offset 2B (m B - m(m-1)/2).
+ * which = 1: radial table, for l = 0..B-1 the (B-l) x 2B block
+ * rho_nl(r_i) = sigma_i N_nl R_nl(r_i), rows n = l+1..B, same offsets. */
+sgl_status_t sgl_table(sgl_plan_t plan, int B, int which, double* host_out);
+
+/* Per-stage kernel timing with HIP events recorded on the caller's stream.
+ * While enabled every forward/inverse call records events around its stage
+ * launches; sgl_stage_times accumulates them (synchronizing on the events)
+ * into ms[6] (forward a, b, c, inverse c, b, a) and counts[6], then resets. */
+sgl_status_t sgl_set_timing(sgl_plan_t plan, int enable);
+sgl_status_t sgl_stage_times(sgl_plan_t plan, double* ms, int* counts);
+
+/* Run the GEMM core of stages (b)/(c) once on device buffers, for tests:
+ * C[M x N] = A[M x K] * X[K x N], all FP64 row-major, in precision dtype
+ * (inputs rounded/split on the fly).  Synchronizes. */
+sgl_status_t sgl_debug_gemm(int dtype, int M, int N, int K, const double* d_A, const double* d_X, double* d_C);
+
+const char* sgl_status_string(sgl_status_t status);
+const char* sgl_last_error(void); /* message of the last failing call on this thread */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGL_H */

@@ -1,0 +1,103 @@
+// Internal definitions shared by the libsgl translation units (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sgl.h"
+
+namespace sgl {
+
+// ---------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define SGL_HIP_TRY(expr)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::sgl::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));         \
+      return e_ == hipErrorOutOfMemory ? SGL_ERR_OOM : SGL_ERR_HIP;                \
+    }                                                                              \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Sizes and table offsets
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int64_t num_coeffs(int B) { return (int64_t)B * (B + 1) * (2 * B + 1) / 6; }
+__host__ __device__ inline int64_t num_samples(int B) { return 8ll * B * B * B; }
+__host__ __device__ inline int64_t omega(int n, int l, int m) {
+  return (int64_t)n * (n - 1) * (2 * n - 1) / 6 + (int64_t)l * (l + 1) + m;
+}
+// Offset (in elements) of block q (order m for the Legendre table, degree l for
+// the radial table) in a table of blocks (B-q) x 2B, q = 0..B-1.
+__host__ __device__ inline int64_t table_block(int B, int q) {
+  return 2ll * B * ((int64_t)q * B - (int64_t)q * (q - 1) / 2);
+}
+__host__ __device__ inline int64_t table_size(int B) { return (int64_t)B * B * (B + 1); }
+
+// ---------------------------------------------------------------------------
+// Device-side description of one bandlimit class (all functions sharing B)
+// ---------------------------------------------------------------------------
+constexpr int kMaxRadices = 12;
+
+struct ClassDesc {
+  int B;            // bandlimit
+  int nf;           // functions in the class
+  int L;            // 2B, ring length
+  int nrad;         // FFT radix count
+  int rad[kMaxRadices];
+  const int64_t* soff;  // per-function sample offsets (complex values)
+  const int64_t* coff;  // per-function coefficient offsets (complex values)
+  const void* P;        // Legendre table in the plan precision (A operand of stage b)
+  const void* R;        // radial table in the plan precision (A operand of stage c)
+  const double* btilde; // b~_j, 2B
+  const double* sigma;  // sigma_i, 2B (raw-sample scaling)
+  const void* tw;       // twiddles exp(-2 pi i q / L), q < L (double2 or float2)
+  void* F;              // stage (a)/(b) workspace, [(2B-1)][2B][nf*2B] complex
+  void* g;              // stage (b)/(c) workspace, [l][b][m+l][2B] complex, block l at l^2 nf 2B
+};
+
+// Work items (int4): stage a {class, j, col block, 0}; stage b {class, m, row tile, col tile};
+// stage c {class, l, row tile, col tile}.
+
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_SPLIT = 2 };
+
+// Stage kernels (defined in sgl_fft.hip / sgl_gemm.hip)
+// stage (a) work items carry the rings per block in .w; lds_bytes = 2 * rpb * L * sizeof(complex)
+hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
+                              int lds_bytes, const void* samples, hipStream_t s);
+hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
+                              int lds_bytes, void* samples, hipStream_t s);
+size_t fft_lds_bytes_for(int prec, int rpb, int L);
+hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
+                           hipStream_t s);
+hipError_t launch_radial(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
+                         const void* coeffs_in, void* coeffs_out, hipStream_t s);
+hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, const double* X, double* C,
+                             hipStream_t s);
+int gemm_tile_m();
+int gemm_tile_n_complex();
+
+// Plan-time FP64 kernels (sgl_tables.hip)
+struct GridBuild {
+  int B;
+  double* r;      // 2B
+  double* log_a;  // 2B
+  double* log_sig;
+  double* sig;
+  double* theta;
+  double* btilde;
+};
+sgl_status_t build_grid(GridBuild& g, hipStream_t s);
+hipError_t build_tables(int B, const double* r, const double* log_sig, const double* theta, double* P64,
+                        double* R64, hipStream_t s);
+hipError_t build_twiddles(int L, void* tw, bool f32, hipStream_t s);
+hipError_t convert_table_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t convert_table_split(const double* src, uint16_t* dst, int64_t n, hipStream_t s);
+
+}  // namespace sgl

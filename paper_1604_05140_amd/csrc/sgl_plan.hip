@@ -1,0 +1,484 @@
+// Host side of libsgl: argument checks, plan construction (FP64 grid and
+// tables on the GPU, workspace, work lists) and the stream-ordered forward /
+// inverse entry points.  See include/sgl.h for the contract.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "sgl_internal.h"
+
+namespace sgl {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+struct ClassHost {
+  int B = 0;
+  std::vector<int> funcs;
+  double* grid = nullptr;  // r, log_a, log_sig, sig, theta, btilde (6 x 2B)
+  double* P64 = nullptr;
+  double* R64 = nullptr;
+  void* P = nullptr;
+  void* R = nullptr;
+  void* tw = nullptr;
+  void* F = nullptr;
+  void* g = nullptr;
+  int64_t* soff = nullptr;
+  int64_t* coff = nullptr;
+  int rpb = 1;
+  std::vector<int> radices;
+};
+
+std::vector<int> fft_radices(int L) {
+  std::vector<int> out;
+  while (L % 4 == 0) { out.push_back(4); L /= 4; }
+  for (int p : {2, 3, 5, 7}) {
+    while (L % p == 0) { out.push_back(p); L /= p; }
+  }
+  for (int q = 11; L > 1; q += 2) {
+    while (L % q == 0) { out.push_back(q); L /= q; }
+  }
+  return out;
+}
+
+}  // namespace
+}  // namespace sgl
+
+using namespace sgl;
+
+struct sgl_plan_s {
+  int dtype = 0;
+  unsigned flags = 0;
+  std::vector<int> Bs;
+  std::vector<int64_t> soff, coff;
+  int64_t tot_s = 0, tot_c = 0;
+  std::vector<ClassHost> classes;
+  std::vector<void*> allocs;
+  ClassDesc* d_cls = nullptr;
+  int4* d_work = nullptr;
+  int off_a = 0, n_a = 0, off_bf = 0, n_bf = 0, off_bi = 0, n_bi = 0, off_cf = 0, n_cf = 0, off_ci = 0, n_ci = 0;
+  int lds_a = 0;
+  // timing
+  bool timing = false;
+  static constexpr int kRing = 64;
+  std::vector<hipEvent_t> ev;  // [stage][slot][start/stop]
+  int head[6] = {0, 0, 0, 0, 0, 0};
+  int pending[6] = {0, 0, 0, 0, 0, 0};
+  double ms[6] = {0, 0, 0, 0, 0, 0};
+  int cnt[6] = {0, 0, 0, 0, 0, 0};
+
+  ~sgl_plan_s() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (void* q : allocs) (void)hipFree(q);
+  }
+
+  sgl_status_t alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? SGL_ERR_OOM : SGL_ERR_HIP;
+    }
+    allocs.push_back(*p);
+    return SGL_OK;
+  }
+  size_t esz() const { return dtype == SGL_F64 ? 16 : 8; }
+};
+
+namespace {
+
+#define SGL_TRY(x)                  \
+  do {                              \
+    sgl_status_t st_ = (x);         \
+    if (st_ != SGL_OK) return st_;  \
+  } while (0)
+
+sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
+  const int B = c.B, L = 2 * B, nf = (int)c.funcs.size();
+  const int64_t ts = table_size(B);
+  SGL_TRY(p->alloc((void**)&c.grid, 6 * (size_t)L * sizeof(double)));
+  GridBuild gb{B, c.grid, c.grid + L, c.grid + 2 * L, c.grid + 3 * L, c.grid + 4 * L, c.grid + 5 * L};
+  SGL_TRY(build_grid(gb, s));
+  SGL_TRY(p->alloc((void**)&c.P64, ts * sizeof(double)));
+  SGL_TRY(p->alloc((void**)&c.R64, ts * sizeof(double)));
+  SGL_HIP_TRY(build_tables(B, gb.r, gb.log_sig, gb.theta, c.P64, c.R64, s));
+  if (p->dtype == SGL_F64) {
+    c.P = c.P64;
+    c.R = c.R64;
+  } else if (p->dtype == SGL_F32) {
+    SGL_TRY(p->alloc(&c.P, ts * sizeof(float)));
+    SGL_TRY(p->alloc(&c.R, ts * sizeof(float)));
+    SGL_HIP_TRY(convert_table_f32(c.P64, (float*)c.P, ts, s));
+    SGL_HIP_TRY(convert_table_f32(c.R64, (float*)c.R, ts, s));
+  } else {
+    SGL_TRY(p->alloc(&c.P, 3 * ts * sizeof(uint16_t)));
+    SGL_TRY(p->alloc(&c.R, 3 * ts * sizeof(uint16_t)));
+    SGL_HIP_TRY(convert_table_split(c.P64, (uint16_t*)c.P, ts, s));
+    SGL_HIP_TRY(convert_table_split(c.R64, (uint16_t*)c.R, ts, s));
+  }
+  const bool f32 = p->dtype != SGL_F64;
+  SGL_TRY(p->alloc(&c.tw, (size_t)L * (f32 ? sizeof(float2) : sizeof(double2))));
+  SGL_HIP_TRY(build_twiddles(L, c.tw, f32, s));
+  c.radices = fft_radices(L);
+  if ((int)c.radices.size() > kMaxRadices) {
+    set_error("FFT length has too many factors");
+    return SGL_ERR_UNSUPPORTED;
+  }
+  const size_t es = p->esz();
+  SGL_TRY(p->alloc(&c.F, (size_t)(2 * B - 1) * L * nf * L * es));
+  SGL_TRY(p->alloc(&c.g, (size_t)B * B * nf * L * es));
+  std::vector<int64_t> so(nf), co(nf);
+  for (int q = 0; q < nf; ++q) {
+    so[q] = p->soff[c.funcs[q]];
+    co[q] = p->coff[c.funcs[q]];
+  }
+  SGL_TRY(p->alloc((void**)&c.soff, nf * sizeof(int64_t)));
+  SGL_TRY(p->alloc((void**)&c.coff, nf * sizeof(int64_t)));
+  SGL_HIP_TRY(hipMemcpyAsync(c.soff, so.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  SGL_HIP_TRY(hipMemcpyAsync(c.coff, co.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  // rings per FFT block: 64 KB of LDS for the ping-pong buffers
+  const int cap = (int)(65536 / (2 * (size_t)L * es));
+  c.rpb = std::max(1, std::min(64, std::min(cap, nf * L)));
+  return SGL_OK;
+}
+
+sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
+  const int BM = gemm_tile_m(), BNC = gemm_tile_n_complex();
+  std::vector<int4> wa, wbf, wbi, wcf, wci;
+  struct Item { int cost; int4 w; };
+  std::vector<Item> bf, bi, cf, ci;
+  int lds = 0;
+  for (int ci_ = 0; ci_ < (int)p->classes.size(); ++ci_) {
+    const ClassHost& c = p->classes[ci_];
+    const int B = c.B, L = 2 * B, nf = (int)c.funcs.size();
+    const int ncol = nf * L;
+    const int ncb = (ncol + c.rpb - 1) / c.rpb;
+    for (int j = 0; j < L; ++j)
+      for (int cb = 0; cb < ncb; ++cb) wa.push_back(make_int4(ci_, j, cb, c.rpb));
+    lds = std::max(lds, (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
+    for (int m = 0; m < B; ++m) {
+      const int rows = B - m;
+      const int ncc = (m ? 2 : 1) * nf * L;
+      const int nt = (ncc + BNC - 1) / BNC;
+      for (int mt = 0; mt < (rows + BM - 1) / BM; ++mt)
+        for (int t = 0; t < nt; ++t) bf.push_back({L, make_int4(ci_, m, mt, t)});
+      for (int mt = 0; mt < (L + BM - 1) / BM; ++mt)
+        for (int t = 0; t < nt; ++t) bi.push_back({rows, make_int4(ci_, m, mt, t)});
+    }
+    for (int l = 0; l < B; ++l) {
+      const int rows = B - l;
+      const int ncc = (2 * l + 1) * nf;
+      const int nt = (ncc + BNC - 1) / BNC;
+      for (int mt = 0; mt < (rows + BM - 1) / BM; ++mt)
+        for (int t = 0; t < nt; ++t) cf.push_back({L, make_int4(ci_, l, mt, t)});
+      for (int mt = 0; mt < (L + BM - 1) / BM; ++mt)
+        for (int t = 0; t < nt; ++t) ci.push_back({rows, make_int4(ci_, l, mt, t)});
+    }
+  }
+  // longest contraction first (persistent blocks then balance like LPT)
+  auto order = [](std::vector<Item>& v, std::vector<int4>& out) {
+    std::stable_sort(v.begin(), v.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    out.clear();
+    for (auto& it : v) out.push_back(it.w);
+  };
+  order(bf, wbf);
+  order(bi, wbi);
+  order(cf, wcf);
+  order(ci, wci);
+  std::vector<int4> all;
+  p->off_a = 0; p->n_a = (int)wa.size(); all.insert(all.end(), wa.begin(), wa.end());
+  p->off_bf = (int)all.size(); p->n_bf = (int)wbf.size(); all.insert(all.end(), wbf.begin(), wbf.end());
+  p->off_bi = (int)all.size(); p->n_bi = (int)wbi.size(); all.insert(all.end(), wbi.begin(), wbi.end());
+  p->off_cf = (int)all.size(); p->n_cf = (int)wcf.size(); all.insert(all.end(), wcf.begin(), wcf.end());
+  p->off_ci = (int)all.size(); p->n_ci = (int)wci.size(); all.insert(all.end(), wci.begin(), wci.end());
+  SGL_TRY(p->alloc((void**)&p->d_work, all.size() * sizeof(int4)));
+  SGL_HIP_TRY(hipMemcpyAsync(p->d_work, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  p->lds_a = lds;
+  return SGL_OK;
+}
+
+sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
+  std::map<int, std::vector<int>> byB;
+  for (int f = 0; f < (int)p->Bs.size(); ++f) byB[p->Bs[f]].push_back(f);
+  // largest bandlimit first
+  for (auto it = byB.rbegin(); it != byB.rend(); ++it) {
+    ClassHost c;
+    c.B = it->first;
+    c.funcs = it->second;
+    p->classes.push_back(c);
+  }
+  for (auto& c : p->classes) SGL_TRY(build_class(p, c, s));
+  std::vector<ClassDesc> descs;
+  for (auto& c : p->classes) {
+    ClassDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.B = c.B;
+    d.nf = (int)c.funcs.size();
+    d.L = 2 * c.B;
+    d.nrad = (int)c.radices.size();
+    for (int q = 0; q < d.nrad; ++q) d.rad[q] = c.radices[q];
+    d.soff = c.soff;
+    d.coff = c.coff;
+    d.P = c.P;
+    d.R = c.R;
+    d.btilde = c.grid + 5 * d.L;
+    d.sigma = c.grid + 3 * d.L;
+    d.tw = c.tw;
+    d.F = c.F;
+    d.g = c.g;
+    descs.push_back(d);
+  }
+  SGL_TRY(p->alloc((void**)&p->d_cls, descs.size() * sizeof(ClassDesc)));
+  SGL_HIP_TRY(hipMemcpyAsync(p->d_cls, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice, s));
+  SGL_TRY(build_work(p, s));
+  SGL_HIP_TRY(hipStreamSynchronize(s));
+  return SGL_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
+int prec_of(int dtype) { return dtype == SGL_F64 ? PREC_F64 : (dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT); }
+
+void time_begin(sgl_plan_s* p, int stage, hipStream_t s) {
+  if (!p->timing) return;
+  if (p->pending[stage] == sgl_plan_s::kRing) {
+    // fold the oldest pair
+    int slot = (p->head[stage] - p->pending[stage] + sgl_plan_s::kRing) % sgl_plan_s::kRing;
+    hipEvent_t a = p->ev[(stage * sgl_plan_s::kRing + slot) * 2], b = p->ev[(stage * sgl_plan_s::kRing + slot) * 2 + 1];
+    float ms = 0;
+    if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+      p->ms[stage] += ms;
+      p->cnt[stage] += 1;
+    }
+    p->pending[stage] -= 1;
+  }
+  (void)hipEventRecord(p->ev[(stage * sgl_plan_s::kRing + p->head[stage]) * 2], s);
+}
+void time_end(sgl_plan_s* p, int stage, hipStream_t s) {
+  if (!p->timing) return;
+  (void)hipEventRecord(p->ev[(stage * sgl_plan_s::kRing + p->head[stage]) * 2 + 1], s);
+  p->head[stage] = (p->head[stage] + 1) % sgl_plan_s::kRing;
+  p->pending[stage] += 1;
+}
+
+sgl_status_t check_call(sgl_plan_t plan, const void* in, size_t nin, const void* out, size_t nout) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  if (!in || !out) { set_error("null data pointer"); return SGL_ERR_INVALID_ARG; }
+  if (overlap(in, nin, out, nout)) { set_error("input and output overlap"); return SGL_ERR_INVALID_ARG; }
+  return SGL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sgl_status_string(sgl_status_t st) {
+  switch (st) {
+    case SGL_OK: return "SGL_OK";
+    case SGL_ERR_INVALID_ARG: return "SGL_ERR_INVALID_ARG";
+    case SGL_ERR_UNSUPPORTED: return "SGL_ERR_UNSUPPORTED";
+    case SGL_ERR_HIP: return "SGL_ERR_HIP";
+    case SGL_ERR_OOM: return "SGL_ERR_OOM";
+    case SGL_ERR_NUMERIC: return "SGL_ERR_NUMERIC";
+  }
+  return "SGL_ERR_UNKNOWN";
+}
+
+const char* sgl_last_error(void) { return g_last_error.c_str(); }
+
+int64_t sgl_num_samples(int B) { return (B < 1 || B > SGL_MAX_B) ? -1 : num_samples(B); }
+int64_t sgl_num_coeffs(int B) { return (B < 1 || B > SGL_MAX_B) ? -1 : num_coeffs(B); }
+int64_t sgl_coeff_index(int n, int l, int m) {
+  if (n < 1 || l < 0 || l >= n || m < -l || m > l) return -1;
+  return omega(n, l, m);
+}
+
+sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtype, unsigned flags) {
+  if (!out) { set_error("null output pointer"); return SGL_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (!B_list || nfunc < 1) { set_error("need at least one function"); return SGL_ERR_INVALID_ARG; }
+  if (dtype != SGL_F64 && dtype != SGL_F32 && dtype != SGL_SPLIT_BF16) {
+    set_error("unknown dtype");
+    return SGL_ERR_INVALID_ARG;
+  }
+  if (flags & ~SGL_SAMPLES_RAW) { set_error("unknown flag"); return SGL_ERR_INVALID_ARG; }
+  if ((flags & SGL_SAMPLES_RAW) && dtype != SGL_F64) {
+    set_error("raw samples need SGL_F64 (they leave the FP32 range for B > ~40)");
+    return SGL_ERR_UNSUPPORTED;
+  }
+  for (int f = 0; f < nfunc; ++f) {
+    if (B_list[f] < 1 || B_list[f] > SGL_MAX_B) {
+      set_error("bandlimit out of range [1, " + std::to_string(SGL_MAX_B) + "]");
+      return SGL_ERR_INVALID_ARG;
+    }
+  }
+  std::unique_ptr<sgl_plan_s> p(new (std::nothrow) sgl_plan_s());
+  if (!p) { set_error("host allocation failed"); return SGL_ERR_OOM; }
+  p->dtype = dtype;
+  p->flags = flags;
+  p->Bs.assign(B_list, B_list + nfunc);
+  for (int f = 0; f < nfunc; ++f) {
+    p->soff.push_back(p->tot_s);
+    p->coff.push_back(p->tot_c);
+    p->tot_s += num_samples(B_list[f]);
+    p->tot_c += num_coeffs(B_list[f]);
+  }
+  hipStream_t s = nullptr;
+  sgl_status_t st = make_plan(p.get(), s);
+  if (st != SGL_OK) return st;  // unique_ptr frees everything allocated so far
+  *out = p.release();
+  return SGL_OK;
+}
+
+sgl_status_t sgl_plan(sgl_plan_t* out, int B, int batch, int dtype) {
+  if (!out) { set_error("null output pointer"); return SGL_ERR_INVALID_ARG; }
+  *out = nullptr;
+  if (batch < 1) { set_error("batch must be >= 1"); return SGL_ERR_INVALID_ARG; }
+  if (B < 1 || B > SGL_MAX_B) {
+    set_error("bandlimit out of range [1, " + std::to_string(SGL_MAX_B) + "]");
+    return SGL_ERR_INVALID_ARG;
+  }
+  std::vector<int> Bs(batch, B);
+  return sgl_plan_ex(out, Bs.data(), batch, dtype, 0u);
+}
+
+sgl_status_t sgl_plan_destroy(sgl_plan_t plan) {
+  delete plan;
+  return SGL_OK;
+}
+
+sgl_status_t sgl_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  SGL_TRY(check_call(plan, d_samples, plan->tot_s * plan->esz(), d_coeffs, plan->tot_c * plan->esz()));
+  hipStream_t s = (hipStream_t)stream;
+  const int prec = prec_of(plan->dtype);
+  const bool raw = (plan->flags & SGL_SAMPLES_RAW) != 0;
+  time_begin(plan, 0, s);
+  SGL_HIP_TRY(launch_fft_forward(prec, raw, plan->d_cls, plan->d_work + plan->off_a, plan->n_a, plan->lds_a,
+                                 d_samples, s));
+  time_end(plan, 0, s);
+  time_begin(plan, 1, s);
+  SGL_HIP_TRY(launch_legendre(prec, false, plan->d_cls, plan->d_work + plan->off_bf, plan->n_bf, s));
+  time_end(plan, 1, s);
+  time_begin(plan, 2, s);
+  SGL_HIP_TRY(launch_radial(prec, false, plan->d_cls, plan->d_work + plan->off_cf, plan->n_cf, nullptr, d_coeffs, s));
+  time_end(plan, 2, s);
+  return SGL_OK;
+}
+
+sgl_status_t sgl_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  SGL_TRY(check_call(plan, d_coeffs, plan->tot_c * plan->esz(), d_samples, plan->tot_s * plan->esz()));
+  hipStream_t s = (hipStream_t)stream;
+  const int prec = prec_of(plan->dtype);
+  const bool raw = (plan->flags & SGL_SAMPLES_RAW) != 0;
+  time_begin(plan, 3, s);
+  SGL_HIP_TRY(launch_radial(prec, true, plan->d_cls, plan->d_work + plan->off_ci, plan->n_ci, d_coeffs, nullptr, s));
+  time_end(plan, 3, s);
+  time_begin(plan, 4, s);
+  SGL_HIP_TRY(launch_legendre(prec, true, plan->d_cls, plan->d_work + plan->off_bi, plan->n_bi, s));
+  time_end(plan, 4, s);
+  time_begin(plan, 5, s);
+  SGL_HIP_TRY(launch_fft_inverse(prec, raw, plan->d_cls, plan->d_work + plan->off_a, plan->n_a, plan->lds_a,
+                                 d_samples, s));
+  time_end(plan, 5, s);
+  return SGL_OK;
+}
+
+sgl_status_t sgl_plan_info(sgl_plan_t plan, int64_t* total_samples, int64_t* total_coeffs, int* nfunc) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  if (total_samples) *total_samples = plan->tot_s;
+  if (total_coeffs) *total_coeffs = plan->tot_c;
+  if (nfunc) *nfunc = (int)plan->Bs.size();
+  return SGL_OK;
+}
+
+sgl_status_t sgl_offsets(sgl_plan_t plan, int64_t* sample_off, int64_t* coeff_off) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  if (sample_off) std::copy(plan->soff.begin(), plan->soff.end(), sample_off);
+  if (coeff_off) std::copy(plan->coff.begin(), plan->coff.end(), coeff_off);
+  return SGL_OK;
+}
+
+static const ClassHost* find_class(sgl_plan_t plan, int B) {
+  for (auto& c : plan->classes)
+    if (c.B == B) return &c;
+  return nullptr;
+}
+
+sgl_status_t sgl_grid(sgl_plan_t plan, int B, double* r, double* log_a, double* log_sigma, double* theta,
+                      double* btilde) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  const ClassHost* c = find_class(plan, B);
+  if (!c) { set_error("bandlimit not in plan"); return SGL_ERR_INVALID_ARG; }
+  const int L = 2 * B;
+  double* dst[6] = {r, log_a, log_sigma, nullptr, theta, btilde};
+  for (int q = 0; q < 6; ++q)
+    if (dst[q]) SGL_HIP_TRY(hipMemcpy(dst[q], c->grid + q * L, L * sizeof(double), hipMemcpyDeviceToHost));
+  return SGL_OK;
+}
+
+sgl_status_t sgl_table(sgl_plan_t plan, int B, int which, double* host_out) {
+  if (!plan || !host_out || (which != 0 && which != 1)) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
+  const ClassHost* c = find_class(plan, B);
+  if (!c) { set_error("bandlimit not in plan"); return SGL_ERR_INVALID_ARG; }
+  SGL_HIP_TRY(hipMemcpy(host_out, which == 0 ? c->P64 : c->R64, table_size(B) * sizeof(double),
+                        hipMemcpyDeviceToHost));
+  return SGL_OK;
+}
+
+sgl_status_t sgl_set_timing(sgl_plan_t plan, int enable) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  if (enable && plan->ev.empty()) {
+    plan->ev.resize(6 * sgl_plan_s::kRing * 2);
+    for (auto& e : plan->ev) SGL_HIP_TRY(hipEventCreate(&e));
+  }
+  plan->timing = enable != 0;
+  return SGL_OK;
+}
+
+sgl_status_t sgl_stage_times(sgl_plan_t plan, double* ms, int* counts) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  for (int st = 0; st < 6; ++st) {
+    while (plan->pending[st] > 0) {
+      int slot = (plan->head[st] - plan->pending[st] + sgl_plan_s::kRing) % sgl_plan_s::kRing;
+      hipEvent_t a = plan->ev[(st * sgl_plan_s::kRing + slot) * 2];
+      hipEvent_t b = plan->ev[(st * sgl_plan_s::kRing + slot) * 2 + 1];
+      float t = 0;
+      SGL_HIP_TRY(hipEventSynchronize(b));
+      SGL_HIP_TRY(hipEventElapsedTime(&t, a, b));
+      plan->ms[st] += t;
+      plan->cnt[st] += 1;
+      plan->pending[st] -= 1;
+    }
+    if (ms) ms[st] = plan->ms[st];
+    if (counts) counts[st] = plan->cnt[st];
+    plan->ms[st] = 0;
+    plan->cnt[st] = 0;
+  }
+  return SGL_OK;
+}
+
+sgl_status_t sgl_debug_gemm(int dtype, int M, int N, int K, const double* d_A, const double* d_X, double* d_C) {
+  if (M < 0 || N < 0 || K < 0 || !d_A || !d_X || !d_C) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
+  if (dtype != SGL_F64 && dtype != SGL_F32 && dtype != SGL_SPLIT_BF16) {
+    set_error("unknown dtype");
+    return SGL_ERR_INVALID_ARG;
+  }
+  SGL_HIP_TRY(launch_debug_gemm(prec_of(dtype), M, N, K, d_A, d_X, d_C, nullptr));
+  SGL_HIP_TRY(hipDeviceSynchronize());
+  return SGL_OK;
+}
+
+}  // extern "C"

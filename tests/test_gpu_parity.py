@@ -1,0 +1,247 @@
+"""GPU parity: libsgl (HIP, through the C ABI) against the CPU oracle.
+
+Error metric (reading of Sect. 4's relative error): e_inf =
+max|delta| / max|reference| per function.  Bars: FP64 1e-12 against the
+oracle; FP32 1e-5 and split-bf16 1e-6 against the plain FP64 GPU path on the
+same inputs (which is itself held to 1e-12 against the oracle).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import basis as BS, direct as D, quadrature as Q  # noqa: E402
+from paper_1604_05140_amd import sgl, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SEED = synth.BASE_SEED
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(x, ct):
+    return torch.from_numpy(np.ascontiguousarray(x).reshape(-1)).to(DEV, ct)
+
+
+def gpu_forward(plan, samples):
+    out = torch.empty(plan.total_coeffs, dtype=plan.complex_dtype, device=DEV)
+    s = samples if isinstance(samples, torch.Tensor) else dev(samples, plan.complex_dtype)
+    sgl.sgl_forward(plan, s, out)
+    torch.cuda.synchronize()
+    return out
+
+
+def gpu_inverse(plan, coeffs):
+    out = torch.empty(plan.total_samples, dtype=plan.complex_dtype, device=DEV)
+    c = coeffs if isinstance(coeffs, torch.Tensor) else dev(coeffs, plan.complex_dtype)
+    sgl.sgl_inverse(plan, c, out)
+    torch.cuda.synchronize()
+    return out
+
+
+def einf(ref, got):
+    return D.error_metrics(np.asarray(ref), np.asarray(got))["e_inf"]
+
+
+# ---------------------------------------------------------------------------
+# GEMM core (MFMA lane layouts, ragged tiles, the three precisions)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-14), ("f32", 2e-6), ("split_bf16", 2e-6)])
+@pytest.mark.parametrize("M,K,N", [(70, 45, 100), (64, 256, 128), (1, 1, 2), (130, 33, 17)])
+def test_gemm_core(dtype, tol, M, K, N):
+    g = np.random.default_rng(M * 1000 + K + N)
+    A = g.standard_normal((M, K))
+    X = g.standard_normal((K, N))
+    ref = A @ X
+    Ag, Xg = torch.from_numpy(A).to(DEV), torch.from_numpy(X).to(DEV)
+    Cg = torch.full((M, N), float("nan"), dtype=torch.float64, device=DEV)
+    sgl.sgl_debug_gemm(dtype, Ag, Xg, Cg)
+    C = Cg.cpu().numpy()
+    scale = np.abs(A).max() * np.abs(X).max() * math.sqrt(K)
+    assert np.isfinite(C).all()
+    assert np.abs(C - ref).max() <= tol * scale
+
+
+# ---------------------------------------------------------------------------
+# Plan-time FP64 grid and tables
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("B", [1, 2, 8, 17, 64, 128, 256])
+def test_grid_matches_oracle(B):
+    plan = sgl.sgl_plan(B, 1, "f64")
+    g = plan.grid(B)
+    o = Q.sgl_grid(B)
+    rel_r = np.abs(g["r"] / o["r"] - 1).max()
+    assert rel_r < 1e-13, rel_r
+    assert np.abs(g["log_a"] - o["log_a"]).max() < 1e-11 * max(1.0, np.abs(o["log_a"]).max() / 100)
+    assert np.abs(g["log_sigma"] - o["log_sigma"]).max() < 1e-11 * max(1.0, np.abs(o["log_sigma"]).max() / 100)
+    assert np.abs(g["theta"] - o["theta"]).max() < 1e-15
+    assert np.abs(g["btilde"] / o["btilde"] - 1).max() < 1e-13
+    plan.destroy()
+
+
+def _oracle_tables(B):
+    g = Q.sgl_grid(B)
+    P = BS.legendre_table(B, g["theta"])
+    R = BS.radial_table(B, g["r"], g["log_sigma"])
+    Pt, Rt = [], []
+    for m in range(B):
+        Pt.append(P[m, m:B].reshape(-1))
+    for l in range(B):
+        Rt.append(R[l + 1:B + 1, l].reshape(-1))
+    return np.concatenate(Pt), np.concatenate(Rt)
+
+
+@pytest.mark.parametrize("B", [1, 3, 8, 64, 128])
+def test_tables_match_oracle(B):
+    plan = sgl.sgl_plan(B, 1, "f64")
+    Pg, Rg = plan.table(B, 0), plan.table(B, 1)
+    Po, Ro = _oracle_tables(B)
+    assert np.abs(Pg - Po).max() < 2e-13
+    assert np.abs(Rg - Ro).max() < 2e-13
+    plan.destroy()
+
+
+# ---------------------------------------------------------------------------
+# FP64 transforms against the oracle
+# ---------------------------------------------------------------------------
+def test_fp64_config1_b8_recovers_coefficients():
+    """B = 8, one function, CN(0,1) coefficients: oracle synthesis -> GPU forward
+    recovers them; GPU inverse reproduces the oracle's samples."""
+    B = 8
+    c = synth.complex_normal_coeffs(B, 1, seed=SEED + 1)[0]
+    s = D.inverse(c, B)
+    plan = sgl.sgl_plan(B, 1, "f64")
+    cg = gpu_forward(plan, s).cpu().numpy()
+    sg = gpu_inverse(plan, c).cpu().numpy()
+    assert einf(c, cg) <= 1e-12
+    assert einf(s, sg) <= 1e-12
+    assert einf(D.forward(s, B), cg) <= 1e-12
+
+
+@pytest.mark.parametrize("B,batch", [(1, 1), (2, 3), (3, 2), (5, 2), (6, 1), (12, 2)])
+def test_fp64_arbitrary_samples_and_coefficients(B, batch):
+    """The forward map is the quadrature sum for any samples (not only bandlimited
+    ones); the inverse is the synthesis sum for any coefficients."""
+    s = synth.complex_normal_samples(B, batch, seed=SEED + 10 + B)
+    c = synth.complex_normal_coeffs(B, batch, seed=SEED + 20 + B)
+    plan = sgl.sgl_plan(B, batch, "f64")
+    cg = gpu_forward(plan, s).cpu().numpy().reshape(batch, -1)
+    sg = gpu_inverse(plan, c).cpu().numpy().reshape(batch, -1)
+    for b in range(batch):
+        assert einf(D.forward(s[b], B), cg[b]) <= 1e-12, b
+        assert einf(D.inverse(c[b], B), sg[b]) <= 1e-12, b
+
+
+def test_fp64_raw_samples():
+    B = 7
+    c = synth.complex_normal_coeffs(B, 1, seed=SEED + 30)[0]
+    f = D.inverse(c, B, raw=True)
+    plan = sgl.sgl_plan_ex([B], "f64", sgl.SGL_SAMPLES_RAW)
+    cg = gpu_forward(plan, f).cpu().numpy()
+    fg = gpu_inverse(plan, c).cpu().numpy()
+    assert einf(c, cg) <= 1e-12
+    assert einf(f, fg) <= 1e-12
+
+
+def test_fp64_config2_b64_subsets_and_round_trip():
+    """B = 64, batch 1, CN(0,1)/n: GPU inverse at 200 seeded grid points against
+    the oracle's synthesis sum; GPU forward at 200 seeded coefficients against the
+    oracle's quadrature sum on the same samples; round trip."""
+    B = 64
+    c = synth.complex_normal_coeffs(B, 1, seed=SEED + 2, decay=1.0)[0]
+    plan = sgl.sgl_plan(B, 1, "f64")
+    s_gpu = gpu_inverse(plan, c)
+    s = s_gpu.cpu().numpy()
+    pts = synth.grid_points(200, B, seed=SEED + 1002)
+    s_or = D.inverse(c, B, points=pts)
+    s_at = s.reshape(2 * B, 2 * B, 2 * B)[pts[:, 0], pts[:, 1], pts[:, 2]]
+    assert np.abs(s_at - s_or).max() <= 1e-12 * np.abs(s).max()
+    c2 = gpu_forward(plan, s_gpu).cpu().numpy()
+    assert einf(c, c2) <= 1e-12
+    oms = synth.subset(200, D.num_coeffs(B), seed=SEED + 1003)
+    f_or = D.forward(s, B, omegas=oms)
+    assert np.abs(c2[oms] - f_or).max() <= 1e-12 * np.abs(c).max()
+
+
+def test_batched_uneven_bandlimits_fp64():
+    Bs = [3, 5, 3, 8, 1, 5]
+    plan = sgl.sgl_plan_ex(Bs, "f64")
+    so, co = plan.offsets()
+    cs = [synth.complex_normal_coeffs(B, 1, seed=SEED + 40 + q)[0] for q, B in enumerate(Bs)]
+    ss = [synth.complex_normal_samples(B, 1, seed=SEED + 50 + q)[0] for q, B in enumerate(Bs)]
+    cg = gpu_forward(plan, np.concatenate(ss)).cpu().numpy()
+    sg = gpu_inverse(plan, np.concatenate(cs)).cpu().numpy()
+    for q, B in enumerate(Bs):
+        assert einf(D.forward(ss[q], B), cg[co[q]:co[q] + D.num_coeffs(B)]) <= 1e-12
+        assert einf(D.inverse(cs[q], B), sg[so[q]:so[q] + D.num_samples(B)]) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Precision forms against the plain FP64 GPU path
+# ---------------------------------------------------------------------------
+def einf_dev(ref, got):
+    """e_inf on the device (large cases), in float64."""
+    ref = ref.to(torch.complex128)
+    got = got.to(torch.complex128)
+    return float((got - ref).abs().max() / ref.abs().max())
+
+
+def _precision_case(B, batch, decay, seed, dtypes=(("f32", 1e-5), ("split_bf16", 1e-6)), host_fn=0):
+    c = synth.complex_normal_coeffs(B, batch, seed=seed, decay=decay)
+    c_dev = dev(c, torch.complex128)
+    p64 = sgl.sgl_plan(B, batch, "f64")
+    s64 = gpu_inverse(p64, c_dev)
+    c64 = gpu_forward(p64, s64)
+    ns, nc = D.num_samples(B), D.num_coeffs(B)
+    for b in range(batch):
+        assert einf_dev(c_dev[b * nc:(b + 1) * nc], c64[b * nc:(b + 1) * nc]) <= 1e-12
+    res = {}
+    s32 = s64.to(torch.complex64)
+    c32 = c_dev.to(torch.complex64)
+    for dtype, tol in dtypes:
+        p = sgl.sgl_plan(B, batch, dtype)
+        cf = gpu_forward(p, s32)
+        sf = gpu_inverse(p, c32)
+        ef = max(einf_dev(c64[b * nc:(b + 1) * nc], cf[b * nc:(b + 1) * nc]) for b in range(batch))
+        ei = max(einf_dev(s64[b * ns:(b + 1) * ns], sf[b * ns:(b + 1) * ns]) for b in range(batch))
+        res[dtype] = (ef, ei)
+        print(f"B={B} batch={batch} {dtype}: forward e_inf {ef:.2e}, inverse e_inf {ei:.2e}", flush=True)
+        assert ef <= tol and ei <= tol, (dtype, ef, ei)
+        del cf, sf
+        p.destroy()
+    s_host = s64[host_fn * ns:(host_fn + 1) * ns].cpu().numpy()
+    del s64, c64, s32
+    p64.destroy()
+    torch.cuda.empty_cache()
+    return c, s_host, res
+
+
+def test_precision_forms_small_b():
+    _precision_case(12, 3, 1.0, SEED + 60)
+
+
+def test_precision_forms_config3_b128():
+    """B = 128, batch 4, CN(0,1)/n: FP32 MFMA (1e-5) and split-bf16 (1e-6) against
+    FP64; the FP64 samples checked against the oracle at 24 seeded coefficients."""
+    B, batch = 128, 4
+    c, s1, _ = _precision_case(B, batch, 1.0, SEED + 3, host_fn=1)
+    oms = synth.subset(24, D.num_coeffs(B), seed=SEED + 1004)
+    f_or = D.forward(s1, B, omegas=oms)
+    assert np.abs(c[1][oms] - f_or).max() <= 1e-12 * np.abs(c[1]).max()
+
+
+def test_precision_config5_b256_split():
+    """B = 256, batch 8, CN(0,1) n^-1.5: split-bf16 against FP64 (1e-6)."""
+    B, batch = 256, 8
+    c, s0, _ = _precision_case(B, batch, 1.5, SEED + 5, dtypes=(("split_bf16", 1e-6),), host_fn=0)
+    oms = synth.subset(6, D.num_coeffs(B), seed=SEED + 1005)
+    f_or = D.forward(s0, B, omegas=oms)
+    assert np.abs(c[0][oms] - f_or).max() <= 1e-12 * np.abs(c[0]).max()
