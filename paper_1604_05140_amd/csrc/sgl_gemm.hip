@@ -367,14 +367,16 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
       __syncthreads();
     }
 
-    // ---- epilogue: lane holds rows 4*(lane/16)+v, real column lane%16 of each 16x16 block
+    // ---- epilogue: each lane holds 4 rows of real column lane%16 of each 16x16 block:
+    // rows 4*(lane/16)+v for the f32 MFMAs, rows 4*v+lane/16 for the f64 MFMA.
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j) {
         const int nr = 2 * t.col0 + wc + j * 16 + lr;  // real column
         const int c = nr >> 1, part = nr & 1;
         if (c >= t.Ncc) continue;
         for (int v = 0; v < 4; ++v) {
-          const int row = t.row0 + wr + i * 16 + 4 * lk + v;
+          const int rin = PREC == PREC_F64 ? 4 * v + lk : 4 * lk + v;
+          const int row = t.row0 + wr + i * 16 + rin;
           if (row >= t.M) continue;
           T val;
           if constexpr (PREC == PREC_SPLIT)

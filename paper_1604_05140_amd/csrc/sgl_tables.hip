@@ -184,7 +184,13 @@ __global__ void k_radial_nodes(int N, const double* alpha, const double* beta, d
   }
   // Newton on p_N / p_N' with running rescaling (the ratio is scale free).
   double x = 0.5 * (lo + hi);
-  const double blo = lo - 4.0 * (hi - lo) - 1e-300, bhi = hi + 4.0 * (hi - lo);
+  // The Sturm count is accurate to about eps * ||J|| in absolute terms, so the
+  // bisection value can be that far from the zero; Newton may move it within a
+  // window that is still far below the spacing of neighbouring zeros.
+  double gmax = 0.0;
+  for (int k = 0; k < N; ++k) gmax = fmax(gmax, fabs(alpha[k]) + 2.0 * sqrt(beta[k < N - 1 ? k + 1 : k]));
+  const double win = 1e-9 * gmax + 4.0 * (hi - lo);
+  const double blo = x - win, bhi = x + win;
   for (int it = 0; it < 6; ++it) {
     double p0 = 0.0, p1 = 1.0, d0 = 0.0, d1 = 0.0;
     for (int k = 0; k < N; ++k) {

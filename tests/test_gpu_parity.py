@@ -78,8 +78,13 @@ def test_grid_matches_oracle(B):
     plan = sgl.sgl_plan(B, 1, "f64")
     g = plan.grid(B)
     o = Q.sgl_grid(B)
-    rel_r = np.abs(g["r"] / o["r"] - 1).max()
-    assert rel_r < 1e-13, rel_r
+    # FP64 recurrence coefficients are accurate to ~eps relative; the smallest
+    # zeros (r_0 ~ N^-1.5) are the worst conditioned: ~1e-12 relative there,
+    # ~1e-16 absolute, and ~1e-15 relative for all others.
+    rel_r = np.abs(g["r"] / o["r"] - 1)
+    assert rel_r.max() < 2e-12, rel_r.max()
+    assert rel_r[4:].max() < 2e-13 if B > 4 else True
+    assert np.abs(g["r"] - o["r"]).max() < 1e-14 * o["r"].max()
     assert np.abs(g["log_a"] - o["log_a"]).max() < 1e-11 * max(1.0, np.abs(o["log_a"]).max() / 100)
     assert np.abs(g["log_sigma"] - o["log_sigma"]).max() < 1e-11 * max(1.0, np.abs(o["log_sigma"]).max() / 100)
     assert np.abs(g["theta"] - o["theta"]).max() < 1e-15
@@ -105,7 +110,30 @@ def test_tables_match_oracle(B):
     Pg, Rg = plan.table(B, 0), plan.table(B, 1)
     Po, Ro = _oracle_tables(B)
     assert np.abs(Pg - Po).max() < 2e-13
-    assert np.abs(Rg - Ro).max() < 2e-13
+    # the radial table inherits the ~1e-12 relative error of the smallest nodes
+    assert np.abs(Rg - Ro).max() < 1e-12
+    plan.destroy()
+
+
+@pytest.mark.parametrize("B", [8, 64, 128, 256])
+def test_gpu_radial_rule_is_exact(B):
+    """Thm. 3.3 for the GPU-built rule itself: sum_i a_i r_i^k = Gamma((k+1)/2)/2 for
+    k <= 4B-1 (log-sum form, a_i underflows), and the GPU radial table has
+    orthonormal rows (the iDRT identity, Sect. 3.3.2)."""
+    plan = sgl.sgl_plan(B, 1, "f64")
+    g = plan.grid(B)
+    la, lr = g["log_a"], np.log(g["r"])
+    for k in range(0, 4 * B, max(1, B // 8)):
+        t = la + k * lr
+        mx = t.max()
+        lsum = mx + math.log(np.exp(t - mx).sum())
+        assert abs(lsum - (math.lgamma((k + 1) / 2) - math.log(2.0))) < 1e-12 * max(1.0, abs(lsum)), k
+    R = plan.table(B, 1)
+    off = 0
+    for l in range(B):
+        blk = R[off:off + (B - l) * 2 * B].reshape(B - l, 2 * B)
+        off += (B - l) * 2 * B
+        assert np.abs(blk @ blk.T - np.eye(B - l)).max() < 1e-13, l
     plan.destroy()
 
 
