@@ -97,6 +97,191 @@ __device__ void stockham_stage(const T2* in, T2* out, const T2* tw, int L, int R
   }
 }
 
+// ---------------------------------------------------------------------------
+// Power-of-two rings (L = 16 .. 512): register four-step FFT.
+//   x[R2 n1 + n2], X[k1 + R1 k2]:  X = DFT_R2 over n2 of ( w_L^{n2 k1} * DFT_R1 over n1 ),
+// pass 1 holds one n2 column (R1 values) per thread, pass 2 one k1 row (R2
+// values); the exchange goes through LDS laid out [k1][n2][ring] so that both
+// passes access it without bank conflicts, and the ring index is the fastest
+// lane index in pass 2, so spectral values of RPB consecutive columns leave in
+// one contiguous run per (m, j).
+// ---------------------------------------------------------------------------
+
+// cos(2 pi q / 32), sin(2 pi q / 32), q < 16 (first-quadrant values and symmetry)
+#define C32_0 1.0
+#define C32_1 0.98078528040323044913
+#define C32_2 0.92387953251128675613
+#define C32_3 0.83146961230254523708
+#define C32_4 0.70710678118654752440
+#define C32_5 0.55557023301960222474
+#define C32_6 0.38268343236508977173
+#define C32_7 0.19509032201612826785
+#define C32_8 0.0
+__device__ constexpr double kCos32[16] = {C32_0, C32_1, C32_2, C32_3, C32_4, C32_5, C32_6, C32_7,
+                                          C32_8, -C32_7, -C32_6, -C32_5, -C32_4, -C32_3, -C32_2, -C32_1};
+__device__ constexpr double kSin32[16] = {C32_8, C32_7, C32_6, C32_5, C32_4, C32_3, C32_2, C32_1,
+                                          C32_0, C32_1, C32_2, C32_3, C32_4, C32_5, C32_6, C32_7};
+
+template <int R>
+__host__ __device__ constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// In-register DFT of size R (power of two <= 32): v[k] = sum_n v[n] exp(-+2 pi i n k / R).
+template <typename T2, int R, bool INV>
+__device__ inline void dft_reg(T2 (&v)[R]) {
+  using Tr = decltype(v[0].x);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = bitrev<R>(i);
+    if (j > i) {
+      T2 t = v[i];
+      v[i] = v[j];
+      v[j] = t;
+    }
+  }
+#pragma unroll
+  for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < R; i += len) {
+#pragma unroll
+      for (int j = 0; j < len / 2; ++j) {
+        const int q = j * (32 / len);
+        T2 w;
+        w.x = (Tr)kCos32[q];
+        w.y = INV ? (Tr)kSin32[q] : -(Tr)kSin32[q];
+        const T2 u = v[i + j];
+        const T2 t = j == 0 ? v[i + j + len / 2] : cmul(v[i + j + len / 2], w);
+        v[i + j] = cadd(u, t);
+        v[i + j + len / 2] = csub(u, t);
+      }
+    }
+  }
+}
+
+template <typename T, int R1, int R2, bool RAW>
+__device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int rpb,
+                                const typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds) {
+  using T2 = typename C2<T>::t;
+  constexpr int L = R1 * R2, B = L / 2;
+  const int t = threadIdx.x;
+  const int P = rpb + 1;
+  const T2* tw = reinterpret_cast<const T2*>(C.tw);
+  if (t < rpb * R2) {
+    const int r = t / R2, n2 = t % R2;
+    if (r < nr) {
+      const int col = col0 + r;
+      const int b = col / L, i = col % L;
+      const T2* src = samples + C.soff[b] + ((int64_t)i * L + j) * L;
+      T2 v[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) v[n1] = src[R2 * n1 + n2];
+      if (RAW) {
+        const T sg = (T)C.sigma[i];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) {
+          v[n1].x *= sg;
+          v[n1].y *= sg;
+        }
+      }
+      dft_reg<T2, R1, false>(v);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) {
+        const T2 w = k1 == 0 ? v[k1] : cmul(v[k1], tw[(n2 * k1) % L]);
+        lds[(k1 * R2 + n2) * P + r] = w;
+      }
+    }
+  }
+  __syncthreads();
+  if (t < rpb * R1) {
+    const int r = t % rpb, k1 = t / rpb;
+    if (r < nr) {
+      T2 y[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) y[n2] = lds[(k1 * R2 + n2) * P + r];
+      dft_reg<T2, R2, false>(y);
+      const T wj = (T)C.btilde[j];
+      const int ncol = C.nf * L;
+      T2* F = reinterpret_cast<T2*>(C.F);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        const int bin = k1 + R1 * k2;
+        if (bin == B) continue;
+        const int mi = (bin < B ? bin : bin - L) + B - 1;
+        T2 o = y[k2];
+        o.x *= wj;
+        o.y *= wj;
+        F[((int64_t)mi * L + j) * ncol + col0 + r] = o;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int R1, int R2, bool RAW>
+__device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int rpb,
+                                typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds) {
+  using T2 = typename C2<T>::t;
+  constexpr int L = R1 * R2, B = L / 2;
+  const int t = threadIdx.x;
+  const int P = rpb + 1;
+  const T2* tw = reinterpret_cast<const T2*>(C.tw);
+  if (t < rpb * R1) {
+    const int r = t % rpb, k1 = t / rpb;
+    if (r < nr) {
+      const int ncol = C.nf * L;
+      const T2* F = reinterpret_cast<const T2*>(C.F);
+      T2 y[R2];
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        const int bin = k1 + R1 * k2;
+        if (bin == B) {
+          y[k2].x = 0;
+          y[k2].y = 0;
+        } else {
+          const int mi = (bin < B ? bin : bin - L) + B - 1;
+          y[k2] = F[((int64_t)mi * L + j) * ncol + col0 + r];
+        }
+      }
+      dft_reg<T2, R2, true>(y);
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) {
+        const T2 w = n2 == 0 ? y[n2] : cmul(y[n2], conjc(tw[(n2 * k1) % L]));
+        lds[(k1 * R2 + n2) * P + r] = w;
+      }
+    }
+  }
+  __syncthreads();
+  if (t < rpb * R2) {
+    const int r = t / R2, n2 = t % R2;
+    if (r < nr) {
+      T2 v[R1];
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) v[k1] = lds[(k1 * R2 + n2) * P + r];
+      dft_reg<T2, R1, true>(v);
+      const int col = col0 + r;
+      const int b = col / L, i = col % L;
+      T2* dst = samples + C.soff[b] + ((int64_t)i * L + j) * L;
+      if (RAW) {
+        const T sg = (T)(1.0 / C.sigma[i]);
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) {
+          v[n1].x *= sg;
+          v[n1].y *= sg;
+        }
+      }
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) dst[R2 * n1 + n2] = v[n1];
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T, bool RAW>
 __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                                      int nwork, const void* __restrict__ samples_v) {
@@ -112,6 +297,15 @@ __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict
     const int rpb = it.w;
     const int col0 = it.z * rpb;
     const int nr = min(rpb, ncol - col0);
+    switch (L) {
+      case 16: fwd_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 32: fwd_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 64: fwd_pow2<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 128: fwd_pow2<T, 16, 8, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 256: fwd_pow2<T, 16, 16, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 512: fwd_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      default: break;
+    }
     T2* buf0 = smem;
     T2* buf1 = smem + rpb * L;
     for (int e = threadIdx.x; e < nr * L; e += blockDim.x) {
@@ -171,6 +365,15 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const ClassDesc* __restrict
     const int rpb = it.w;
     const int col0 = it.z * rpb;
     const int nr = min(rpb, ncol - col0);
+    switch (L) {
+      case 16: inv_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 32: inv_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 64: inv_pow2<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 128: inv_pow2<T, 16, 8, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 256: inv_pow2<T, 16, 16, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      case 512: inv_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
+      default: break;
+    }
     T2* buf0 = smem;
     T2* buf1 = smem + rpb * L;
     const T2* F = reinterpret_cast<const T2*>(C.F);
@@ -223,14 +426,25 @@ inline int grid_for(int nwork) { return nwork < 4096 ? nwork : 4096; }
 }  // namespace
 
 // LDS bytes for rings_per_block rings of length L in the given precision
-static size_t fft_lds_bytes(int prec, int rpb, int Lmax) {
-  return (size_t)2 * rpb * Lmax * (prec == PREC_F64 ? sizeof(double2) : sizeof(float2));
+static size_t fft_lds_bytes(int prec, int rpb, int L) {
+  const size_t es = prec == PREC_F64 ? sizeof(double2) : sizeof(float2);
+  if (fft_pow2_path(L)) return (size_t)L * (rpb + 1) * es;
+  return (size_t)2 * rpb * L * es;
+}
+
+template <typename K>
+static void allow_lds(K kernel, int bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
                               int lds_bytes, const void* samples, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   dim3 grid(grid_for(nwork)), block(256);
+  allow_lds(k_fft_forward<double, true>, lds_bytes);
+  allow_lds(k_fft_forward<double, false>, lds_bytes);
+  allow_lds(k_fft_forward<float, false>, lds_bytes);
   if (prec == PREC_F64) {
     if (raw)
       hipLaunchKernelGGL((k_fft_forward<double, true>), grid, block, lds_bytes, s, d_cls, d_work, nwork, samples);
@@ -246,6 +460,9 @@ hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const 
                               int lds_bytes, void* samples, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   dim3 grid(grid_for(nwork)), block(256);
+  allow_lds(k_fft_inverse<double, true>, lds_bytes);
+  allow_lds(k_fft_inverse<double, false>, lds_bytes);
+  allow_lds(k_fft_inverse<float, false>, lds_bytes);
   if (prec == PREC_F64) {
     if (raw)
       hipLaunchKernelGGL((k_fft_inverse<double, true>), grid, block, lds_bytes, s, d_cls, d_work, nwork, samples);

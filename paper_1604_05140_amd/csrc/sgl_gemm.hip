@@ -5,40 +5,51 @@
 //   forward  g[l][m][b,i] = sum_j Pbar_lm(cos th_j) F[m][j][b,i],   l = |m|..B-1
 //   inverse  F[m][j][b,i] = sum_l Pbar_lm(cos th_j) g[l][m][b,i]
 // with the b~_j weight already folded into F by stage (a).  Orders m and -m
-// share one launch tile list: Pbar_{l,-m} = (-1)^m Pbar_lm, so the -m columns
-// run against the same table block and take the sign in the epilogue.
+// share one tile list: Pbar_{l,-m} = (-1)^m Pbar_lm, so the -m columns run
+// against the same table block and take the sign in the epilogue.
 //
 // Stage (c), radial projection per degree l (discrete R transform, Eq. DRT /
 // Eq. DRT_matrix; inverse R_l^T, Sect. 3.3.2):
 //   forward  fhat[b][omega(n,l,m)] = sum_i rho_nl(r_i) g[l][m][b,i],  n = l+1..B
 //   inverse  g[l][m][b,i] = sum_n rho_nl(r_i) fhat[b][omega(n,l,m)]
 // where rho_nl(r_i) = sigma_i N_nl R_nl(r_i) has orthonormal rows (the iDRT
-// identity), so one table serves both directions.
+// identity), so the same values serve both directions.
 //
 // Every contraction is a real table (M x K) times complex data (K x N complex
-// columns = 2N real columns).  One kernel template covers the four cases; the
-// tile loaders read the operands where they live (no transposed copies) and
-// the epilogues write the next stage's layout directly:
-//   F  [(m+B-1)][j][b*2B+i]          (stage a <-> b)
-//   g  [l][b][m+l][i], block l at l^2 * nf * 2B   (stage b <-> c)
-//   fhat[b][omega]                    (stage c <-> caller)
+// columns = 2N real columns).  One kernel template covers the four cases:
+//   * tile 128 x 128 real outputs, 4 waves of 64 x 64 (4 x 4 MFMA blocks of
+//     16 x 16); K in chunks of 32 through LDS, the next chunk prefetched into
+//     registers while the MFMAs of the current one run;
+//   * the table operand comes pre-packed per direction (row-major, K padded to
+//     a multiple of 32 with zeros), so every table load is a 16-byte vector;
+//   * data-operand loads follow the layout the previous stage wrote (16-byte
+//     runs along the contiguous index), are transposed in registers so that
+//     each lane holds 8 consecutive k of one column, and go to LDS as [column][k]
+//     (one 16-byte LDS store per column and bf16 plane);
+//   * the epilogue stages the tile through LDS and writes the next stage's
+//     layout with coalesced 16-byte stores:
+//       F    [(m+B-1)][j][b*2B+i]                 (stage a <-> b)
+//       g    [l][b][m+l][i], block l at l^2 nf 2B  (stage b <-> c)
+//       fhat [b][omega]                             (stage c <-> caller)
 //
 // Precisions: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4), and a
 // three-piece bf16 split of both operands (x = x0 + x1 + x2, each a bf16
 // rounding of the remainder) whose six products of order <= 2 run on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation (main product and
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation (main product and the five
 // corrections in separate accumulators).
 #include "sgl_internal.h"
 
 namespace sgl {
 namespace {
 
-constexpr int BM = 64;   // rows per tile
-constexpr int BN = 64;   // real columns per tile (32 complex)
-constexpr int BNC = BN / 2;
-constexpr int BK = 32;   // contraction chunk
-constexpr int NT = 256;  // threads per block (4 waves, 2 x 2 layout of 32 x 32)
-constexpr int BKS = BK + 8;  // bf16 LDS row pitch (80 bytes, 16-byte aligned rows)
+constexpr int BM = 128;      // rows per tile
+constexpr int BN = 128;      // real columns per tile
+constexpr int BNC = BN / 2;  // complex columns per tile
+constexpr int BK = 32;       // contraction chunk
+constexpr int NT = 256;      // 4 waves, 2 x 2 layout of 64 x 64
+constexpr int PS = BK + 8;   // bf16 LDS pitch (80 bytes)
+constexpr int PF = BK + 4;   // f32/f64 LDS pitch in elements
+constexpr int EP = BN + 1;   // epilogue tile pitch (elements)
 
 enum Kind { K_B_FWD = 0, K_B_INV = 1, K_C_FWD = 2, K_C_INV = 3, K_DEBUG = 4 };
 
@@ -48,7 +59,6 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 template <int PREC> struct DT { using t = float; };
 template <> struct DT<PREC_F64> { using t = double; };
-
 template <int PREC> struct Acc { using t = f4; };
 template <> struct Acc<PREC_F64> { using t = d4; };
 
@@ -59,14 +69,17 @@ __device__ inline uint16_t f2bf(float f) {
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-// LDS footprint
-template <int PREC> struct LdsSize {
-  static constexpr int a = BM * (BK + 1) * (int)sizeof(typename DT<PREC>::t);
-  static constexpr int x = BN * (BK + 1) * (int)sizeof(typename DT<PREC>::t);
+template <int PREC> struct Lds {
+  static constexpr int a = BM * PF * (int)sizeof(typename DT<PREC>::t);
+  static constexpr int x = BN * PF * (int)sizeof(typename DT<PREC>::t);
+  static constexpr int ep = 64 * EP * (int)sizeof(typename DT<PREC>::t);
+  static constexpr int total = (a + x) > ep ? (a + x) : ep;
 };
-template <> struct LdsSize<PREC_SPLIT> {
-  static constexpr int a = 3 * BM * BKS * 2;
-  static constexpr int x = 3 * BN * BKS * 2;
+template <> struct Lds<PREC_SPLIT> {
+  static constexpr int a = 3 * BM * PS * 2;
+  static constexpr int x = 3 * BN * PS * 2;
+  static constexpr int ep = 64 * EP * 4;
+  static constexpr int total = (a + x) > ep ? (a + x) : ep;
 };
 
 struct DebugArgs {
@@ -80,54 +93,17 @@ struct Tile {
   int M, K, Ncc;   // rows, contraction length, complex columns of the group
   int row0, col0;  // first row, first complex column of the tile
   int q;           // m (stage b) or l (stage c)
+  int pitch;       // packed table row pitch
   const ClassDesc* C;
 };
 
-// ---- LDS stores ------------------------------------------------------------
-template <int PREC>
-__device__ inline void lds_put_a(unsigned char* sm, int r, int k, const void* tab, int64_t idx, int64_t plane,
-                                 bool valid) {
-  if constexpr (PREC == PREC_SPLIT) {
-    uint16_t* As = reinterpret_cast<uint16_t*>(sm);
-    const uint16_t* t = reinterpret_cast<const uint16_t*>(tab);
-    for (int p = 0; p < 3; ++p) As[(p * BM + r) * BKS + k] = valid ? t[p * plane + idx] : (uint16_t)0;
-  } else {
-    using T = typename DT<PREC>::t;
-    T* As = reinterpret_cast<T*>(sm);
-    As[r * (BK + 1) + k] = valid ? reinterpret_cast<const T*>(tab)[idx] : (T)0;
-  }
-}
-
-template <int PREC>
-__device__ inline void lds_put_x(unsigned char* sm, int n, int k, float vf, double vd) {
-  if constexpr (PREC == PREC_SPLIT) {
-    uint16_t* Xs = reinterpret_cast<uint16_t*>(sm + LdsSize<PREC>::a);
-    uint16_t h0 = f2bf(vf);
-    float r1 = vf - bf2f(h0);
-    uint16_t h1 = f2bf(r1);
-    float r2 = r1 - bf2f(h1);
-    uint16_t h2 = f2bf(r2);
-    Xs[(0 * BN + n) * BKS + k] = h0;
-    Xs[(1 * BN + n) * BKS + k] = h1;
-    Xs[(2 * BN + n) * BKS + k] = h2;
-  } else if constexpr (PREC == PREC_F64) {
-    double* Xs = reinterpret_cast<double*>(sm + LdsSize<PREC>::a);
-    Xs[n * (BK + 1) + k] = vd;
-  } else {
-    float* Xs = reinterpret_cast<float*>(sm + LdsSize<PREC>::a);
-    Xs[n * (BK + 1) + k] = vf;
-  }
-}
-
-// ---- operand addressing ----------------------------------------------------
 __device__ inline int64_t gbase(int l, int nf, int L) { return (int64_t)l * l * nf * L; }
 
-// complex element (k, c) of the data operand; returns pointer index in complex units
+// complex index of data-operand element (k, c)
 template <int KIND>
-__device__ inline int64_t x_index(const Tile& t, int k, int c, int& sgn) {
+__device__ inline int64_t x_index(const Tile& t, int k, int c) {
   const ClassDesc& C = *t.C;
   const int B = C.B, L = C.L, nf = C.nf;
-  sgn = 1;
   if constexpr (KIND == K_B_FWD) {
     const int ncf = nf * L;
     const int seg = c >= ncf;
@@ -152,7 +128,7 @@ __device__ inline int64_t x_index(const Tile& t, int k, int c, int& sgn) {
   }
 }
 
-// output index (complex units) and sign for element (row, c)
+// complex index and sign of output element (row, c)
 template <int KIND>
 __device__ inline int64_t c_index(const Tile& t, int row, int c, int& sgn) {
   const ClassDesc& C = *t.C;
@@ -181,6 +157,168 @@ __device__ inline int64_t c_index(const Tile& t, int row, int c, int& sgn) {
   }
 }
 
+// ---- per-thread register staging of one K chunk -----------------------------
+// A: split -> 6 x uint4 (3 planes x 2 vectors); f32 -> 4 x float4; f64 -> 8 x double2.
+// X: 8 consecutive k of one complex column -> 8 complex values.
+template <int PREC> struct Stage {
+  static constexpr int NA = PREC == PREC_SPLIT ? 6 : (PREC == PREC_F32 ? 4 : 8);
+  uint4 a[NA];
+  typename DT<PREC>::t xr[8], xi[8];
+};
+
+// A chunk: BM rows x BK (padded, zero filled) from a packed table block.
+template <int PREC>
+__device__ inline void load_a(Stage<PREC>& st, const Tile& t, const void* tab, int64_t plane, int k0, int tid) {
+  if constexpr (PREC == PREC_SPLIT) {
+    // 3 planes x 128 rows x 4 vectors of 8 bf16
+    for (int v = 0; v < 6; ++v) {
+      const int e = tid + v * NT;  // 0..1535
+      const int p = e / 512, rem = e - p * 512;
+      const int r = rem >> 2, kg = rem & 3;
+      const int gr = t.row0 + r;
+      uint4 z = make_uint4(0, 0, 0, 0);
+      if (gr < t.M)
+        z = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(tab) + p * plane +
+                                            (int64_t)gr * t.pitch + k0 + kg * 8);
+      st.a[v] = z;
+    }
+  } else if constexpr (PREC == PREC_F32) {
+    for (int v = 0; v < 4; ++v) {
+      const int e = tid + v * NT;  // 128 rows x 8 vectors of 4 floats
+      const int r = e >> 3, kg = e & 7;
+      const int gr = t.row0 + r;
+      uint4 z = make_uint4(0, 0, 0, 0);
+      if (gr < t.M)
+        z = *reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(tab) + (int64_t)gr * t.pitch + k0 + kg * 4);
+      st.a[v] = z;
+    }
+  } else {
+    for (int v = 0; v < 8; ++v) {
+      const int e = tid + v * NT;  // 128 rows x 16 vectors of 2 doubles
+      const int r = e >> 4, kg = e & 15;
+      const int gr = t.row0 + r;
+      uint4 z = make_uint4(0, 0, 0, 0);
+      if (gr < t.M)
+        z = *reinterpret_cast<const uint4*>(reinterpret_cast<const double*>(tab) + (int64_t)gr * t.pitch + k0 + kg * 2);
+      st.a[v] = z;
+    }
+  }
+}
+
+template <int PREC>
+__device__ inline void store_a(const Stage<PREC>& st, unsigned char* sm, int tid) {
+  if constexpr (PREC == PREC_SPLIT) {
+    uint16_t* As = reinterpret_cast<uint16_t*>(sm);
+    for (int v = 0; v < 6; ++v) {
+      const int e = tid + v * NT;
+      const int p = e / 512, rem = e - p * 512;
+      const int r = rem >> 2, kg = rem & 3;
+      *reinterpret_cast<uint4*>(&As[(p * BM + r) * PS + kg * 8]) = st.a[v];
+    }
+  } else if constexpr (PREC == PREC_F32) {
+    float* As = reinterpret_cast<float*>(sm);
+    for (int v = 0; v < 4; ++v) {
+      const int e = tid + v * NT;
+      const int r = e >> 3, kg = e & 7;
+      *reinterpret_cast<uint4*>(&As[r * PF + kg * 4]) = st.a[v];
+    }
+  } else {
+    double* As = reinterpret_cast<double*>(sm);
+    for (int v = 0; v < 8; ++v) {
+      const int e = tid + v * NT;
+      const int r = e >> 4, kg = e & 15;
+      *reinterpret_cast<uint4*>(&As[r * PF + kg * 2]) = st.a[v];
+    }
+  }
+}
+
+// X chunk: thread -> (complex column cc = tid & 63, k group kg = tid >> 6 of 8 rows)
+template <int PREC, int KIND>
+__device__ inline void load_x(Stage<PREC>& st, const Tile& t, const void* xbase, const DebugArgs& dbg, int k0,
+                              int tid) {
+  using T = typename DT<PREC>::t;
+  const int cc = tid & 63, kg = tid >> 6;
+  const int c = t.col0 + cc;
+  const int kb = k0 + kg * 8;
+  if constexpr (KIND == K_DEBUG) {
+    for (int u = 0; u < 8; ++u) {
+      const int k = kb + u;
+      const int n0 = 2 * c, n1 = 2 * c + 1;
+      const bool ok = k < t.K;
+      st.xr[u] = (ok && n0 < dbg.N) ? (T)dbg.X[(int64_t)k * dbg.N + n0] : (T)0;
+      st.xi[u] = (ok && n1 < dbg.N) ? (T)dbg.X[(int64_t)k * dbg.N + n1] : (T)0;
+    }
+  } else {
+    const T* X = reinterpret_cast<const T*>(xbase);
+    if (c < t.Ncc) {
+      if constexpr (KIND == K_C_FWD) {
+        // 8 consecutive k of one column are contiguous (g rows run along i)
+        const int64_t ix = x_index<KIND>(t, kb, c);
+        for (int u = 0; u < 8; ++u) {
+          const bool ok = kb + u < t.K;
+          st.xr[u] = ok ? X[2 * (ix + u)] : (T)0;
+          st.xi[u] = ok ? X[2 * (ix + u) + 1] : (T)0;
+        }
+      } else {
+        for (int u = 0; u < 8; ++u) {
+          const int k = kb + u;
+          if (k < t.K) {
+            const int64_t ix = x_index<KIND>(t, k, c);
+            st.xr[u] = X[2 * ix];
+            st.xi[u] = X[2 * ix + 1];
+          } else {
+            st.xr[u] = 0;
+            st.xi[u] = 0;
+          }
+        }
+      }
+    } else {
+      for (int u = 0; u < 8; ++u) {
+        st.xr[u] = 0;
+        st.xi[u] = 0;
+      }
+    }
+  }
+}
+
+template <int PREC>
+__device__ inline void store_x(const Stage<PREC>& st, unsigned char* sm, int tid) {
+  const int cc = tid & 63, kg = tid >> 6;
+  if constexpr (PREC == PREC_SPLIT) {
+    uint16_t* Xs = reinterpret_cast<uint16_t*>(sm + Lds<PREC>::a);
+    uint16_t h[2][3][8];
+    for (int u = 0; u < 8; ++u) {
+      const float v2[2] = {st.xr[u], st.xi[u]};
+      for (int part = 0; part < 2; ++part) {
+        const float v = v2[part];
+        const uint16_t h0 = f2bf(v);
+        const float r1 = v - bf2f(h0);
+        const uint16_t h1 = f2bf(r1);
+        const float r2 = r1 - bf2f(h1);
+        h[part][0][u] = h0;
+        h[part][1][u] = h1;
+        h[part][2][u] = f2bf(r2);
+      }
+    }
+    for (int part = 0; part < 2; ++part)
+      for (int p = 0; p < 3; ++p) {
+        uint4 w;
+        w.x = (uint32_t)h[part][p][0] | ((uint32_t)h[part][p][1] << 16);
+        w.y = (uint32_t)h[part][p][2] | ((uint32_t)h[part][p][3] << 16);
+        w.z = (uint32_t)h[part][p][4] | ((uint32_t)h[part][p][5] << 16);
+        w.w = (uint32_t)h[part][p][6] | ((uint32_t)h[part][p][7] << 16);
+        *reinterpret_cast<uint4*>(&Xs[(p * BN + 2 * cc + part) * PS + kg * 8]) = w;
+      }
+  } else {
+    using T = typename DT<PREC>::t;
+    T* Xs = reinterpret_cast<T*>(sm + Lds<PREC>::a);
+    for (int u = 0; u < 8; ++u) {
+      Xs[(2 * cc) * PF + kg * 8 + u] = st.xr[u];
+      Xs[(2 * cc + 1) * PF + kg * 8 + u] = st.xi[u];
+    }
+  }
+}
+
 // ---- the kernel ------------------------------------------------------------
 template <int PREC, int KIND>
 __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
@@ -188,18 +326,18 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
                                              DebugArgs dbg) {
   using T = typename DT<PREC>::t;
   using AccT = typename Acc<PREC>::t;
-  __shared__ __align__(16) unsigned char sm[LdsSize<PREC>::a + LdsSize<PREC>::x];
+  __shared__ __align__(16) unsigned char sm[Lds<PREC>::total];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
   const int lr = lane & 15, lk = lane >> 4;
 
-  int nitems = KIND == K_DEBUG ? ((dbg.M + BM - 1) / BM) * ((dbg.N + BN - 1) / BN) : nwork;
+  const int nitems = KIND == K_DEBUG ? ((dbg.M + BM - 1) / BM) * ((dbg.N + BN - 1) / BN) : nwork;
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     Tile t;
     const void* tab = nullptr;
     int64_t plane = 0;
-    int ld = 0;
+    const void* xbase = nullptr;
     if constexpr (KIND == K_DEBUG) {
       const int ntn = (dbg.N + BN - 1) / BN;
       t.M = dbg.M;
@@ -208,6 +346,7 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
       t.row0 = (w / ntn) * BM;
       t.col0 = (w % ntn) * BNC;
       t.q = 0;
+      t.pitch = 0;
       t.C = nullptr;
     } else {
       const int4 it = work[w];
@@ -215,190 +354,207 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
       t.C = &C;
       t.q = it.y;
       const int B = C.B, L = C.L;
-      if constexpr (KIND == K_B_FWD || KIND == K_B_INV) {
-        const int rows = B - t.q;
-        t.M = KIND == K_B_FWD ? rows : L;
-        t.K = KIND == K_B_FWD ? L : rows;
+      const int rows = B - t.q;
+      constexpr int kind = KIND;
+      if constexpr (KIND == K_B_FWD || KIND == K_B_INV)
         t.Ncc = (t.q ? 2 : 1) * C.nf * L;
-        tab = C.P;
-      } else {
-        const int rows = B - t.q;
-        t.M = KIND == K_C_FWD ? rows : L;
-        t.K = KIND == K_C_FWD ? L : rows;
+      else
         t.Ncc = (2 * t.q + 1) * C.nf;
-        tab = C.R;
-      }
-      const int64_t off = table_block(B, t.q);
-      if constexpr (PREC == PREC_SPLIT) {
-        tab = reinterpret_cast<const uint16_t*>(tab) + off;
-        plane = table_size(B);
-      } else {
-        tab = reinterpret_cast<const T*>(tab) + off;
-      }
-      ld = L;
+      const bool fwd = KIND == K_B_FWD || KIND == K_C_FWD;
+      t.M = fwd ? rows : L;
+      t.K = fwd ? L : rows;
+      t.pitch = (t.K + BK - 1) / BK * BK;
+      plane = C.Aplane[kind];
+      tab = reinterpret_cast<const unsigned char*>(C.A[kind]) + C.Aoff[kind][t.q] * (int64_t)(PREC == PREC_SPLIT ? 2 : sizeof(T));
       t.row0 = it.z * BM;
       t.col0 = it.w * BNC;
+      xbase = KIND == K_B_FWD ? C.F : (KIND == K_C_INV ? cin : C.g);
     }
 
-    AccT acc[2][2], acc2[2][2];
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b)
+    AccT acc[4][4], acc2[4][4];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
         for (int v = 0; v < 4; ++v) {
           acc[a][b][v] = 0;
-          acc2[a][b][v] = 0;
+          if constexpr (PREC == PREC_SPLIT) acc2[a][b][v] = 0;
         }
+    // wave-uniform MFMA block masks (rows / columns beyond the group)
+    int nbi = 0, nbj = 0;
+    {
+      const int rleft = t.M - (t.row0 + wr);
+      nbi = rleft <= 0 ? 0 : (rleft >= 64 ? 4 : (rleft + 15) / 16);
+      const int cleft = 2 * t.Ncc - (2 * t.col0 + wc);
+      nbj = cleft <= 0 ? 0 : (cleft >= 64 ? 4 : (cleft + 15) / 16);
+    }
+
+    Stage<PREC> st;
+    if constexpr (KIND == K_DEBUG) {
+      // debug: A straight from FP64 row-major [M][K]
+      for (int v = 0; v < Stage<PREC>::NA; ++v) st.a[v] = make_uint4(0, 0, 0, 0);
+    } else {
+      load_a<PREC>(st, t, tab, plane, 0, tid);
+    }
+    load_x<PREC, KIND>(st, t, xbase, dbg, 0, tid);
 
     for (int k0 = 0; k0 < t.K; k0 += BK) {
-      // ---- A tile -> LDS
+      __syncthreads();  // previous chunk's MFMAs are done with LDS
       if constexpr (KIND == K_DEBUG) {
         for (int e = tid; e < BM * BK; e += NT) {
           const int r = e / BK, k = e - r * BK;
           const int gr = t.row0 + r, gk = k0 + k;
-          const bool ok = gr < t.M && gk < t.K;
-          const double v = ok ? dbg.A[(int64_t)gr * t.K + gk] : 0.0;
+          const double v = (gr < t.M && gk < t.K) ? dbg.A[(int64_t)gr * t.K + gk] : 0.0;
           if constexpr (PREC == PREC_SPLIT) {
             uint16_t* As = reinterpret_cast<uint16_t*>(sm);
-            uint16_t h0 = f2bf((float)v);
-            double r1 = v - (double)bf2f(h0);
-            uint16_t h1 = f2bf((float)r1);
-            double r2 = r1 - (double)bf2f(h1);
-            As[(0 * BM + r) * BKS + k] = h0;
-            As[(1 * BM + r) * BKS + k] = h1;
-            As[(2 * BM + r) * BKS + k] = f2bf((float)r2);
+            const uint16_t h0 = f2bf((float)v);
+            const double r1 = v - (double)bf2f(h0);
+            const uint16_t h1 = f2bf((float)r1);
+            As[(0 * BM + r) * PS + k] = h0;
+            As[(1 * BM + r) * PS + k] = h1;
+            As[(2 * BM + r) * PS + k] = f2bf((float)(r1 - (double)bf2f(h1)));
           } else {
-            reinterpret_cast<T*>(sm)[r * (BK + 1) + k] = (T)v;
+            reinterpret_cast<T*>(sm)[r * PF + k] = (T)v;
           }
-        }
-      } else if constexpr (KIND == K_B_FWD || KIND == K_C_FWD) {
-        // table block rows are contiguous in k
-        for (int e = tid; e < BM * BK; e += NT) {
-          const int r = e / BK, k = e - r * BK;
-          const int gr = t.row0 + r, gk = k0 + k;
-          lds_put_a<PREC>(sm, r, k, tab, (int64_t)gr * ld + gk, plane, gr < t.M && gk < t.K);
         }
       } else {
-        // inverse: A = table block transposed, contiguous in the tile row
-        for (int e = tid; e < BM * BK; e += NT) {
-          const int k = e / BM, r = e - k * BM;
-          const int gr = t.row0 + r, gk = k0 + k;
-          lds_put_a<PREC>(sm, r, k, tab, (int64_t)gk * ld + gr, plane, gr < t.M && gk < t.K);
-        }
+        store_a<PREC>(st, sm, tid);
       }
-      // ---- X tile -> LDS (as [real column][k])
-      if constexpr (KIND == K_DEBUG) {
-        for (int e = tid; e < BN * BK; e += NT) {
-          const int k = e / BN, n = e - k * BN;
-          const int gk = k0 + k, gn = 2 * t.col0 + n;
-          const double v = (gk < t.K && gn < dbg.N) ? dbg.X[(int64_t)gk * dbg.N + gn] : 0.0;
-          lds_put_x<PREC>(sm, n, k, (float)v, v);
-        }
-      } else if constexpr (KIND == K_C_FWD) {
-        // contiguous along k
-        const T* X = reinterpret_cast<const T*>(t.C->g);
-        for (int e = tid; e < BNC * BK; e += NT) {
-          const int cc = e / BK, k = e - cc * BK;
-          const int gk = k0 + k, c = t.col0 + cc;
-          T re = 0, im = 0;
-          if (gk < t.K && c < t.Ncc) {
-            int sg;
-            const int64_t ix = x_index<KIND>(t, gk, c, sg);
-            re = X[2 * ix];
-            im = X[2 * ix + 1];
-          }
-          lds_put_x<PREC>(sm, 2 * cc, k, (float)re, (double)re);
-          lds_put_x<PREC>(sm, 2 * cc + 1, k, (float)im, (double)im);
-        }
-      } else {
-        // contiguous along the column index
-        const T* X = reinterpret_cast<const T*>(KIND == K_B_FWD ? t.C->F : (KIND == K_B_INV ? t.C->g : cin));
-        for (int e = tid; e < BNC * BK; e += NT) {
-          const int k = e / BNC, cc = e - k * BNC;
-          const int gk = k0 + k, c = t.col0 + cc;
-          T re = 0, im = 0;
-          if (gk < t.K && c < t.Ncc) {
-            int sg;
-            const int64_t ix = x_index<KIND>(t, gk, c, sg);
-            re = X[2 * ix];
-            im = X[2 * ix + 1];
-          }
-          lds_put_x<PREC>(sm, 2 * cc, k, (float)re, (double)re);
-          lds_put_x<PREC>(sm, 2 * cc + 1, k, (float)im, (double)im);
-        }
-      }
+      store_x<PREC>(st, sm, tid);
       __syncthreads();
-
-      // ---- MFMA
+      if (k0 + BK < t.K) {  // prefetch the next chunk while the MFMAs run
+        if constexpr (KIND != K_DEBUG) load_a<PREC>(st, t, tab, plane, k0 + BK, tid);
+        load_x<PREC, KIND>(st, t, xbase, dbg, k0 + BK, tid);
+      }
       if constexpr (PREC == PREC_SPLIT) {
         const uint16_t* As = reinterpret_cast<const uint16_t*>(sm);
-        const uint16_t* Xs = reinterpret_cast<const uint16_t*>(sm + LdsSize<PREC>::a);
-        bf8 a[2][3], b[2][3];
-        for (int i = 0; i < 2; ++i)
-          for (int p = 0; p < 3; ++p) {
-            a[i][p] = *reinterpret_cast<const bf8*>(&As[(p * BM + wr + i * 16 + lr) * BKS + 8 * lk]);
-            b[i][p] = *reinterpret_cast<const bf8*>(&Xs[(p * BN + wc + i * 16 + lr) * BKS + 8 * lk]);
+        const uint16_t* Xs = reinterpret_cast<const uint16_t*>(sm + Lds<PREC>::a);
+        bf8 b[4][3];
+        for (int j = 0; j < 4; ++j)
+          if (j < nbj)
+            for (int p = 0; p < 3; ++p)
+              b[j][p] = *reinterpret_cast<const bf8*>(&Xs[(p * BN + wc + j * 16 + lr) * PS + 8 * lk]);
+        for (int i = 0; i < 4; ++i) {
+          if (i >= nbi) continue;
+          bf8 a[3];
+          for (int p = 0; p < 3; ++p)
+            a[p] = *reinterpret_cast<const bf8*>(&As[(p * BM + wr + i * 16 + lr) * PS + 8 * lk]);
+          for (int j = 0; j < 4; ++j) {
+            if (j >= nbj) continue;
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc[i][j], 0, 0, 0);
+            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][1], acc2[i][j], 0, 0, 0);
+            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][0], acc2[i][j], 0, 0, 0);
+            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][2], acc2[i][j], 0, 0, 0);
+            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][1], acc2[i][j], 0, 0, 0);
+            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][0], acc2[i][j], 0, 0, 0);
           }
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], acc[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][1], acc2[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][0], acc2[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][2], acc2[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][1], acc2[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][0], acc2[i][j], 0, 0, 0);
-          }
+        }
       } else {
         const T* As = reinterpret_cast<const T*>(sm);
-        const T* Xs = reinterpret_cast<const T*>(sm + LdsSize<PREC>::a);
+        const T* Xs = reinterpret_cast<const T*>(sm + Lds<PREC>::a);
         for (int kk = 0; kk < BK; kk += 4) {
-          T a[2], b[2];
-          for (int i = 0; i < 2; ++i) {
-            a[i] = As[(wr + i * 16 + lr) * (BK + 1) + kk + lk];
-            b[i] = Xs[(wc + i * 16 + lr) * (BK + 1) + kk + lk];
+          T a[4], b[4];
+          for (int i = 0; i < 4; ++i) {
+            a[i] = As[(wr + i * 16 + lr) * PF + kk + lk];
+            b[i] = Xs[(wc + i * 16 + lr) * PF + kk + lk];
           }
-          for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) {
+          for (int i = 0; i < 4; ++i) {
+            if (i >= nbi) continue;
+            for (int j = 0; j < 4; ++j) {
+              if (j >= nbj) continue;
               if constexpr (PREC == PREC_F64)
                 acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
               else
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
             }
-        }
-      }
-      __syncthreads();
-    }
-
-    // ---- epilogue: each lane holds 4 rows of real column lane%16 of each 16x16 block:
-    // rows 4*(lane/16)+v for the f32 MFMAs, rows 4*v+lane/16 for the f64 MFMA.
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) {
-        const int nr = 2 * t.col0 + wc + j * 16 + lr;  // real column
-        const int c = nr >> 1, part = nr & 1;
-        if (c >= t.Ncc) continue;
-        for (int v = 0; v < 4; ++v) {
-          const int rin = PREC == PREC_F64 ? 4 * v + lk : 4 * lk + v;
-          const int row = t.row0 + wr + i * 16 + rin;
-          if (row >= t.M) continue;
-          T val;
-          if constexpr (PREC == PREC_SPLIT)
-            val = acc[i][j][v] + acc2[i][j][v];
-          else
-            val = acc[i][j][v];
-          if constexpr (KIND == K_DEBUG) {
-            if (nr < dbg.N) dbg.C[(int64_t)row * dbg.N + nr] = (double)val;
-          } else {
-            int sg;
-            const int64_t ix = c_index<KIND>(t, row, c, sg);
-            T* out;
-            if constexpr (KIND == K_B_FWD || KIND == K_C_INV)
-              out = reinterpret_cast<T*>(t.C->g);
-            else if constexpr (KIND == K_B_INV)
-              out = reinterpret_cast<T*>(t.C->F);
-            else
-              out = reinterpret_cast<T*>(cout);
-            out[2 * ix + part] = sg < 0 ? -val : val;
           }
         }
       }
+    }
+
+    // ---- epilogue through LDS, one 64-row half at a time.  Lane layout of a
+    // 16 x 16 block: real column lane%16; rows 4*(lane/16)+v (f32 MFMAs) or
+    // 4*v+lane/16 (f64 MFMA).
+    T* E = reinterpret_cast<T*>(sm);
+    for (int half = 0; half < 2; ++half) {
+      if (t.row0 + half * 64 >= t.M) break;
+      __syncthreads();
+      if (wr == half * 64) {
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j)
+            for (int v = 0; v < 4; ++v) {
+              const int rin = PREC == PREC_F64 ? 4 * v + lk : 4 * lk + v;
+              T val;
+              if constexpr (PREC == PREC_SPLIT)
+                val = acc[i][j][v] + acc2[i][j][v];
+              else
+                val = acc[i][j][v];
+              E[(i * 16 + rin) * EP + wc + j * 16 + lr] = val;
+            }
+      }
+      __syncthreads();
+      const int rbase = t.row0 + half * 64;
+      if constexpr (KIND == K_DEBUG) {
+        for (int e = tid; e < 64 * BN; e += NT) {
+          const int r = e / BN, n = e - r * BN;
+          const int row = rbase + r, nr = 2 * t.col0 + n;
+          if (row < t.M && nr < dbg.N) dbg.C[(int64_t)row * dbg.N + nr] = (double)E[r * EP + n];
+        }
+      } else if constexpr (KIND == K_C_INV) {
+        // column-major output (g rows run along i = tile row): pairs of rows
+        T* out = reinterpret_cast<T*>(t.C->g);
+        for (int e = tid; e < 32 * BNC; e += NT) {
+          const int cc = e >> 5, rp = (e & 31) * 2;
+          const int c = t.col0 + cc, row = rbase + rp;
+          if (c >= t.Ncc || row >= t.M) continue;
+          int sg;
+          const int64_t ix = c_index<KIND>(t, row, c, sg);
+          const T r0 = E[rp * EP + 2 * cc], i0 = E[rp * EP + 2 * cc + 1];
+          if (row + 1 < t.M) {
+            const T r1 = E[(rp + 1) * EP + 2 * cc], i1 = E[(rp + 1) * EP + 2 * cc + 1];
+            if constexpr (PREC == PREC_F64) {
+              reinterpret_cast<double2*>(out)[ix] = make_double2(r0, i0);
+              reinterpret_cast<double2*>(out)[ix + 1] = make_double2(r1, i1);
+            } else {
+              *reinterpret_cast<float4*>(out + 2 * ix) = make_float4(r0, i0, r1, i1);
+            }
+          } else {
+            out[2 * ix] = r0;
+            out[2 * ix + 1] = i0;
+          }
+        }
+      } else {
+        // row-major outputs: pairs of consecutive complex columns of one row
+        T* out = reinterpret_cast<T*>(KIND == K_B_FWD ? t.C->g : (KIND == K_B_INV ? t.C->F : cout));
+        for (int e = tid; e < 64 * (BNC / 2); e += NT) {
+          const int r = e >> 5, cp = (e & 31) * 2;
+          const int row = rbase + r, c = t.col0 + cp;
+          if (row >= t.M || c >= t.Ncc) continue;
+          int s0, s1 = 1;
+          const int64_t i0 = c_index<KIND>(t, row, c, s0);
+          T re0 = E[r * EP + 2 * cp], im0 = E[r * EP + 2 * cp + 1];
+          if (s0 < 0) { re0 = -re0; im0 = -im0; }
+          if (c + 1 < t.Ncc) {
+            const int64_t i1 = c_index<KIND>(t, row, c + 1, s1);
+            T re1 = E[r * EP + 2 * cp + 2], im1 = E[r * EP + 2 * cp + 3];
+            if (s1 < 0) { re1 = -re1; im1 = -im1; }
+            if constexpr (PREC != PREC_F64) {
+              if (i1 == i0 + 1 && ((reinterpret_cast<uintptr_t>(out + 2 * i0) & 15) == 0)) {
+                *reinterpret_cast<float4*>(out + 2 * i0) = make_float4(re0, im0, re1, im1);
+                continue;
+              }
+            }
+            out[2 * i1] = re1;
+            out[2 * i1 + 1] = im1;
+          }
+          if constexpr (PREC == PREC_F64) {
+            reinterpret_cast<double2*>(out)[i0] = make_double2(re0, im0);
+          } else {
+            out[2 * i0] = re0;
+            out[2 * i0 + 1] = im0;
+          }
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -438,6 +594,7 @@ hipError_t launch_any(int prec, int kind, const ClassDesc* d_cls, const int4* d_
 
 int gemm_tile_m() { return BM; }
 int gemm_tile_n_complex() { return BNC; }
+int gemm_k_chunk() { return BK; }
 
 hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
                            hipStream_t s) {

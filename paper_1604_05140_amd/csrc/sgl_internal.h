@@ -53,8 +53,15 @@ struct ClassDesc {
   int rad[kMaxRadices];
   const int64_t* soff;  // per-function sample offsets (complex values)
   const int64_t* coff;  // per-function coefficient offsets (complex values)
-  const void* P;        // Legendre table in the plan precision (A operand of stage b)
-  const void* R;        // radial table in the plan precision (A operand of stage c)
+  // Packed table operands in the plan precision, one per contraction:
+  // 0 Legendre forward (rows l, k = j), 1 Legendre inverse (rows j, k = l),
+  // 2 radial forward (rows n, k = i), 3 radial inverse (rows i, k = n).
+  // Block q (order m or degree l) is row-major with the contraction length
+  // padded to a multiple of 32 (zeros); split tables hold 3 bf16 planes of
+  // Aplane elements each.
+  const void* A[4];
+  const int64_t* Aoff[4];  // element offset of block q
+  int64_t Aplane[4];
   const double* btilde; // b~_j, 2B
   const double* sigma;  // sigma_i, 2B (raw-sample scaling)
   const void* tw;       // twiddles exp(-2 pi i q / L), q < L (double2 or float2)
@@ -74,6 +81,14 @@ hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const 
 hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
                               int lds_bytes, void* samples, hipStream_t s);
 size_t fft_lds_bytes_for(int prec, int rpb, int L);
+// power-of-two ring lengths 16..512 take the register four-step path; its rings
+// per block are 256 / R1 with L = R1 * R2, R1 = R2 or 2 R2.
+inline bool fft_pow2_path(int L) { return L >= 16 && L <= 512 && (L & (L - 1)) == 0; }
+inline int fft_pow2_rpb(int L) {
+  int r1 = 1;
+  while (r1 * r1 < L) r1 <<= 1;  // R1 = sqrt(L) or sqrt(2L)
+  return 256 / r1;
+}
 hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
                            hipStream_t s);
 hipError_t launch_radial(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
@@ -82,6 +97,7 @@ hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, con
                              hipStream_t s);
 int gemm_tile_m();
 int gemm_tile_n_complex();
+int gemm_k_chunk();
 
 // Plan-time FP64 kernels (sgl_tables.hip)
 struct GridBuild {
@@ -99,5 +115,9 @@ hipError_t build_tables(int B, const double* r, const double* log_sig, const dou
 hipError_t build_twiddles(int L, void* tw, bool f32, hipStream_t s);
 hipError_t convert_table_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 hipError_t convert_table_split(const double* src, uint16_t* dst, int64_t n, hipStream_t s);
+// Pack an FP64 natural table (Legendre for kind 0/1, radial for kind 2/3) into the
+// GEMM operand layout of `kind` in precision `prec` (see ClassDesc::A).
+hipError_t pack_table(int B, int kind, int prec, const double* T64, const int64_t* d_offs, void* dst,
+                      int64_t plane, hipStream_t s);
 
 }  // namespace sgl

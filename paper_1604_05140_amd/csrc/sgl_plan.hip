@@ -23,8 +23,9 @@ struct ClassHost {
   double* grid = nullptr;  // r, log_a, log_sig, sig, theta, btilde (6 x 2B)
   double* P64 = nullptr;
   double* R64 = nullptr;
-  void* P = nullptr;
-  void* R = nullptr;
+  void* A[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t* Aoff[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t Aplane[4] = {0, 0, 0, 0};
   void* tw = nullptr;
   void* F = nullptr;
   void* g = nullptr;
@@ -109,19 +110,25 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
   SGL_TRY(p->alloc((void**)&c.P64, ts * sizeof(double)));
   SGL_TRY(p->alloc((void**)&c.R64, ts * sizeof(double)));
   SGL_HIP_TRY(build_tables(B, gb.r, gb.log_sig, gb.theta, c.P64, c.R64, s));
-  if (p->dtype == SGL_F64) {
-    c.P = c.P64;
-    c.R = c.R64;
-  } else if (p->dtype == SGL_F32) {
-    SGL_TRY(p->alloc(&c.P, ts * sizeof(float)));
-    SGL_TRY(p->alloc(&c.R, ts * sizeof(float)));
-    SGL_HIP_TRY(convert_table_f32(c.P64, (float*)c.P, ts, s));
-    SGL_HIP_TRY(convert_table_f32(c.R64, (float*)c.R, ts, s));
-  } else {
-    SGL_TRY(p->alloc(&c.P, 3 * ts * sizeof(uint16_t)));
-    SGL_TRY(p->alloc(&c.R, 3 * ts * sizeof(uint16_t)));
-    SGL_HIP_TRY(convert_table_split(c.P64, (uint16_t*)c.P, ts, s));
-    SGL_HIP_TRY(convert_table_split(c.R64, (uint16_t*)c.R, ts, s));
+  // packed GEMM operands, one per contraction direction
+  const int prec = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
+  const size_t el = prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2);
+  const int KC = gemm_k_chunk();
+  for (int kind = 0; kind < 4; ++kind) {
+    const bool fwd = kind == 0 || kind == 2;
+    std::vector<int64_t> offs(B);
+    int64_t tot = 0;
+    for (int q = 0; q < B; ++q) {
+      const int rows = fwd ? B - q : L;
+      const int K = fwd ? L : B - q;
+      offs[q] = tot;
+      tot += (int64_t)rows * ((K + KC - 1) / KC * KC);
+    }
+    SGL_TRY(p->alloc((void**)&c.Aoff[kind], B * sizeof(int64_t)));
+    SGL_HIP_TRY(hipMemcpyAsync(c.Aoff[kind], offs.data(), B * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    SGL_TRY(p->alloc(&c.A[kind], (size_t)tot * el * (prec == PREC_SPLIT ? 3 : 1)));
+    c.Aplane[kind] = tot;
+    SGL_HIP_TRY(pack_table(B, kind, prec, kind < 2 ? c.P64 : c.R64, c.Aoff[kind], c.A[kind], tot, s));
   }
   const bool f32 = p->dtype != SGL_F64;
   SGL_TRY(p->alloc(&c.tw, (size_t)L * (f32 ? sizeof(float2) : sizeof(double2))));
@@ -143,9 +150,13 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
   SGL_TRY(p->alloc((void**)&c.coff, nf * sizeof(int64_t)));
   SGL_HIP_TRY(hipMemcpyAsync(c.soff, so.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice, s));
   SGL_HIP_TRY(hipMemcpyAsync(c.coff, co.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  // rings per FFT block: 64 KB of LDS for the ping-pong buffers
-  const int cap = (int)(65536 / (2 * (size_t)L * es));
-  c.rpb = std::max(1, std::min(64, std::min(cap, nf * L)));
+  if (fft_pow2_path(L)) {
+    c.rpb = fft_pow2_rpb(L);
+  } else {
+    // rings per generic-FFT block: 64 KB of LDS for the ping-pong buffers
+    const int cap = (int)(65536 / (2 * (size_t)L * es));
+    c.rpb = std::max(1, std::min(64, std::min(cap, nf * L)));
+  }
   return SGL_OK;
 }
 
@@ -226,8 +237,11 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
     for (int q = 0; q < d.nrad; ++q) d.rad[q] = c.radices[q];
     d.soff = c.soff;
     d.coff = c.coff;
-    d.P = c.P;
-    d.R = c.R;
+    for (int k = 0; k < 4; ++k) {
+      d.A[k] = c.A[k];
+      d.Aoff[k] = c.Aoff[k];
+      d.Aplane[k] = c.Aplane[k];
+    }
     d.btilde = c.grid + 5 * d.L;
     d.sigma = c.grid + 3 * d.L;
     d.tw = c.tw;

@@ -366,6 +366,39 @@ __global__ void k_to_split(const double* src, uint16_t* dst, int64_t n) {
   dst[2 * n + i] = h2;
 }
 
+// Packed GEMM operand from a natural FP64 table (see ClassDesc::A).
+__global__ void k_pack(int B, int kind, int prec, const double* T64, const int64_t* offs, void* dst,
+                       int64_t plane) {
+  const int q = blockIdx.y;
+  const bool fwd = kind == 0 || kind == 2;
+  const int L = 2 * B;
+  const int rows = fwd ? B - q : L;
+  const int K = fwd ? L : B - q;
+  const int pitch = (K + 31) / 32 * 32;
+  const double* src = T64 + table_block(B, q);
+  const int64_t base = offs[q];
+  const int64_t n = (int64_t)rows * pitch;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / pitch), k = (int)(e - (int64_t)r * pitch);
+    double v = 0.0;
+    if (k < K) v = fwd ? src[(int64_t)r * L + k] : src[(int64_t)k * L + r];
+    if (prec == PREC_F64) {
+      reinterpret_cast<double*>(dst)[base + e] = v;
+    } else if (prec == PREC_F32) {
+      reinterpret_cast<float*>(dst)[base + e] = (float)v;
+    } else {
+      uint16_t* d = reinterpret_cast<uint16_t*>(dst);
+      const uint16_t h0 = bf16_rne((float)v);
+      const double r1 = v - bf16_to_double(h0);
+      const uint16_t h1 = bf16_rne((float)r1);
+      const double r2 = r1 - bf16_to_double(h1);
+      d[base + e] = h0;
+      d[plane + base + e] = h1;
+      d[2 * plane + base + e] = bf16_rne((float)r2);
+    }
+  }
+}
+
 inline int nblk(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -456,6 +489,12 @@ hipError_t build_twiddles(int L, void* tw, bool f32, hipStream_t s) {
 
 hipError_t convert_table_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t pack_table(int B, int kind, int prec, const double* T64, const int64_t* d_offs, void* dst,
+                      int64_t plane, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(64, B), dim3(256), 0, s, B, kind, prec, T64, d_offs, dst, plane);
   return hipGetLastError();
 }
 
