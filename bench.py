@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--dtype", default="split_bf16", choices=["split_bf16", "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and FP32 side runs")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -133,6 +135,16 @@ def main():
     from paper_1604_05140_amd import sgl, synth
 
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "launches": 3}), flush=True)
+        return
     B, nf = args.B, args.batch
     ns, nc = 8 * B ** 3, num_coeffs(B)
     print(f"[bench] B={B} batch={nf} form={args.dtype}: building inputs", file=sys.stderr, flush=True)

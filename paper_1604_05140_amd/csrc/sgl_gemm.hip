@@ -17,11 +17,13 @@
 //
 // Every contraction is a real table (M x K) times complex data (K x N complex
 // columns = 2N real columns).  One kernel template covers the four cases:
-//   * tile 128 x 128 real outputs, 4 waves of 64 x 64 (4 x 4 MFMA blocks of
-//     16 x 16); K in chunks of 32 through LDS, the next chunk prefetched into
-//     registers while the MFMAs of the current one run;
+//   * tile 128 x 128 real outputs, 8 waves of 64 x 32 (4 x 2 MFMA blocks of
+//     16 x 16); 128 rows cover a whole Legendre block at B <= 128, so the
+//     spectrum F is read from HBM once; K in chunks of 64 through LDS, with
+//     two register stages: the loads of chunk c+2 are issued before the MFMAs
+//     of chunk c, so each load has two MFMA phases to arrive;
 //   * the table operand comes pre-packed per direction (row-major, K padded to
-//     a multiple of 32 with zeros), so every table load is a 16-byte vector;
+//     a multiple of 64 with zeros), so every table load is a 16-byte vector;
 //   * data-operand loads follow the layout the previous stage wrote (16-byte
 //     runs along the contiguous index), are transposed in registers so that
 //     each lane holds 8 consecutive k of one column, and go to LDS as [column][k]
@@ -45,8 +47,8 @@ namespace {
 constexpr int BM = 128;      // rows per tile
 constexpr int BN = 128;      // real columns per tile
 constexpr int BNC = BN / 2;  // complex columns per tile
-constexpr int BK = 32;       // contraction chunk
-constexpr int NT = 256;      // 4 waves, 2 x 2 layout of 64 x 64
+constexpr int BK = 64;       // contraction chunk
+constexpr int NT = 512;      // 8 waves, 2 x 4 layout of 64 x 32
 constexpr int PS = BK + 8;   // bf16 LDS pitch (80 bytes)
 constexpr int PF = BK + 4;   // f32/f64 LDS pitch in elements
 constexpr int EP = BN + 1;   // epilogue tile pitch (elements)
@@ -99,64 +101,6 @@ struct Tile {
 
 __device__ inline int64_t gbase(int l, int nf, int L) { return (int64_t)l * l * nf * L; }
 
-// complex index of data-operand element (k, c)
-template <int KIND>
-__device__ inline int64_t x_index(const Tile& t, int k, int c) {
-  const ClassDesc& C = *t.C;
-  const int B = C.B, L = C.L, nf = C.nf;
-  if constexpr (KIND == K_B_FWD) {
-    const int ncf = nf * L;
-    const int seg = c >= ncf;
-    const int cp = c - seg * ncf;
-    const int mp = seg ? -t.q : t.q;
-    return ((int64_t)(mp + B - 1) * L + k) * ncf + cp;
-  } else if constexpr (KIND == K_B_INV) {
-    const int ncf = nf * L;
-    const int seg = c >= ncf;
-    const int cp = c - seg * ncf;
-    const int mp = seg ? -t.q : t.q;
-    const int l = t.q + k;
-    const int b = cp / L, i = cp - b * L;
-    return gbase(l, nf, L) + ((int64_t)b * (2 * l + 1) + mp + l) * L + i;
-  } else if constexpr (KIND == K_C_FWD) {
-    return gbase(t.q, nf, L) + (int64_t)c * L + k;
-  } else {  // K_C_INV: coefficient (n = l+1+k, l, m) of function b
-    const int l = t.q;
-    const int b = c / (2 * l + 1);
-    const int m = c - b * (2 * l + 1) - l;
-    return C.coff[b] + omega(l + 1 + k, l, m);
-  }
-}
-
-// complex index and sign of output element (row, c)
-template <int KIND>
-__device__ inline int64_t c_index(const Tile& t, int row, int c, int& sgn) {
-  const ClassDesc& C = *t.C;
-  const int B = C.B, L = C.L, nf = C.nf;
-  sgn = 1;
-  if constexpr (KIND == K_B_FWD || KIND == K_B_INV) {
-    const int ncf = nf * L;
-    const int seg = c >= ncf;
-    const int cp = c - seg * ncf;
-    const int mp = seg ? -t.q : t.q;
-    if (seg && (t.q & 1)) sgn = -1;
-    if constexpr (KIND == K_B_FWD) {
-      const int l = t.q + row;
-      const int b = cp / L, i = cp - b * L;
-      return gbase(l, nf, L) + ((int64_t)b * (2 * l + 1) + mp + l) * L + i;
-    } else {
-      return ((int64_t)(mp + B - 1) * L + row) * ncf + cp;
-    }
-  } else if constexpr (KIND == K_C_FWD) {
-    const int l = t.q;
-    const int b = c / (2 * l + 1);
-    const int m = c - b * (2 * l + 1) - l;
-    return C.coff[b] + omega(l + 1 + row, l, m);
-  } else {  // K_C_INV
-    return gbase(t.q, nf, L) + (int64_t)c * L + row;
-  }
-}
-
 // ---- per-thread register staging of one K chunk -----------------------------
 // A: split -> 6 x uint4 (3 planes x 2 vectors); f32 -> 4 x float4; f64 -> 8 x double2.
 // X: 8 consecutive k of one complex column -> 8 complex values.
@@ -170,11 +114,11 @@ template <int PREC> struct Stage {
 template <int PREC>
 __device__ inline void load_a(Stage<PREC>& st, const Tile& t, const void* tab, int64_t plane, int k0, int tid) {
   if constexpr (PREC == PREC_SPLIT) {
-    // 3 planes x 128 rows x 4 vectors of 8 bf16
+    // 3 planes x 128 rows x 8 vectors of 8 bf16
     for (int v = 0; v < 6; ++v) {
-      const int e = tid + v * NT;  // 0..1535
-      const int p = e / 512, rem = e - p * 512;
-      const int r = rem >> 2, kg = rem & 3;
+      const int e = tid + v * NT;  // 0..3071
+      const int p = e >> 10, rem = e & 1023;
+      const int r = rem >> 3, kg = rem & 7;
       const int gr = t.row0 + r;
       uint4 z = make_uint4(0, 0, 0, 0);
       if (gr < t.M)
@@ -184,8 +128,8 @@ __device__ inline void load_a(Stage<PREC>& st, const Tile& t, const void* tab, i
     }
   } else if constexpr (PREC == PREC_F32) {
     for (int v = 0; v < 4; ++v) {
-      const int e = tid + v * NT;  // 128 rows x 8 vectors of 4 floats
-      const int r = e >> 3, kg = e & 7;
+      const int e = tid + v * NT;  // 128 rows x 16 vectors of 4 floats
+      const int r = e >> 4, kg = e & 15;
       const int gr = t.row0 + r;
       uint4 z = make_uint4(0, 0, 0, 0);
       if (gr < t.M)
@@ -194,8 +138,8 @@ __device__ inline void load_a(Stage<PREC>& st, const Tile& t, const void* tab, i
     }
   } else {
     for (int v = 0; v < 8; ++v) {
-      const int e = tid + v * NT;  // 128 rows x 16 vectors of 2 doubles
-      const int r = e >> 4, kg = e & 15;
+      const int e = tid + v * NT;  // 128 rows x 32 vectors of 2 doubles
+      const int r = e >> 5, kg = e & 31;
       const int gr = t.row0 + r;
       uint4 z = make_uint4(0, 0, 0, 0);
       if (gr < t.M)
@@ -211,31 +155,91 @@ __device__ inline void store_a(const Stage<PREC>& st, unsigned char* sm, int tid
     uint16_t* As = reinterpret_cast<uint16_t*>(sm);
     for (int v = 0; v < 6; ++v) {
       const int e = tid + v * NT;
-      const int p = e / 512, rem = e - p * 512;
-      const int r = rem >> 2, kg = rem & 3;
+      const int p = e >> 10, rem = e & 1023;
+      const int r = rem >> 3, kg = rem & 7;
       *reinterpret_cast<uint4*>(&As[(p * BM + r) * PS + kg * 8]) = st.a[v];
     }
   } else if constexpr (PREC == PREC_F32) {
     float* As = reinterpret_cast<float*>(sm);
     for (int v = 0; v < 4; ++v) {
       const int e = tid + v * NT;
-      const int r = e >> 3, kg = e & 7;
+      const int r = e >> 4, kg = e & 15;
       *reinterpret_cast<uint4*>(&As[r * PF + kg * 4]) = st.a[v];
     }
   } else {
     double* As = reinterpret_cast<double*>(sm);
     for (int v = 0; v < 8; ++v) {
       const int e = tid + v * NT;
-      const int r = e >> 4, kg = e & 15;
+      const int r = e >> 5, kg = e & 31;
       *reinterpret_cast<uint4*>(&As[r * PF + kg * 2]) = st.a[v];
     }
   }
 }
 
+// Per-thread decode of one data-operand column, done once per tile: the complex
+// index of element (k, c) is then a cheap function of k.
+struct XCol {
+  int64_t base;  // index at k = 0 (linear kinds) or the constant term
+  int64_t s1;    // linear coefficient
+  int64_t s2;    // quadratic coefficient (stage-b inverse)
+  int ok;        // column inside the group
+};
+
+template <int KIND>
+__device__ inline XCol x_col(const Tile& t, int c) {
+  XCol x{0, 0, 0, c < t.Ncc};
+  if constexpr (KIND != K_DEBUG) {
+    if (!x.ok) return x;
+    const ClassDesc& C = *t.C;
+    const int B = C.B, L = C.L, nf = C.nf;
+    if constexpr (KIND == K_B_FWD) {
+      const int ncf = nf * L;
+      const int seg = c >= ncf;
+      const int cp = c - seg * ncf;
+      const int mp = seg ? -t.q : t.q;
+      x.base = (int64_t)(mp + B - 1) * L * ncf + cp;  // + k * ncf
+      x.s1 = ncf;
+    } else if constexpr (KIND == K_B_INV) {
+      // element (k, c) sits at g[l][b][mp+l][i], l = q + k:
+      //   l^2 nf L + (2b+1) L l + (b+mp) L + i
+      const int ncf = nf * L;
+      const int seg = c >= ncf;
+      const int cp = c - seg * ncf;
+      const int mp = seg ? -t.q : t.q;
+      const int b = cp / L, i = cp - b * L;
+      x.s2 = (int64_t)nf * L;
+      x.s1 = (int64_t)(2 * b + 1) * L;
+      x.base = (int64_t)(b + mp) * L + i;
+    } else if constexpr (KIND == K_C_FWD) {
+      x.base = gbase(t.q, nf, L) + (int64_t)c * L;  // + k
+      x.s1 = 1;
+    } else {  // K_C_INV: coefficient (n = q+1+k, q, m) of function b
+      const int l = t.q;
+      const int b = c / (2 * l + 1);
+      const int m = c - b * (2 * l + 1) - l;
+      x.base = C.coff[b] + (int64_t)l * (l + 1) + m;  // + omega(n, 0, 0)
+    }
+  }
+  return x;
+}
+
+template <int KIND>
+__device__ inline int64_t x_at(const Tile& t, const XCol& x, int k) {
+  if constexpr (KIND == K_B_INV) {
+    const int64_t l = t.q + k;
+    return x.base + l * (x.s1 + l * x.s2);
+  } else if constexpr (KIND == K_C_INV) {
+    const int64_t n = t.q + 1 + k;
+    return x.base + n * (n - 1) * (2 * n - 1) / 6;
+  } else {
+    return x.base + (int64_t)k * x.s1;
+  }
+}
+
 // X chunk: thread -> (complex column cc = tid & 63, k group kg = tid >> 6 of 8 rows)
 template <int PREC, int KIND>
-__device__ inline void load_x(Stage<PREC>& st, const Tile& t, const void* xbase, const DebugArgs& dbg, int k0,
-                              int tid) {
+__device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol& xc, const void* xbase,
+                              const DebugArgs& dbg, int k0, int tid) {
   using T = typename DT<PREC>::t;
   const int cc = tid & 63, kg = tid >> 6;
   const int c = t.col0 + cc;
@@ -250,10 +254,10 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const void* xbase,
     }
   } else {
     const T* X = reinterpret_cast<const T*>(xbase);
-    if (c < t.Ncc) {
+    if (xc.ok) {
       if constexpr (KIND == K_C_FWD) {
         // 8 consecutive k of one column are contiguous (g rows run along i)
-        const int64_t ix = x_index<KIND>(t, kb, c);
+        const int64_t ix = x_at<KIND>(t, xc, kb);
         for (int u = 0; u < 8; ++u) {
           const bool ok = kb + u < t.K;
           st.xr[u] = ok ? X[2 * (ix + u)] : (T)0;
@@ -263,7 +267,7 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const void* xbase,
         for (int u = 0; u < 8; ++u) {
           const int k = kb + u;
           if (k < t.K) {
-            const int64_t ix = x_index<KIND>(t, k, c);
+            const int64_t ix = x_at<KIND>(t, xc, k);
             st.xr[u] = X[2 * ix];
             st.xi[u] = X[2 * ix + 1];
           } else {
@@ -281,40 +285,51 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const void* xbase,
   }
 }
 
+// Exact three-piece bf16 split of an FP32 value by truncation: x0 keeps the top
+// 8 significand bits, x1 the next 8 of the (exact) remainder, and the last
+// remainder has at most 8 significant bits, so x = x0 + x1 + x2 exactly.  The
+// pieces are returned as FP32 bit patterns whose low halves are zero.
+__device__ inline void split3(float v, uint32_t& h0, uint32_t& h1, uint32_t& h2) {
+  h0 = __float_as_uint(v) & 0xFFFF0000u;
+  const float r1 = v - __uint_as_float(h0);
+  h1 = __float_as_uint(r1) & 0xFFFF0000u;
+  h2 = __float_as_uint(r1 - __uint_as_float(h1));
+}
+// pack the high halves of two FP32 patterns into one dword (lo element first)
+__device__ inline uint32_t pack_hi(uint32_t lo, uint32_t hi) { return __builtin_amdgcn_perm(hi, lo, 0x07060302u); }
+
 template <int PREC>
 __device__ inline void store_x(const Stage<PREC>& st, unsigned char* sm, int tid) {
   const int cc = tid & 63, kg = tid >> 6;
   if constexpr (PREC == PREC_SPLIT) {
     uint16_t* Xs = reinterpret_cast<uint16_t*>(sm + Lds<PREC>::a);
-    uint16_t h[2][3][8];
-    for (int u = 0; u < 8; ++u) {
-      const float v2[2] = {st.xr[u], st.xi[u]};
-      for (int part = 0; part < 2; ++part) {
-        const float v = v2[part];
-        const uint16_t h0 = f2bf(v);
-        const float r1 = v - bf2f(h0);
-        const uint16_t h1 = f2bf(r1);
-        const float r2 = r1 - bf2f(h1);
-        h[part][0][u] = h0;
-        h[part][1][u] = h1;
-        h[part][2][u] = f2bf(r2);
-      }
-    }
-    for (int part = 0; part < 2; ++part)
+    for (int part = 0; part < 2; ++part) {
+      uint32_t h[3][8];
+      for (int u = 0; u < 8; ++u) split3(part ? st.xi[u] : st.xr[u], h[0][u], h[1][u], h[2][u]);
       for (int p = 0; p < 3; ++p) {
         uint4 w;
-        w.x = (uint32_t)h[part][p][0] | ((uint32_t)h[part][p][1] << 16);
-        w.y = (uint32_t)h[part][p][2] | ((uint32_t)h[part][p][3] << 16);
-        w.z = (uint32_t)h[part][p][4] | ((uint32_t)h[part][p][5] << 16);
-        w.w = (uint32_t)h[part][p][6] | ((uint32_t)h[part][p][7] << 16);
+        w.x = pack_hi(h[p][0], h[p][1]);
+        w.y = pack_hi(h[p][2], h[p][3]);
+        w.z = pack_hi(h[p][4], h[p][5]);
+        w.w = pack_hi(h[p][6], h[p][7]);
         *reinterpret_cast<uint4*>(&Xs[(p * BN + 2 * cc + part) * PS + kg * 8]) = w;
       }
+    }
+  } else if constexpr (PREC == PREC_F32) {
+    float* Xs = reinterpret_cast<float*>(sm + Lds<PREC>::a);
+    float* r0 = &Xs[(2 * cc) * PF + kg * 8];
+    float* r1 = &Xs[(2 * cc + 1) * PF + kg * 8];
+    *reinterpret_cast<float4*>(r0) = make_float4(st.xr[0], st.xr[1], st.xr[2], st.xr[3]);
+    *reinterpret_cast<float4*>(r0 + 4) = make_float4(st.xr[4], st.xr[5], st.xr[6], st.xr[7]);
+    *reinterpret_cast<float4*>(r1) = make_float4(st.xi[0], st.xi[1], st.xi[2], st.xi[3]);
+    *reinterpret_cast<float4*>(r1 + 4) = make_float4(st.xi[4], st.xi[5], st.xi[6], st.xi[7]);
   } else {
-    using T = typename DT<PREC>::t;
-    T* Xs = reinterpret_cast<T*>(sm + Lds<PREC>::a);
-    for (int u = 0; u < 8; ++u) {
-      Xs[(2 * cc) * PF + kg * 8 + u] = st.xr[u];
-      Xs[(2 * cc + 1) * PF + kg * 8 + u] = st.xi[u];
+    double* Xs = reinterpret_cast<double*>(sm + Lds<PREC>::a);
+    double* r0 = &Xs[(2 * cc) * PF + kg * 8];
+    double* r1 = &Xs[(2 * cc + 1) * PF + kg * 8];
+    for (int u = 0; u < 8; u += 2) {
+      *reinterpret_cast<double2*>(r0 + u) = make_double2(st.xr[u], st.xr[u + 1]);
+      *reinterpret_cast<double2*>(r1 + u) = make_double2(st.xi[u], st.xi[u + 1]);
     }
   }
 }
@@ -329,7 +344,7 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
   __shared__ __align__(16) unsigned char sm[Lds<PREC>::total];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;
   const int lr = lane & 15, lk = lane >> 4;
 
   const int nitems = KIND == K_DEBUG ? ((dbg.M + BM - 1) / BM) * ((dbg.N + BN - 1) / BN) : nwork;
@@ -371,9 +386,9 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
       xbase = KIND == K_B_FWD ? C.F : (KIND == K_C_INV ? cin : C.g);
     }
 
-    AccT acc[4][4], acc2[4][4];
+    AccT acc[4][2], acc2[4][2];
     for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < 2; ++b)
         for (int v = 0; v < 4; ++v) {
           acc[a][b][v] = 0;
           if constexpr (PREC == PREC_SPLIT) acc2[a][b][v] = 0;
@@ -384,20 +399,11 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
       const int rleft = t.M - (t.row0 + wr);
       nbi = rleft <= 0 ? 0 : (rleft >= 64 ? 4 : (rleft + 15) / 16);
       const int cleft = 2 * t.Ncc - (2 * t.col0 + wc);
-      nbj = cleft <= 0 ? 0 : (cleft >= 64 ? 4 : (cleft + 15) / 16);
+      nbj = cleft <= 0 ? 0 : (cleft >= 32 ? 2 : (cleft + 15) / 16);
     }
 
-    Stage<PREC> st;
-    if constexpr (KIND == K_DEBUG) {
-      // debug: A straight from FP64 row-major [M][K]
-      for (int v = 0; v < Stage<PREC>::NA; ++v) st.a[v] = make_uint4(0, 0, 0, 0);
-    } else {
-      load_a<PREC>(st, t, tab, plane, 0, tid);
-    }
-    load_x<PREC, KIND>(st, t, xbase, dbg, 0, tid);
-
-    for (int k0 = 0; k0 < t.K; k0 += BK) {
-      __syncthreads();  // previous chunk's MFMAs are done with LDS
+    // stage one chunk into LDS: A (table or debug matrix) and X
+    auto to_lds = [&](const Stage<PREC>& st, int k0) {
       if constexpr (KIND == K_DEBUG) {
         for (int e = tid; e < BM * BK; e += NT) {
           const int r = e / BK, k = e - r * BK;
@@ -419,46 +425,52 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
         store_a<PREC>(st, sm, tid);
       }
       store_x<PREC>(st, sm, tid);
-      __syncthreads();
-      if (k0 + BK < t.K) {  // prefetch the next chunk while the MFMAs run
-        if constexpr (KIND != K_DEBUG) load_a<PREC>(st, t, tab, plane, k0 + BK, tid);
-        load_x<PREC, KIND>(st, t, xbase, dbg, k0 + BK, tid);
-      }
+    };
+    const XCol xc = x_col<KIND>(t, t.col0 + (tid & 63));
+    auto fetch = [&](Stage<PREC>& st, int k0) {
+      if constexpr (KIND != K_DEBUG) load_a<PREC>(st, t, tab, plane, k0, tid);
+      load_x<PREC, KIND>(st, t, xc, xbase, dbg, k0, tid);
+    };
+    // MFMAs of the chunk in LDS; k sub-steps wholly beyond K are skipped
+    auto compute = [&](int k0) {
+      const int kend = t.K - k0 < BK ? t.K - k0 : BK;
       if constexpr (PREC == PREC_SPLIT) {
         const uint16_t* As = reinterpret_cast<const uint16_t*>(sm);
         const uint16_t* Xs = reinterpret_cast<const uint16_t*>(sm + Lds<PREC>::a);
-        bf8 b[4][3];
-        for (int j = 0; j < 4; ++j)
-          if (j < nbj)
+        for (int kk = 0; kk < BK; kk += 32) {
+          if (kk >= kend) break;
+          bf8 b[2][3];
+          for (int j = 0; j < 2; ++j)
+            if (j < nbj)
+              for (int p = 0; p < 3; ++p)
+                b[j][p] = *reinterpret_cast<const bf8*>(&Xs[(p * BN + wc + j * 16 + lr) * PS + kk + 8 * lk]);
+          for (int i = 0; i < 4; ++i) {
+            if (i >= nbi) continue;
+            bf8 a[3];
             for (int p = 0; p < 3; ++p)
-              b[j][p] = *reinterpret_cast<const bf8*>(&Xs[(p * BN + wc + j * 16 + lr) * PS + 8 * lk]);
-        for (int i = 0; i < 4; ++i) {
-          if (i >= nbi) continue;
-          bf8 a[3];
-          for (int p = 0; p < 3; ++p)
-            a[p] = *reinterpret_cast<const bf8*>(&As[(p * BM + wr + i * 16 + lr) * PS + 8 * lk]);
-          for (int j = 0; j < 4; ++j) {
-            if (j >= nbj) continue;
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][1], acc2[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][0], acc2[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][2], acc2[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][1], acc2[i][j], 0, 0, 0);
-            acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][0], acc2[i][j], 0, 0, 0);
+              a[p] = *reinterpret_cast<const bf8*>(&As[(p * BM + wr + i * 16 + lr) * PS + kk + 8 * lk]);
+            for (int j = 0; j < 2; ++j) {
+              if (j >= nbj) continue;
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc[i][j], 0, 0, 0);
+              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][1], acc2[i][j], 0, 0, 0);
+              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][0], acc2[i][j], 0, 0, 0);
+              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][2], acc2[i][j], 0, 0, 0);
+              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][1], acc2[i][j], 0, 0, 0);
+              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][0], acc2[i][j], 0, 0, 0);
+            }
           }
         }
       } else {
         const T* As = reinterpret_cast<const T*>(sm);
         const T* Xs = reinterpret_cast<const T*>(sm + Lds<PREC>::a);
         for (int kk = 0; kk < BK; kk += 4) {
-          T a[4], b[4];
-          for (int i = 0; i < 4; ++i) {
-            a[i] = As[(wr + i * 16 + lr) * PF + kk + lk];
-            b[i] = Xs[(wc + i * 16 + lr) * PF + kk + lk];
-          }
+          if (kk >= kend) break;
+          T a[4], b[2];
+          for (int i = 0; i < 4; ++i) a[i] = As[(wr + i * 16 + lr) * PF + kk + lk];
+          for (int j = 0; j < 2; ++j) b[j] = Xs[(wc + j * 16 + lr) * PF + kk + lk];
           for (int i = 0; i < 4; ++i) {
             if (i >= nbi) continue;
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 2; ++j) {
               if (j >= nbj) continue;
               if constexpr (PREC == PREC_F64)
                 acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
@@ -468,6 +480,26 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
           }
         }
       }
+    };
+
+    Stage<PREC> s0, s1;
+    if constexpr (KIND == K_DEBUG) {
+      for (int v = 0; v < Stage<PREC>::NA; ++v) s0.a[v] = s1.a[v] = make_uint4(0, 0, 0, 0);
+    }
+    fetch(s0, 0);
+    if (BK < t.K) fetch(s1, BK);
+    for (int k0 = 0; k0 < t.K; k0 += 2 * BK) {
+      __syncthreads();  // the previous chunk's MFMAs are done with LDS
+      to_lds(s0, k0);
+      __syncthreads();
+      if (k0 + 2 * BK < t.K) fetch(s0, k0 + 2 * BK);
+      compute(k0);
+      if (k0 + BK >= t.K) break;
+      __syncthreads();
+      to_lds(s1, k0 + BK);
+      __syncthreads();
+      if (k0 + 3 * BK < t.K) fetch(s1, k0 + 3 * BK);
+      compute(k0 + BK);
     }
 
     // ---- epilogue through LDS, one 64-row half at a time.  Lane layout of a
@@ -479,7 +511,7 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
       __syncthreads();
       if (wr == half * 64) {
         for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < 2; ++j)
             for (int v = 0; v < 4; ++v) {
               const int rin = PREC == PREC_F64 ? 4 * v + lk : 4 * lk + v;
               T val;
@@ -499,57 +531,77 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
           if (row < t.M && nr < dbg.N) dbg.C[(int64_t)row * dbg.N + nr] = (double)E[r * EP + n];
         }
       } else if constexpr (KIND == K_C_INV) {
-        // column-major output (g rows run along i = tile row): pairs of rows
+        // column-major output (g rows run along i = tile row): pairs of rows;
+        // the output index of (row, c) is the stage-c forward operand index
         T* out = reinterpret_cast<T*>(t.C->g);
-        for (int e = tid; e < 32 * BNC; e += NT) {
-          const int cc = e >> 5, rp = (e & 31) * 2;
-          const int c = t.col0 + cc, row = rbase + rp;
-          if (c >= t.Ncc || row >= t.M) continue;
-          int sg;
-          const int64_t ix = c_index<KIND>(t, row, c, sg);
-          const T r0 = E[rp * EP + 2 * cc], i0 = E[rp * EP + 2 * cc + 1];
-          if (row + 1 < t.M) {
-            const T r1 = E[(rp + 1) * EP + 2 * cc], i1 = E[(rp + 1) * EP + 2 * cc + 1];
-            if constexpr (PREC == PREC_F64) {
-              reinterpret_cast<double2*>(out)[ix] = make_double2(r0, i0);
-              reinterpret_cast<double2*>(out)[ix + 1] = make_double2(r1, i1);
+        const int cc = tid >> 3;            // 64 columns, 8 threads each
+        const int c = t.col0 + cc;
+        const XCol oc = x_col<K_C_FWD>(t, c);
+        if (oc.ok) {
+          for (int rp = (tid & 7) * 2; rp < 64; rp += 16) {
+            const int row = rbase + rp;
+            if (row >= t.M) break;
+            const int64_t ix = x_at<K_C_FWD>(t, oc, row);
+            const T r0 = E[rp * EP + 2 * cc], i0 = E[rp * EP + 2 * cc + 1];
+            if (row + 1 < t.M) {
+              const T r1 = E[(rp + 1) * EP + 2 * cc], i1 = E[(rp + 1) * EP + 2 * cc + 1];
+              if constexpr (PREC == PREC_F64) {
+                reinterpret_cast<double2*>(out)[ix] = make_double2(r0, i0);
+                reinterpret_cast<double2*>(out)[ix + 1] = make_double2(r1, i1);
+              } else {
+                *reinterpret_cast<float4*>(out + 2 * ix) = make_float4(r0, i0, r1, i1);
+              }
             } else {
-              *reinterpret_cast<float4*>(out + 2 * ix) = make_float4(r0, i0, r1, i1);
+              out[2 * ix] = r0;
+              out[2 * ix + 1] = i0;
             }
-          } else {
-            out[2 * ix] = r0;
-            out[2 * ix + 1] = i0;
           }
         }
       } else {
-        // row-major outputs: pairs of consecutive complex columns of one row
+        // row-major outputs: each thread owns a pair of consecutive complex
+        // columns (decoded once) and walks rows.  The output index of (row, c)
+        // is the operand index of the opposite direction: stage-b forward
+        // writes where stage-b inverse reads, and so on.
+        constexpr int DUAL = KIND ^ 1;
         T* out = reinterpret_cast<T*>(KIND == K_B_FWD ? t.C->g : (KIND == K_B_INV ? t.C->F : cout));
-        for (int e = tid; e < 64 * (BNC / 2); e += NT) {
-          const int r = e >> 5, cp = (e & 31) * 2;
-          const int row = rbase + r, c = t.col0 + cp;
-          if (row >= t.M || c >= t.Ncc) continue;
-          int s0, s1 = 1;
-          const int64_t i0 = c_index<KIND>(t, row, c, s0);
-          T re0 = E[r * EP + 2 * cp], im0 = E[r * EP + 2 * cp + 1];
-          if (s0 < 0) { re0 = -re0; im0 = -im0; }
-          if (c + 1 < t.Ncc) {
-            const int64_t i1 = c_index<KIND>(t, row, c + 1, s1);
-            T re1 = E[r * EP + 2 * cp + 2], im1 = E[r * EP + 2 * cp + 3];
-            if (s1 < 0) { re1 = -re1; im1 = -im1; }
-            if constexpr (PREC != PREC_F64) {
-              if (i1 == i0 + 1 && ((reinterpret_cast<uintptr_t>(out + 2 * i0) & 15) == 0)) {
-                *reinterpret_cast<float4*>(out + 2 * i0) = make_float4(re0, im0, re1, im1);
-                continue;
+        const int cp = (tid & 31) * 2;
+        const int c = t.col0 + cp;
+        const XCol o0 = x_col<DUAL>(t, c);
+        const XCol o1 = x_col<DUAL>(t, c + 1);
+        T s0 = 1, s1 = 1;
+        if constexpr (KIND == K_B_FWD || KIND == K_B_INV) {
+          const int ncf = t.C->nf * t.C->L;
+          if ((t.q & 1) && c >= ncf) s0 = -1;
+          if ((t.q & 1) && c + 1 >= ncf) s1 = -1;
+        }
+        if (o0.ok) {
+          for (int r = tid >> 5; r < 64; r += NT / 32) {
+            const int row = rbase + r;
+            if (row >= t.M) break;
+            const int64_t i0 = x_at<DUAL>(t, o0, row);
+            const T re0 = s0 * E[r * EP + 2 * cp], im0 = s0 * E[r * EP + 2 * cp + 1];
+            if (o1.ok) {
+              const int64_t i1 = x_at<DUAL>(t, o1, row);
+              const T re1 = s1 * E[r * EP + 2 * cp + 2], im1 = s1 * E[r * EP + 2 * cp + 3];
+              if constexpr (PREC != PREC_F64) {
+                if (i1 == i0 + 1 && ((reinterpret_cast<uintptr_t>(out + 2 * i0) & 15) == 0)) {
+                  *reinterpret_cast<float4*>(out + 2 * i0) = make_float4(re0, im0, re1, im1);
+                  continue;
+                }
+              }
+              if constexpr (PREC == PREC_F64) {
+                reinterpret_cast<double2*>(out)[i1] = make_double2(re1, im1);
+              } else {
+                out[2 * i1] = re1;
+                out[2 * i1 + 1] = im1;
               }
             }
-            out[2 * i1] = re1;
-            out[2 * i1 + 1] = im1;
-          }
-          if constexpr (PREC == PREC_F64) {
-            reinterpret_cast<double2*>(out)[i0] = make_double2(re0, im0);
-          } else {
-            out[2 * i0] = re0;
-            out[2 * i0 + 1] = im0;
+            if constexpr (PREC == PREC_F64) {
+              reinterpret_cast<double2*>(out)[i0] = make_double2(re0, im0);
+            } else {
+              out[2 * i0] = re0;
+              out[2 * i0 + 1] = im0;
+            }
           }
         }
       }

@@ -57,7 +57,7 @@ struct ClassDesc {
   // 0 Legendre forward (rows l, k = j), 1 Legendre inverse (rows j, k = l),
   // 2 radial forward (rows n, k = i), 3 radial inverse (rows i, k = n).
   // Block q (order m or degree l) is row-major with the contraction length
-  // padded to a multiple of 32 (zeros); split tables hold 3 bf16 planes of
+  // padded to a multiple of the GEMM K chunk (zeros); split tables hold 3 bf16 planes of
   // Aplane elements each.
   const void* A[4];
   const int64_t* Aoff[4];  // element offset of block q

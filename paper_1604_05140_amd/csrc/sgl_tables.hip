@@ -368,13 +368,13 @@ __global__ void k_to_split(const double* src, uint16_t* dst, int64_t n) {
 
 // Packed GEMM operand from a natural FP64 table (see ClassDesc::A).
 __global__ void k_pack(int B, int kind, int prec, const double* T64, const int64_t* offs, void* dst,
-                       int64_t plane) {
+                       int64_t plane, int kchunk) {
   const int q = blockIdx.y;
   const bool fwd = kind == 0 || kind == 2;
   const int L = 2 * B;
   const int rows = fwd ? B - q : L;
   const int K = fwd ? L : B - q;
-  const int pitch = (K + 31) / 32 * 32;
+  const int pitch = (K + kchunk - 1) / kchunk * kchunk;
   const double* src = T64 + table_block(B, q);
   const int64_t base = offs[q];
   const int64_t n = (int64_t)rows * pitch;
@@ -494,7 +494,7 @@ hipError_t convert_table_f32(const double* src, float* dst, int64_t n, hipStream
 
 hipError_t pack_table(int B, int kind, int prec, const double* T64, const int64_t* d_offs, void* dst,
                       int64_t plane, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack, dim3(64, B), dim3(256), 0, s, B, kind, prec, T64, d_offs, dst, plane);
+  hipLaunchKernelGGL(k_pack, dim3(64, B), dim3(256), 0, s, B, kind, prec, T64, d_offs, dst, plane, gemm_k_chunk());
   return hipGetLastError();
 }
 
