@@ -166,12 +166,12 @@ __device__ inline void dft_reg(T2 (&v)[R]) {
 
 template <typename T, int R1, int R2, bool RAW>
 __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int rpb,
-                                const typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds) {
+                                const typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds,
+                                const typename C2<T>::t* tw) {
   using T2 = typename C2<T>::t;
   constexpr int L = R1 * R2, B = L / 2;
   const int t = threadIdx.x;
   const int P = rpb + 1;
-  const T2* tw = reinterpret_cast<const T2*>(C.tw);
   if (t < rpb * R2) {
     const int r = t / R2, n2 = t % R2;
     if (r < nr) {
@@ -225,12 +225,12 @@ __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int
 
 template <typename T, int R1, int R2, bool RAW>
 __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int rpb,
-                                typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds) {
+                                typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds,
+                                const typename C2<T>::t* tw) {
   using T2 = typename C2<T>::t;
   constexpr int L = R1 * R2, B = L / 2;
   const int t = threadIdx.x;
   const int P = rpb + 1;
-  const T2* tw = reinterpret_cast<const T2*>(C.tw);
   if (t < rpb * R1) {
     const int r = t % rpb, k1 = t / rpb;
     if (r < nr) {
@@ -282,13 +282,14 @@ __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int
   __syncthreads();
 }
 
-template <typename T, bool RAW>
+template <typename T, bool RAW, bool BIG>
 __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                                      int nwork, const void* __restrict__ samples_v) {
   using T2 = typename C2<T>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* smem = reinterpret_cast<T2*>(smem_raw);
   const T2* samples = reinterpret_cast<const T2*>(samples_v);
+  int tw_cls = -1;  // class whose twiddles sit in LDS (block-uniform)
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int4 it = work[w];
     const ClassDesc& C = cls[it.x];
@@ -297,14 +298,26 @@ __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict
     const int rpb = it.w;
     const int col0 = it.z * rpb;
     const int nr = min(rpb, ncol - col0);
-    switch (L) {
-      case 16: fwd_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 32: fwd_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 64: fwd_pow2<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 128: fwd_pow2<T, 16, 8, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 256: fwd_pow2<T, 16, 16, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 512: fwd_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      default: break;
+    if (fft_pow2_path(L)) {
+      T2* twl = smem + L * (rpb + 1);
+      if (it.x != tw_cls) {
+        const T2* tw = reinterpret_cast<const T2*>(C.tw);
+        for (int q = threadIdx.x; q < L; q += blockDim.x) twl[q] = tw[q];
+        __syncthreads();
+        tw_cls = it.x;
+      }
+      if constexpr (BIG) {
+        fwd_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, twl);
+      } else {
+        switch (L) {
+          case 16: fwd_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+          case 32: fwd_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+          case 64: fwd_pow2<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+          case 128: fwd_pow2<T, 16, 8, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+          default: fwd_pow2<T, 16, 16, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+        }
+      }
+      continue;
     }
     T2* buf0 = smem;
     T2* buf1 = smem + rpb * L;
@@ -350,13 +363,14 @@ __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict
   }
 }
 
-template <typename T, bool RAW>
+template <typename T, bool RAW, bool BIG>
 __global__ void __launch_bounds__(256) k_fft_inverse(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                                      int nwork, void* __restrict__ samples_v) {
   using T2 = typename C2<T>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* smem = reinterpret_cast<T2*>(smem_raw);
   T2* samples = reinterpret_cast<T2*>(samples_v);
+  int tw_cls = -1;
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int4 it = work[w];
     const ClassDesc& C = cls[it.x];
@@ -365,14 +379,26 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const ClassDesc* __restrict
     const int rpb = it.w;
     const int col0 = it.z * rpb;
     const int nr = min(rpb, ncol - col0);
-    switch (L) {
-      case 16: inv_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 32: inv_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 64: inv_pow2<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 128: inv_pow2<T, 16, 8, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 256: inv_pow2<T, 16, 16, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      case 512: inv_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem); continue;
-      default: break;
+    if (fft_pow2_path(L)) {
+      T2* twl = smem + L * (rpb + 1);
+      if (it.x != tw_cls) {
+        const T2* tw = reinterpret_cast<const T2*>(C.tw);
+        for (int q = threadIdx.x; q < L; q += blockDim.x) twl[q] = tw[q];
+        __syncthreads();
+        tw_cls = it.x;
+      }
+      if constexpr (BIG) {
+        inv_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, twl);
+      } else {
+        switch (L) {
+          case 16: inv_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+          case 32: inv_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+          case 64: inv_pow2<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+          case 128: inv_pow2<T, 16, 8, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+          default: inv_pow2<T, 16, 16, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
+        }
+      }
+      continue;
     }
     T2* buf0 = smem;
     T2* buf1 = smem + rpb * L;
@@ -428,7 +454,7 @@ inline int grid_for(int nwork) { return nwork < 4096 ? nwork : 4096; }
 // LDS bytes for rings_per_block rings of length L in the given precision
 static size_t fft_lds_bytes(int prec, int rpb, int L) {
   const size_t es = prec == PREC_F64 ? sizeof(double2) : sizeof(float2);
-  if (fft_pow2_path(L)) return (size_t)L * (rpb + 1) * es;
+  if (fft_pow2_path(L)) return (size_t)L * (rpb + 2) * es;  // exchange buffer + twiddle table
   return (size_t)2 * rpb * L * es;
 }
 
@@ -438,40 +464,56 @@ static void allow_lds(K kernel, int bytes) {
                                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, const void* samples, hipStream_t s) {
+template <bool BIG>
+static hipError_t fft_fwd(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork, int lds,
+                          const void* samples, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   dim3 grid(grid_for(nwork)), block(256);
-  allow_lds(k_fft_forward<double, true>, lds_bytes);
-  allow_lds(k_fft_forward<double, false>, lds_bytes);
-  allow_lds(k_fft_forward<float, false>, lds_bytes);
-  if (prec == PREC_F64) {
-    if (raw)
-      hipLaunchKernelGGL((k_fft_forward<double, true>), grid, block, lds_bytes, s, d_cls, d_work, nwork, samples);
-    else
-      hipLaunchKernelGGL((k_fft_forward<double, false>), grid, block, lds_bytes, s, d_cls, d_work, nwork, samples);
+  if (prec == PREC_F64 && raw) {
+    allow_lds(k_fft_forward<double, true, BIG>, lds);
+    hipLaunchKernelGGL((k_fft_forward<double, true, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
+  } else if (prec == PREC_F64) {
+    allow_lds(k_fft_forward<double, false, BIG>, lds);
+    hipLaunchKernelGGL((k_fft_forward<double, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   } else {
-    hipLaunchKernelGGL((k_fft_forward<float, false>), grid, block, lds_bytes, s, d_cls, d_work, nwork, samples);
+    allow_lds(k_fft_forward<float, false, BIG>, lds);
+    hipLaunchKernelGGL((k_fft_forward<float, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, void* samples, hipStream_t s) {
+template <bool BIG>
+static hipError_t fft_inv(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork, int lds,
+                          void* samples, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   dim3 grid(grid_for(nwork)), block(256);
-  allow_lds(k_fft_inverse<double, true>, lds_bytes);
-  allow_lds(k_fft_inverse<double, false>, lds_bytes);
-  allow_lds(k_fft_inverse<float, false>, lds_bytes);
-  if (prec == PREC_F64) {
-    if (raw)
-      hipLaunchKernelGGL((k_fft_inverse<double, true>), grid, block, lds_bytes, s, d_cls, d_work, nwork, samples);
-    else
-      hipLaunchKernelGGL((k_fft_inverse<double, false>), grid, block, lds_bytes, s, d_cls, d_work, nwork, samples);
+  if (prec == PREC_F64 && raw) {
+    allow_lds(k_fft_inverse<double, true, BIG>, lds);
+    hipLaunchKernelGGL((k_fft_inverse<double, true, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
+  } else if (prec == PREC_F64) {
+    allow_lds(k_fft_inverse<double, false, BIG>, lds);
+    hipLaunchKernelGGL((k_fft_inverse<double, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   } else {
-    hipLaunchKernelGGL((k_fft_inverse<float, false>), grid, block, lds_bytes, s, d_cls, d_work, nwork, samples);
+    allow_lds(k_fft_inverse<float, false, BIG>, lds);
+    hipLaunchKernelGGL((k_fft_inverse<float, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
+                              int lds_bytes, const int4* d_work_big, int nwork_big, int lds_big,
+                              const void* samples, hipStream_t s) {
+  hipError_t e = fft_fwd<false>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, s);
+  if (e != hipSuccess) return e;
+  return fft_fwd<true>(prec, raw, d_cls, d_work_big, nwork_big, lds_big, samples, s);
+}
+
+hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
+                              int lds_bytes, const int4* d_work_big, int nwork_big, int lds_big, void* samples,
+                              hipStream_t s) {
+  hipError_t e = fft_inv<false>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, s);
+  if (e != hipSuccess) return e;
+  return fft_inv<true>(prec, raw, d_cls, d_work_big, nwork_big, lds_big, samples, s);
 }
 
 size_t fft_lds_bytes_for(int prec, int rpb, int L) { return fft_lds_bytes(prec, rpb, L); }

@@ -76,14 +76,18 @@ enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_SPLIT = 2 };
 
 // Stage kernels (defined in sgl_fft.hip / sgl_gemm.hip)
 // stage (a) work items carry the rings per block in .w; lds_bytes = 2 * rpb * L * sizeof(complex)
+// Rings of length 512 (B = 256) run in a kernel of their own (d_work_big) so that
+// their register footprint does not lower the occupancy of the other lengths.
 hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, const void* samples, hipStream_t s);
+                              int lds_bytes, const int4* d_work_big, int nwork_big, int lds_big,
+                              const void* samples, hipStream_t s);
 hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, void* samples, hipStream_t s);
+                              int lds_bytes, const int4* d_work_big, int nwork_big, int lds_big, void* samples,
+                              hipStream_t s);
 size_t fft_lds_bytes_for(int prec, int rpb, int L);
 // power-of-two ring lengths 16..512 take the register four-step path; its rings
 // per block are 256 / R1 with L = R1 * R2, R1 = R2 or 2 R2.
-inline bool fft_pow2_path(int L) { return L >= 16 && L <= 512 && (L & (L - 1)) == 0; }
+__host__ __device__ inline bool fft_pow2_path(int L) { return L >= 16 && L <= 512 && (L & (L - 1)) == 0; }
 inline int fft_pow2_rpb(int L) {
   int r1 = 1;
   while (r1 * r1 < L) r1 <<= 1;  // R1 = sqrt(L) or sqrt(2L)

@@ -63,7 +63,8 @@ struct sgl_plan_s {
   ClassDesc* d_cls = nullptr;
   int4* d_work = nullptr;
   int off_a = 0, n_a = 0, off_bf = 0, n_bf = 0, off_bi = 0, n_bi = 0, off_cf = 0, n_cf = 0, off_ci = 0, n_ci = 0;
-  int lds_a = 0;
+  int off_a2 = 0, n_a2 = 0;  // stage (a) items of length-512 rings
+  int lds_a = 0, lds_a2 = 0;
   // timing
   bool timing = false;
   static constexpr int kRing = 64;
@@ -162,18 +163,20 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
 
 sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
   const int BM = gemm_tile_m(), BNC = gemm_tile_n_complex();
-  std::vector<int4> wa, wbf, wbi, wcf, wci;
+  std::vector<int4> wa, wa2, wbf, wbi, wcf, wci;
   struct Item { int cost; int4 w; };
   std::vector<Item> bf, bi, cf, ci;
-  int lds = 0;
+  int lds = 0, lds2 = 0;
   for (int ci_ = 0; ci_ < (int)p->classes.size(); ++ci_) {
     const ClassHost& c = p->classes[ci_];
     const int B = c.B, L = 2 * B, nf = (int)c.funcs.size();
     const int ncol = nf * L;
     const int ncb = (ncol + c.rpb - 1) / c.rpb;
+    std::vector<int4>& dst = L == 512 ? wa2 : wa;
     for (int j = 0; j < L; ++j)
-      for (int cb = 0; cb < ncb; ++cb) wa.push_back(make_int4(ci_, j, cb, c.rpb));
-    lds = std::max(lds, (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
+      for (int cb = 0; cb < ncb; ++cb) dst.push_back(make_int4(ci_, j, cb, c.rpb));
+    int& lmax = L == 512 ? lds2 : lds;
+    lmax = std::max(lmax, (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
     for (int m = 0; m < B; ++m) {
       const int rows = B - m;
       const int ncc = (m ? 2 : 1) * nf * L;
@@ -205,6 +208,7 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
   order(ci, wci);
   std::vector<int4> all;
   p->off_a = 0; p->n_a = (int)wa.size(); all.insert(all.end(), wa.begin(), wa.end());
+  p->off_a2 = (int)all.size(); p->n_a2 = (int)wa2.size(); all.insert(all.end(), wa2.begin(), wa2.end());
   p->off_bf = (int)all.size(); p->n_bf = (int)wbf.size(); all.insert(all.end(), wbf.begin(), wbf.end());
   p->off_bi = (int)all.size(); p->n_bi = (int)wbi.size(); all.insert(all.end(), wbi.begin(), wbi.end());
   p->off_cf = (int)all.size(); p->n_cf = (int)wcf.size(); all.insert(all.end(), wcf.begin(), wcf.end());
@@ -212,6 +216,7 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
   SGL_TRY(p->alloc((void**)&p->d_work, all.size() * sizeof(int4)));
   SGL_HIP_TRY(hipMemcpyAsync(p->d_work, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   p->lds_a = lds;
+  p->lds_a2 = lds2;
   return SGL_OK;
 }
 
@@ -380,7 +385,7 @@ sgl_status_t sgl_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs,
   const bool raw = (plan->flags & SGL_SAMPLES_RAW) != 0;
   time_begin(plan, 0, s);
   SGL_HIP_TRY(launch_fft_forward(prec, raw, plan->d_cls, plan->d_work + plan->off_a, plan->n_a, plan->lds_a,
-                                 d_samples, s));
+                                 plan->d_work + plan->off_a2, plan->n_a2, plan->lds_a2, d_samples, s));
   time_end(plan, 0, s);
   time_begin(plan, 1, s);
   SGL_HIP_TRY(launch_legendre(prec, false, plan->d_cls, plan->d_work + plan->off_bf, plan->n_bf, s));
@@ -405,7 +410,7 @@ sgl_status_t sgl_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples,
   time_end(plan, 4, s);
   time_begin(plan, 5, s);
   SGL_HIP_TRY(launch_fft_inverse(prec, raw, plan->d_cls, plan->d_work + plan->off_a, plan->n_a, plan->lds_a,
-                                 d_samples, s));
+                                 plan->d_work + plan->off_a2, plan->n_a2, plan->lds_a2, d_samples, s));
   time_end(plan, 5, s);
   return SGL_OK;
 }
