@@ -57,16 +57,7 @@ def stage_work(B, nf, dtype):
     }
 
 
-def run_form(sgl, torch, plan, c_in, s_in, steps, warmup):
-    dev = c_in.device
-    cout = torch.empty(plan.total_coeffs, dtype=plan.complex_dtype, device=dev)
-    sout = torch.empty(plan.total_samples, dtype=plan.complex_dtype, device=dev)
-    for _ in range(warmup):
-        sgl.sgl_forward(plan, s_in, cout)
-        sgl.sgl_inverse(plan, c_in, sout)
-    torch.cuda.synchronize()
-    plan.stage_times()  # reset
-    plan.set_timing(True)
+def time_steps(torch, sgl, plan, c_in, s_in, cout, sout, steps):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -76,11 +67,28 @@ def run_form(sgl, torch, plan, c_in, s_in, steps, warmup):
         sgl.sgl_inverse(plan, c_in, sout)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    return e0.elapsed_time(e1) / steps
+
+
+def run_form(sgl, torch, plan, c_in, s_in, steps, warmup, graph_steps=0):
+    """Timed region: `steps` forward+inverse pairs with per-stage HIP events
+    recorded on the launch stream.  With graph_steps > 0 (plan built with
+    SGL_GRAPHS) a second timed loop replays the captured graphs without events."""
+    dev = c_in.device
+    cout = torch.empty(plan.total_coeffs, dtype=plan.complex_dtype, device=dev)
+    sout = torch.empty(plan.total_samples, dtype=plan.complex_dtype, device=dev)
+    for _ in range(warmup):
+        sgl.sgl_forward(plan, s_in, cout)
+        sgl.sgl_inverse(plan, c_in, sout)
+    torch.cuda.synchronize()
+    plan.stage_times()  # reset
+    plan.set_timing(True)
+    ms = time_steps(torch, sgl, plan, c_in, s_in, cout, sout, steps)
     st_ms, st_cnt = plan.stage_times()
     plan.set_timing(False)
     per_stage = {STAGES[q]: (st_ms[q] / st_cnt[q] if st_cnt[q] else None) for q in range(6)}
-    return ms / steps, per_stage, cout, sout
+    graph_ms = time_steps(torch, sgl, plan, c_in, s_in, cout, sout, graph_steps) if graph_steps else None
+    return ms, per_stage, cout, sout, graph_ms
 
 
 def cpu_baseline(B, n_coef, n_pts, seed):
@@ -111,6 +119,37 @@ def cpu_baseline(B, n_coef, n_pts, seed):
     }
 
 
+def bench_batched(args, torch, sgl, synth, dev):
+    """256 functions with bandlimits uniform in {16..96}, one persistent launch per
+    stage over the (order, bandlimit) work list, autotuned grids, graph replay."""
+    dtype = "f32" if args.dtype == "split_bf16" and "--dtype" not in sys.argv else args.dtype
+    Bs = [int(b) for b in synth.batched_bandlimits(256, 16, 96, seed=synth.BASE_SEED + 4)]
+    print(f"[bench] batched: 256 functions, form {dtype}", file=sys.stderr, flush=True)
+    plan = sgl.sgl_plan_ex(Bs, dtype, sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS)
+    ct = plan.complex_dtype
+    cs = [synth.complex_normal_coeffs(B, 1, seed=synth.BASE_SEED + 4000 + q, decay=1.0)[0] for q, B in enumerate(Bs)]
+    import numpy as np
+    c_in = torch.from_numpy(np.concatenate(cs)).to(dev, ct)
+    s_in = torch.empty(plan.total_samples, dtype=ct, device=dev)
+    sgl.sgl_inverse(plan, c_in, s_in)
+    ms, per_stage, _, _, graph_ms = run_form(sgl, torch, plan, c_in, s_in, args.steps, args.warmup,
+                                             graph_steps=args.steps)
+    out = {
+        "metric": "SGL fwd+inv transforms/s, 256 functions with B uniform in {16..96} (batched form)",
+        "value": 256 * 1000.0 / ms,
+        "unit": "transforms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"split_bf16": "bf16x3 (fp32 accumulate)", "f32": "f32", "f64": "f64"}[dtype],
+        "data": "synthetic",
+        "config": {"workload": "SGL forward+inverse, 256 functions, B uniform in {16..96}, complex-normal/n "
+                               "coefficients", "form": dtype, "total_coeffs": plan.total_coeffs,
+                   "total_samples": plan.total_samples},
+        "stage_ms": per_stage, "graph_ms_per_step": graph_ms, "launch_grids": plan.launch_grids(),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +160,8 @@ def main():
     ap.add_argument("--dtype", default="split_bf16", choices=["split_bf16", "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and FP32 side runs")
+    ap.add_argument("--workload", default="b128", choices=["b128", "batched"],
+                    help="b128: B=128 batch 4 (headline); batched: 256 functions, B uniform in {16..96}")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -145,6 +186,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n, "launches": 3}), flush=True)
         return
+    if args.workload == "batched":
+        return bench_batched(args, torch, sgl, synth, dev)
     B, nf = args.B, args.batch
     ns, nc = 8 * B ** 3, num_coeffs(B)
     print(f"[bench] B={B} batch={nf} form={args.dtype}: building inputs", file=sys.stderr, flush=True)
@@ -166,13 +209,16 @@ def main():
     forms = {}
     order = [args.dtype] + ([] if args.no_compare else [d for d in ("f64", "f32") if d != args.dtype])
     for dtype in order:
-        plan = p64 if dtype == "f64" else sgl.sgl_plan(B, nf, dtype)
+        head_form = dtype == args.dtype
+        flags = (sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS) if head_form else 0
+        plan = p64 if (dtype == "f64" and not head_form) else sgl.sgl_plan_ex([B] * nf, dtype, flags)
         s_in = s128 if dtype == "f64" else s128.to(torch.complex64)
         c_in = c128 if dtype == "f64" else c128.to(torch.complex64)
-        steps = args.steps if dtype == args.dtype else max(3, args.steps // 4)
-        warm = args.warmup if dtype == args.dtype else 2
+        steps = args.steps if head_form else max(3, args.steps // 4)
+        warm = args.warmup if head_form else 2
         print(f"[bench] timing {dtype}: {warm} warmup + {steps} steps", file=sys.stderr, flush=True)
-        ms, per_stage, cout, sout = run_form(sgl, torch, plan, c_in, s_in, steps, warm)
+        ms, per_stage, cout, sout, graph_ms = run_form(sgl, torch, plan, c_in, s_in, steps, warm,
+                                                       graph_steps=steps if head_form else 0)
         forms[dtype] = {
             "ms_per_step": ms,
             "transforms_per_s": nf * 1000.0 / ms,
@@ -181,10 +227,13 @@ def main():
             "e_inf_forward_vs_f64": einf(c_ref, cout, nc),
             "e_inf_inverse_vs_f64": einf(s128, sout, ns),
         }
+        if head_form:
+            forms[dtype]["graph_ms_per_step"] = graph_ms
+            forms[dtype]["launch_grids"] = plan.launch_grids()
         print(f"[bench] {dtype}: {ms:.3f} ms/step, {nf * 1000.0 / ms:.1f} transforms/s", file=sys.stderr,
               flush=True)
         del cout, sout
-        if dtype != "f64":
+        if plan is not p64:
             plan.destroy()
 
     head = forms[args.dtype]

@@ -81,6 +81,13 @@ typedef enum { SGL_F64 = 0, SGL_F32 = 1, SGL_SPLIT_BF16 = 2 } sgl_dtype_t;
 
 /* plan flags */
 #define SGL_SAMPLES_RAW 1u /* raw f instead of sigma_i f (SGL_F64 only) */
+#define SGL_GRAPHS 2u      /* replay each direction as a hipGraph: the first call with a
+                              new (input, output) buffer pair captures and instantiates
+                              it (host-side work only); later calls launch the graph.
+                              Up to 8 pairs are kept (least recently used evicted). */
+#define SGL_AUTOTUNE 4u    /* at plan time, time each stage launch with several
+                              persistent grid sizes on scratch buffers and keep the
+                              fastest (plan creation takes longer) */
 
 #define SGL_MAX_B 256 /* largest supported bandlimit */
 
@@ -95,8 +102,14 @@ sgl_status_t sgl_plan(sgl_plan_t* out, int B, int batch, int dtype);
  * (host array).  Functions are packed back to back in the caller's buffers
  * at the offsets reported by sgl_offsets.  Functions of equal bandlimit share
  * tables; every stage runs as one persistent launch over a work list keyed by
- * (order, bandlimit).  flags: 0 or SGL_SAMPLES_RAW. */
+ * (order, bandlimit).  flags: any of SGL_SAMPLES_RAW, SGL_GRAPHS, SGL_AUTOTUNE. */
 sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtype, unsigned flags);
+
+/* The persistent grid (blocks) of each of the 8 launch slots: forward FFT,
+ * forward FFT of 512-point rings, forward Legendre, forward radial, inverse
+ * radial, inverse Legendre, inverse FFT, inverse FFT of 512-point rings.
+ * grids: host array of 8 ints. */
+sgl_status_t sgl_launch_grids(sgl_plan_t plan, int* grids);
 
 /* Forward transform (Alg. 3) of every function of the plan.
  * d_samples: device, const, total_samples complex values (complex128 for

@@ -447,7 +447,10 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const ClassDesc* __restrict
   }
 }
 
-inline int grid_for(int nwork) { return nwork < 4096 ? nwork : 4096; }
+inline int grid_for(int nwork, int max_grid) {
+  const int g = max_grid > 0 ? max_grid : 4096;
+  return nwork < g ? nwork : g;
+}
 
 }  // namespace
 
@@ -466,54 +469,58 @@ static void allow_lds(K kernel, int bytes) {
 
 template <bool BIG>
 static hipError_t fft_fwd(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork, int lds,
-                          const void* samples, hipStream_t s) {
+                          const void* samples, int max_grid, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
-  dim3 grid(grid_for(nwork)), block(256);
-  if (prec == PREC_F64 && raw) {
-    allow_lds(k_fft_forward<double, true, BIG>, lds);
+  dim3 grid(grid_for(nwork, max_grid)), block(256);
+  if (prec == PREC_F64 && raw)
     hipLaunchKernelGGL((k_fft_forward<double, true, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
-  } else if (prec == PREC_F64) {
-    allow_lds(k_fft_forward<double, false, BIG>, lds);
+  else if (prec == PREC_F64)
     hipLaunchKernelGGL((k_fft_forward<double, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
-  } else {
-    allow_lds(k_fft_forward<float, false, BIG>, lds);
+  else
     hipLaunchKernelGGL((k_fft_forward<float, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
-  }
   return hipGetLastError();
 }
 
 template <bool BIG>
 static hipError_t fft_inv(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork, int lds,
-                          void* samples, hipStream_t s) {
+                          void* samples, int max_grid, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
-  dim3 grid(grid_for(nwork)), block(256);
-  if (prec == PREC_F64 && raw) {
-    allow_lds(k_fft_inverse<double, true, BIG>, lds);
+  dim3 grid(grid_for(nwork, max_grid)), block(256);
+  if (prec == PREC_F64 && raw)
     hipLaunchKernelGGL((k_fft_inverse<double, true, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
-  } else if (prec == PREC_F64) {
-    allow_lds(k_fft_inverse<double, false, BIG>, lds);
+  else if (prec == PREC_F64)
     hipLaunchKernelGGL((k_fft_inverse<double, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
-  } else {
-    allow_lds(k_fft_inverse<float, false, BIG>, lds);
+  else
     hipLaunchKernelGGL((k_fft_inverse<float, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
-  }
   return hipGetLastError();
 }
 
+// Allow the dynamic LDS the FFT launches of a plan need (set once, at plan time).
+void prepare_fft_kernels(int lds_small, int lds_big) {
+  allow_lds(k_fft_forward<double, true, false>, lds_small);
+  allow_lds(k_fft_forward<double, false, false>, lds_small);
+  allow_lds(k_fft_forward<float, false, false>, lds_small);
+  allow_lds(k_fft_inverse<double, true, false>, lds_small);
+  allow_lds(k_fft_inverse<double, false, false>, lds_small);
+  allow_lds(k_fft_inverse<float, false, false>, lds_small);
+  allow_lds(k_fft_forward<double, true, true>, lds_big);
+  allow_lds(k_fft_forward<double, false, true>, lds_big);
+  allow_lds(k_fft_forward<float, false, true>, lds_big);
+  allow_lds(k_fft_inverse<double, true, true>, lds_big);
+  allow_lds(k_fft_inverse<double, false, true>, lds_big);
+  allow_lds(k_fft_inverse<float, false, true>, lds_big);
+}
+
 hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, const int4* d_work_big, int nwork_big, int lds_big,
-                              const void* samples, hipStream_t s) {
-  hipError_t e = fft_fwd<false>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, s);
-  if (e != hipSuccess) return e;
-  return fft_fwd<true>(prec, raw, d_cls, d_work_big, nwork_big, lds_big, samples, s);
+                              int lds_bytes, bool big, const void* samples, int max_grid, hipStream_t s) {
+  return big ? fft_fwd<true>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s)
+             : fft_fwd<false>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
 }
 
 hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, const int4* d_work_big, int nwork_big, int lds_big, void* samples,
-                              hipStream_t s) {
-  hipError_t e = fft_inv<false>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, s);
-  if (e != hipSuccess) return e;
-  return fft_inv<true>(prec, raw, d_cls, d_work_big, nwork_big, lds_big, samples, s);
+                              int lds_bytes, bool big, void* samples, int max_grid, hipStream_t s) {
+  return big ? fft_inv<true>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s)
+             : fft_inv<false>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
 }
 
 size_t fft_lds_bytes_for(int prec, int rpb, int L) { return fft_lds_bytes(prec, rpb, L); }

@@ -610,14 +610,17 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
   }
 }
 
-inline int grid_for(int nwork) { return nwork < 8192 ? nwork : 8192; }
+inline int grid_for(int nwork, int max_grid) {
+  const int g = max_grid > 0 ? max_grid : 8192;
+  return nwork < g ? nwork : g;
+}
 
 template <int PREC>
 hipError_t launch_kind(int kind, const ClassDesc* d_cls, const int4* d_work, int nwork, const void* cin, void* cout,
-                       hipStream_t s) {
+                       int max_grid, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   DebugArgs dbg{0, 0, 0, nullptr, nullptr, nullptr};
-  dim3 grid(grid_for(nwork)), block(NT);
+  dim3 grid(grid_for(nwork, max_grid)), block(NT);
   switch (kind) {
     case K_B_FWD:
       hipLaunchKernelGGL((k_gemm<PREC, K_B_FWD>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
@@ -636,10 +639,10 @@ hipError_t launch_kind(int kind, const ClassDesc* d_cls, const int4* d_work, int
 }
 
 hipError_t launch_any(int prec, int kind, const ClassDesc* d_cls, const int4* d_work, int nwork, const void* cin,
-                      void* cout, hipStream_t s) {
-  if (prec == PREC_F64) return launch_kind<PREC_F64>(kind, d_cls, d_work, nwork, cin, cout, s);
-  if (prec == PREC_F32) return launch_kind<PREC_F32>(kind, d_cls, d_work, nwork, cin, cout, s);
-  return launch_kind<PREC_SPLIT>(kind, d_cls, d_work, nwork, cin, cout, s);
+                      void* cout, int max_grid, hipStream_t s) {
+  if (prec == PREC_F64) return launch_kind<PREC_F64>(kind, d_cls, d_work, nwork, cin, cout, max_grid, s);
+  if (prec == PREC_F32) return launch_kind<PREC_F32>(kind, d_cls, d_work, nwork, cin, cout, max_grid, s);
+  return launch_kind<PREC_SPLIT>(kind, d_cls, d_work, nwork, cin, cout, max_grid, s);
 }
 
 }  // namespace
@@ -649,13 +652,13 @@ int gemm_tile_n_complex() { return BNC; }
 int gemm_k_chunk() { return BK; }
 
 hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                           hipStream_t s) {
-  return launch_any(prec, inverse ? K_B_INV : K_B_FWD, d_cls, d_work, nwork, nullptr, nullptr, s);
+                           int max_grid, hipStream_t s) {
+  return launch_any(prec, inverse ? K_B_INV : K_B_FWD, d_cls, d_work, nwork, nullptr, nullptr, max_grid, s);
 }
 
 hipError_t launch_radial(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                         const void* coeffs_in, void* coeffs_out, hipStream_t s) {
-  return launch_any(prec, inverse ? K_C_INV : K_C_FWD, d_cls, d_work, nwork, coeffs_in, coeffs_out, s);
+                         const void* coeffs_in, void* coeffs_out, int max_grid, hipStream_t s) {
+  return launch_any(prec, inverse ? K_C_INV : K_C_FWD, d_cls, d_work, nwork, coeffs_in, coeffs_out, max_grid, s);
 }
 
 hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, const double* X, double* C,
@@ -663,7 +666,7 @@ hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, con
   DebugArgs dbg{M, N, K, A, X, C};
   const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   if (tiles == 0) return hipSuccess;
-  dim3 grid(grid_for(tiles)), block(NT);
+  dim3 grid(grid_for(tiles, 0)), block(NT);
   if (prec == PREC_F64)
     hipLaunchKernelGGL((k_gemm<PREC_F64, K_DEBUG>), grid, block, 0, s, nullptr, nullptr, 0, nullptr, nullptr, dbg);
   else if (prec == PREC_F32)

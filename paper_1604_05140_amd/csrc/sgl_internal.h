@@ -76,14 +76,14 @@ enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_SPLIT = 2 };
 
 // Stage kernels (defined in sgl_fft.hip / sgl_gemm.hip)
 // stage (a) work items carry the rings per block in .w; lds_bytes = 2 * rpb * L * sizeof(complex)
-// Rings of length 512 (B = 256) run in a kernel of their own (d_work_big) so that
+// Rings of length 512 (B = 256) run in a kernel of their own (big = true) so that
 // their register footprint does not lower the occupancy of the other lengths.
+// max_grid bounds the persistent grid (0 = the default bound).
 hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, const int4* d_work_big, int nwork_big, int lds_big,
-                              const void* samples, hipStream_t s);
+                              int lds_bytes, bool big, const void* samples, int max_grid, hipStream_t s);
 hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, const int4* d_work_big, int nwork_big, int lds_big, void* samples,
-                              hipStream_t s);
+                              int lds_bytes, bool big, void* samples, int max_grid, hipStream_t s);
+void prepare_fft_kernels(int lds_small, int lds_big);
 size_t fft_lds_bytes_for(int prec, int rpb, int L);
 // power-of-two ring lengths 16..512 take the register four-step path; its rings
 // per block are 256 / R1 with L = R1 * R2, R1 = R2 or 2 R2.
@@ -94,9 +94,9 @@ inline int fft_pow2_rpb(int L) {
   return 256 / r1;
 }
 hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                           hipStream_t s);
+                           int max_grid, hipStream_t s);
 hipError_t launch_radial(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                         const void* coeffs_in, void* coeffs_out, hipStream_t s);
+                         const void* coeffs_in, void* coeffs_out, int max_grid, hipStream_t s);
 hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, const double* X, double* C,
                              hipStream_t s);
 int gemm_tile_m();

@@ -65,6 +65,19 @@ struct sgl_plan_s {
   int off_a = 0, n_a = 0, off_bf = 0, n_bf = 0, off_bi = 0, n_bi = 0, off_cf = 0, n_cf = 0, off_ci = 0, n_ci = 0;
   int off_a2 = 0, n_a2 = 0;  // stage (a) items of length-512 rings
   int lds_a = 0, lds_a2 = 0;
+  // persistent grid bound per launch slot (0 = kernel default; set by the autotuner)
+  int grid[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // captured launch sequences, keyed by (direction, input, output)
+  struct GraphEntry {
+    int dir;
+    const void* in;
+    void* out;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t tick = 0;
+  hipStream_t cap = nullptr;
   // timing
   bool timing = false;
   static constexpr int kRing = 64;
@@ -75,6 +88,8 @@ struct sgl_plan_s {
   int cnt[6] = {0, 0, 0, 0, 0, 0};
 
   ~sgl_plan_s() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (cap) (void)hipStreamDestroy(cap);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     for (void* q : allocs) (void)hipFree(q);
   }
@@ -257,6 +272,8 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
   SGL_TRY(p->alloc((void**)&p->d_cls, descs.size() * sizeof(ClassDesc)));
   SGL_HIP_TRY(hipMemcpyAsync(p->d_cls, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice, s));
   SGL_TRY(build_work(p, s));
+  prepare_fft_kernels(p->lds_a, p->lds_a2);
+  if (p->flags & SGL_GRAPHS) SGL_HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
   SGL_HIP_TRY(hipStreamSynchronize(s));
   return SGL_OK;
 }
@@ -298,6 +315,169 @@ sgl_status_t check_call(sgl_plan_t plan, const void* in, size_t nin, const void*
   return SGL_OK;
 }
 
+enum Slot { S_FFT_F = 0, S_FFT_F_BIG, S_LEG_F, S_RAD_F, S_RAD_I, S_LEG_I, S_FFT_I, S_FFT_I_BIG, NSLOT };
+// launch order and timing stage of each direction
+const int kSeq[2][4] = {{S_FFT_F, S_FFT_F_BIG, S_LEG_F, S_RAD_F}, {S_RAD_I, S_LEG_I, S_FFT_I, S_FFT_I_BIG}};
+const int kStage[2][4] = {{0, 0, 1, 2}, {3, 4, 5, 5}};
+
+int slot_work(const sgl_plan_s* p, int slot) {
+  switch (slot) {
+    case S_FFT_F: case S_FFT_I: return p->n_a;
+    case S_FFT_F_BIG: case S_FFT_I_BIG: return p->n_a2;
+    case S_LEG_F: return p->n_bf;
+    case S_LEG_I: return p->n_bi;
+    case S_RAD_F: return p->n_cf;
+    default: return p->n_ci;
+  }
+}
+
+// One stage launch.  in/out: the caller's buffers of this direction.
+hipError_t launch_slot(sgl_plan_s* p, int slot, const void* in, void* out, hipStream_t s) {
+  const int prec = prec_of(p->dtype);
+  const bool raw = (p->flags & SGL_SAMPLES_RAW) != 0;
+  const int g = p->grid[slot];
+  switch (slot) {
+    case S_FFT_F:
+      return launch_fft_forward(prec, raw, p->d_cls, p->d_work + p->off_a, p->n_a, p->lds_a, false, in, g, s);
+    case S_FFT_F_BIG:
+      return launch_fft_forward(prec, raw, p->d_cls, p->d_work + p->off_a2, p->n_a2, p->lds_a2, true, in, g, s);
+    case S_LEG_F:
+      return launch_legendre(prec, false, p->d_cls, p->d_work + p->off_bf, p->n_bf, g, s);
+    case S_RAD_F:
+      return launch_radial(prec, false, p->d_cls, p->d_work + p->off_cf, p->n_cf, nullptr, out, g, s);
+    case S_RAD_I:
+      return launch_radial(prec, true, p->d_cls, p->d_work + p->off_ci, p->n_ci, in, nullptr, g, s);
+    case S_LEG_I:
+      return launch_legendre(prec, true, p->d_cls, p->d_work + p->off_bi, p->n_bi, g, s);
+    case S_FFT_I:
+      return launch_fft_inverse(prec, raw, p->d_cls, p->d_work + p->off_a, p->n_a, p->lds_a, false, out, g, s);
+    default:
+      return launch_fft_inverse(prec, raw, p->d_cls, p->d_work + p->off_a2, p->n_a2, p->lds_a2, true, out, g, s);
+  }
+}
+
+hipError_t launch_sequence(sgl_plan_s* p, int dir, const void* in, void* out, hipStream_t s, bool timed) {
+  int open_stage = -1;
+  for (int q = 0; q < 4; ++q) {
+    const int slot = kSeq[dir][q];
+    if (slot_work(p, slot) == 0) continue;
+    const int st = kStage[dir][q];
+    if (timed && st != open_stage) {
+      if (open_stage >= 0) time_end(p, open_stage, s);
+      time_begin(p, st, s);
+      open_stage = st;
+    }
+    hipError_t e = launch_slot(p, slot, in, out, s);
+    if (e != hipSuccess) return e;
+  }
+  if (timed && open_stage >= 0) time_end(p, open_stage, s);
+  return hipSuccess;
+}
+
+sgl_status_t run_direction(sgl_plan_s* p, int dir, const void* in, void* out, hipStream_t s) {
+  if (p->timing || !(p->flags & SGL_GRAPHS)) {
+    SGL_HIP_TRY(launch_sequence(p, dir, in, out, s, p->timing));
+    return SGL_OK;
+  }
+  for (auto& g : p->graphs) {
+    if (g.dir == dir && g.in == in && g.out == out) {
+      g.used = ++p->tick;
+      SGL_HIP_TRY(hipGraphLaunch(g.exec, s));
+      return SGL_OK;
+    }
+  }
+  // first call with this buffer pair: capture the launch sequence on the plan's
+  // own stream and keep the instantiated graph
+  SGL_HIP_TRY(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t le = launch_sequence(p, dir, in, out, p->cap, false);
+  hipGraph_t graph = nullptr;
+  hipError_t ce = hipStreamEndCapture(p->cap, &graph);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    set_error(std::string("graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ce));
+    return SGL_ERR_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    return SGL_ERR_HIP;
+  }
+  if (p->graphs.size() >= 8) {
+    auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
+                                [](const sgl_plan_s::GraphEntry& a, const sgl_plan_s::GraphEntry& b) {
+                                  return a.used < b.used;
+                                });
+    (void)hipGraphExecDestroy(lru->exec);
+    p->graphs.erase(lru);
+  }
+  p->graphs.push_back({dir, in, out, exec, ++p->tick});
+  SGL_HIP_TRY(hipGraphLaunch(exec, s));
+  return SGL_OK;
+}
+
+// Plan-time autotuner: for every launch slot, time the persistent grid bounds
+// {1, 2, 4, 8, 16} x CUs and "one block per work item" on scratch buffers and
+// keep the fastest.
+sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
+  int dev = 0, ncu = 256;
+  SGL_HIP_TRY(hipGetDevice(&dev));
+  SGL_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  void* tin = nullptr;
+  void* tout = nullptr;
+  SGL_TRY(p->alloc(&tin, (size_t)p->tot_s * p->esz()));
+  SGL_TRY(p->alloc(&tout, (size_t)p->tot_c * p->esz()));
+  SGL_HIP_TRY(hipMemsetAsync(tin, 0, (size_t)p->tot_s * p->esz(), s));
+  SGL_HIP_TRY(hipMemsetAsync(tout, 0, (size_t)p->tot_c * p->esz(), s));
+  hipEvent_t e0, e1;
+  SGL_HIP_TRY(hipEventCreate(&e0));
+  SGL_HIP_TRY(hipEventCreate(&e1));
+  sgl_status_t st = SGL_OK;
+  for (int slot = 0; slot < NSLOT && st == SGL_OK; ++slot) {
+    const int n = slot_work(p, slot);
+    if (n == 0) continue;
+    const bool inv = slot >= S_RAD_I;
+    const void* in = inv ? tout : tin;
+    void* out = inv ? tin : tout;
+    std::vector<int> cand;
+    for (int mult : {1, 2, 4, 8, 16})
+      if (mult * ncu < n) cand.push_back(mult * ncu);
+    cand.push_back(n);
+    float best = 1e30f;
+    int best_g = 0;
+    for (int g : cand) {
+      p->grid[slot] = g;
+      hipError_t e = launch_slot(p, slot, in, out, s);  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_slot(p, slot, in, out, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        set_error(std::string("autotune: ") + hipGetErrorString(e));
+        st = SGL_ERR_HIP;
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_g = g;
+      }
+    }
+    p->grid[slot] = best_g;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // scratch buffers are released now (plan time)
+  for (void* q : {tin, tout}) {
+    auto it = std::find(p->allocs.begin(), p->allocs.end(), q);
+    if (it != p->allocs.end()) p->allocs.erase(it);
+    (void)hipFree(q);
+  }
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -331,7 +511,7 @@ sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtyp
     set_error("unknown dtype");
     return SGL_ERR_INVALID_ARG;
   }
-  if (flags & ~SGL_SAMPLES_RAW) { set_error("unknown flag"); return SGL_ERR_INVALID_ARG; }
+  if (flags & ~(SGL_SAMPLES_RAW | SGL_GRAPHS | SGL_AUTOTUNE)) { set_error("unknown flag"); return SGL_ERR_INVALID_ARG; }
   if ((flags & SGL_SAMPLES_RAW) && dtype != SGL_F64) {
     set_error("raw samples need SGL_F64 (they leave the FP32 range for B > ~40)");
     return SGL_ERR_UNSUPPORTED;
@@ -355,6 +535,7 @@ sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtyp
   }
   hipStream_t s = nullptr;
   sgl_status_t st = make_plan(p.get(), s);
+  if (st == SGL_OK && (flags & SGL_AUTOTUNE)) st = autotune(p.get(), s);
   if (st != SGL_OK) return st;  // unique_ptr frees everything allocated so far
   *out = p.release();
   return SGL_OK;
@@ -380,39 +561,13 @@ sgl_status_t sgl_plan_destroy(sgl_plan_t plan) {
 sgl_status_t sgl_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
   if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
   SGL_TRY(check_call(plan, d_samples, plan->tot_s * plan->esz(), d_coeffs, plan->tot_c * plan->esz()));
-  hipStream_t s = (hipStream_t)stream;
-  const int prec = prec_of(plan->dtype);
-  const bool raw = (plan->flags & SGL_SAMPLES_RAW) != 0;
-  time_begin(plan, 0, s);
-  SGL_HIP_TRY(launch_fft_forward(prec, raw, plan->d_cls, plan->d_work + plan->off_a, plan->n_a, plan->lds_a,
-                                 plan->d_work + plan->off_a2, plan->n_a2, plan->lds_a2, d_samples, s));
-  time_end(plan, 0, s);
-  time_begin(plan, 1, s);
-  SGL_HIP_TRY(launch_legendre(prec, false, plan->d_cls, plan->d_work + plan->off_bf, plan->n_bf, s));
-  time_end(plan, 1, s);
-  time_begin(plan, 2, s);
-  SGL_HIP_TRY(launch_radial(prec, false, plan->d_cls, plan->d_work + plan->off_cf, plan->n_cf, nullptr, d_coeffs, s));
-  time_end(plan, 2, s);
-  return SGL_OK;
+  return run_direction(plan, 0, d_samples, d_coeffs, (hipStream_t)stream);
 }
 
 sgl_status_t sgl_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {
   if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
   SGL_TRY(check_call(plan, d_coeffs, plan->tot_c * plan->esz(), d_samples, plan->tot_s * plan->esz()));
-  hipStream_t s = (hipStream_t)stream;
-  const int prec = prec_of(plan->dtype);
-  const bool raw = (plan->flags & SGL_SAMPLES_RAW) != 0;
-  time_begin(plan, 3, s);
-  SGL_HIP_TRY(launch_radial(prec, true, plan->d_cls, plan->d_work + plan->off_ci, plan->n_ci, d_coeffs, nullptr, s));
-  time_end(plan, 3, s);
-  time_begin(plan, 4, s);
-  SGL_HIP_TRY(launch_legendre(prec, true, plan->d_cls, plan->d_work + plan->off_bi, plan->n_bi, s));
-  time_end(plan, 4, s);
-  time_begin(plan, 5, s);
-  SGL_HIP_TRY(launch_fft_inverse(prec, raw, plan->d_cls, plan->d_work + plan->off_a, plan->n_a, plan->lds_a,
-                                 plan->d_work + plan->off_a2, plan->n_a2, plan->lds_a2, d_samples, s));
-  time_end(plan, 5, s);
-  return SGL_OK;
+  return run_direction(plan, 1, d_coeffs, d_samples, (hipStream_t)stream);
 }
 
 sgl_status_t sgl_plan_info(sgl_plan_t plan, int64_t* total_samples, int64_t* total_coeffs, int* nfunc) {
@@ -454,6 +609,12 @@ sgl_status_t sgl_table(sgl_plan_t plan, int B, int which, double* host_out) {
   if (!c) { set_error("bandlimit not in plan"); return SGL_ERR_INVALID_ARG; }
   SGL_HIP_TRY(hipMemcpy(host_out, which == 0 ? c->P64 : c->R64, table_size(B) * sizeof(double),
                         hipMemcpyDeviceToHost));
+  return SGL_OK;
+}
+
+sgl_status_t sgl_launch_grids(sgl_plan_t plan, int* grids) {
+  if (!plan || !grids) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
+  for (int q = 0; q < NSLOT; ++q) grids[q] = plan->grid[q] ? plan->grid[q] : slot_work(plan, q);
   return SGL_OK;
 }
 

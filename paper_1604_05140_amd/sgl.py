@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libsgl.so")
 
 SGL_F64, SGL_F32, SGL_SPLIT_BF16 = 0, 1, 2
 SGL_SAMPLES_RAW = 1
+SGL_GRAPHS = 2
+SGL_AUTOTUNE = 4
 SGL_MAX_B = 256
 DTYPES = {"f64": SGL_F64, "f32": SGL_F32, "split_bf16": SGL_SPLIT_BF16}
 
@@ -56,6 +58,7 @@ def _load():
         "sgl_grid": ([P, ctypes.c_int, dp, dp, dp, dp, dp], ctypes.c_int),
         "sgl_table": ([P, ctypes.c_int, ctypes.c_int, dp], ctypes.c_int),
         "sgl_set_timing": ([P, ctypes.c_int], ctypes.c_int),
+        "sgl_launch_grids": ([P, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "sgl_stage_times": ([P, dp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "sgl_debug_gemm": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P], ctypes.c_int),
         "sgl_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -79,6 +82,7 @@ _HEADER_NAMES = [
     "sgl_plan", "sgl_plan_ex", "sgl_forward", "sgl_inverse", "sgl_plan_destroy", "sgl_num_samples",
     "sgl_num_coeffs", "sgl_coeff_index", "sgl_plan_info", "sgl_offsets", "sgl_grid", "sgl_table",
     "sgl_set_timing", "sgl_stage_times", "sgl_debug_gemm", "sgl_status_string", "sgl_last_error",
+    "sgl_launch_grids",
 ]
 
 
@@ -153,6 +157,11 @@ class Plan:
         _check(_load().sgl_table(self._h, B, which, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "sgl_table")
         return out
+
+    def launch_grids(self):
+        g = (ctypes.c_int * 8)()
+        _check(_load().sgl_launch_grids(self._h, g), "sgl_launch_grids")
+        return list(g)
 
     def set_timing(self, enable: bool):
         _check(_load().sgl_set_timing(self._h, 1 if enable else 0), "sgl_set_timing")

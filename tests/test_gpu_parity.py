@@ -275,3 +275,87 @@ def test_precision_config5_b256_split():
     oms = synth.subset(6, D.num_coeffs(B), seed=SEED + 1005)
     f_or = D.forward(s0, B, omegas=oms)
     assert np.abs(c[0][oms] - f_or).max() <= 1e-12 * np.abs(c[0]).max()
+
+
+# ---------------------------------------------------------------------------
+# hipGraph replay and the plan-time autotuner
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f64", "split_bf16"])
+def test_graph_replays_match_eager(dtype):
+    """SGL_GRAPHS: every replay equals the eager launch sequence on the same inputs,
+    with eager work (another plan, torch kernels) and input changes in between."""
+    B, batch = 12, 2
+    eager = sgl.sgl_plan(B, batch, dtype)
+    graph = sgl.sgl_plan_ex([B] * batch, dtype, sgl.SGL_GRAPHS)
+    ct = eager.complex_dtype
+    s_in = torch.empty(eager.total_samples, dtype=ct, device=DEV)
+    c_in = torch.empty(eager.total_coeffs, dtype=ct, device=DEV)
+    c_out = torch.empty(eager.total_coeffs, dtype=ct, device=DEV)
+    s_out = torch.empty(eager.total_samples, dtype=ct, device=DEV)
+    for rep in range(4):
+        s_in.copy_(dev(synth.complex_normal_samples(B, batch, seed=SEED + 70 + rep), ct))
+        c_in.copy_(dev(synth.complex_normal_coeffs(B, batch, seed=SEED + 80 + rep), ct))
+        ref_c = gpu_forward(eager, s_in)
+        ref_s = gpu_inverse(eager, c_in)
+        _ = (torch.randn(1 << 20, device=DEV) * 2).sum()  # unrelated eager work
+        sgl.sgl_forward(graph, s_in, c_out)
+        sgl.sgl_inverse(graph, c_in, s_out)
+        torch.cuda.synchronize()
+        assert torch.equal(c_out, ref_c), rep
+        assert torch.equal(s_out, ref_s), rep
+    # a second buffer pair is captured separately and does not disturb the first
+    c_out2 = torch.empty_like(c_out)
+    sgl.sgl_forward(graph, s_in, c_out2)
+    sgl.sgl_forward(graph, s_in, c_out)
+    torch.cuda.synchronize()
+    assert torch.equal(c_out2, c_out)
+
+
+def test_autotuned_plan_matches_default():
+    B, batch = 16, 3
+    s = synth.complex_normal_samples(B, batch, seed=SEED + 90)
+    c = synth.complex_normal_coeffs(B, batch, seed=SEED + 91)
+    for dtype in ("f64", "split_bf16"):
+        p0 = sgl.sgl_plan(B, batch, dtype)
+        p1 = sgl.sgl_plan_ex([B] * batch, dtype, sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS)
+        grids = p1.launch_grids()
+        assert all(g >= 1 for g in grids[:1] + grids[2:6]), grids
+        assert torch.equal(gpu_forward(p0, s), gpu_forward(p1, s))
+        assert torch.equal(gpu_inverse(p0, c), gpu_inverse(p1, c))
+
+
+# ---------------------------------------------------------------------------
+# Batched form: uneven bandlimits through one launch per stage
+# ---------------------------------------------------------------------------
+def test_batched_config4_256_functions_f32():
+    """256 functions with bandlimits uniform in {16..96}, CN(0,1)/n coefficients:
+    FP32 MFMA batched plan (autotuned, graphs) against the FP64 batched plan
+    (1e-5), and the FP64 plan against the oracle on a few coefficients."""
+    Bs = synth.batched_bandlimits(256, 16, 96, seed=SEED + 4)
+    p64 = sgl.sgl_plan_ex(list(Bs), "f64")
+    p32 = sgl.sgl_plan_ex(list(Bs), "f32", sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS)
+    so, co = p64.offsets()
+    cs = [synth.complex_normal_coeffs(int(B), 1, seed=SEED + 4000 + q, decay=1.0)[0] for q, B in enumerate(Bs)]
+    c_dev = dev(np.concatenate(cs), torch.complex128)
+    s64 = gpu_inverse(p64, c_dev)
+    c64 = gpu_forward(p64, s64)
+    s32 = gpu_inverse(p32, c_dev.to(torch.complex64))
+    c32 = gpu_forward(p32, s64.to(torch.complex64))
+    worst_f = worst_i = worst_rt = 0.0
+    for q, B in enumerate(Bs):
+        nc, ns = D.num_coeffs(int(B)), D.num_samples(int(B))
+        cr = c_dev[co[q]:co[q] + nc]
+        worst_rt = max(worst_rt, einf_dev(cr, c64[co[q]:co[q] + nc]))
+        worst_f = max(worst_f, einf_dev(c64[co[q]:co[q] + nc], c32[co[q]:co[q] + nc]))
+        worst_i = max(worst_i, einf_dev(s64[so[q]:so[q] + ns], s32[so[q]:so[q] + ns]))
+    print(f"config4: FP64 round trip {worst_rt:.2e}; FP32 forward {worst_f:.2e}, inverse {worst_i:.2e}", flush=True)
+    assert worst_rt <= 1e-12
+    assert worst_f <= 1e-5 and worst_i <= 1e-5
+    # oracle spot check on the two smallest functions
+    for q in np.argsort(Bs)[:2]:
+        B = int(Bs[q])
+        s_host = s64[so[q]:so[q] + D.num_samples(B)].cpu().numpy()
+        oms = synth.subset(8, D.num_coeffs(B), seed=SEED + 4100 + int(q))
+        f_or = D.forward(s_host, B, omegas=oms)
+        got = c64[co[q]:co[q] + D.num_coeffs(B)].cpu().numpy()[oms]
+        assert np.abs(got - f_or).max() <= 1e-12 * np.abs(cs[q]).max()
