@@ -105,10 +105,14 @@ sgl_status_t sgl_plan(sgl_plan_t* out, int B, int batch, int dtype);
  * (order, bandlimit).  flags: any of SGL_SAMPLES_RAW, SGL_GRAPHS, SGL_AUTOTUNE. */
 sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtype, unsigned flags);
 
-/* The persistent grid (blocks) of each of the 8 launch slots: forward FFT,
- * forward FFT of 512-point rings, forward Legendre, forward radial, inverse
- * radial, inverse Legendre, inverse FFT, inverse FFT of 512-point rings.
- * grids: host array of 8 ints. */
+/* The persistent grid (blocks) of each of the SGL_NUM_SLOTS launch slots, in
+ * order: forward FFT of power-of-two rings up to 256 points (and other
+ * lengths outside the two Bluestein families), forward FFT of 512-point rings
+ * and of Bluestein rings padded to 512, forward FFT of Bluestein rings padded
+ * to <= 256, forward Legendre, forward radial, inverse radial, inverse
+ * Legendre, then the three inverse FFT slots in the forward order.  A slot
+ * with no work reports 0.  grids: host array of SGL_NUM_SLOTS ints. */
+#define SGL_NUM_SLOTS 10
 sgl_status_t sgl_launch_grids(sgl_plan_t plan, int* grids);
 
 /* Forward transform (Alg. 3) of every function of the plan.

@@ -282,7 +282,179 @@ __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int
   __syncthreads();
 }
 
-template <typename T, bool RAW, bool BIG>
+// ---------------------------------------------------------------------------
+// Other ring lengths 6 <= L <= 256: Bluestein's chirp-z form on the register
+// four-step FFT of length M = 2^k >= 2L - 1:
+//   X_m = c_m sum_k (x_k c_k) conj(c_{m-k}),  c_p = exp(-i pi p^2 / L),
+// i.e. a cyclic convolution of length M computed as IFFT_M(FFT_M(a) * BH) with
+// the kernel spectrum BH precomputed (1/M folded in).  The inverse DFT uses
+// conj(c) and the conjugate kernel.  Per ring set: load and twist into LDS,
+// FFT_M pass 1, exchange, pass 2 (times BH) + inverse pass A in registers,
+// exchange, inverse pass B, untwist and store.  One LDS buffer of
+// M x (RPB+1) complex holds the natural-order rings and both exchanges.
+// ---------------------------------------------------------------------------
+template <typename T, int R1, int R2, bool INV>
+__device__ inline void blue_core(int rpb, int nr, typename C2<T>::t* buf, const typename C2<T>::t* twM,
+                                 const typename C2<T>::t* bh, int out_r_fastest, typename C2<T>::t (&res)[R1]) {
+  // buf holds rings in natural order [r][M]; on return thread (r, n2) of the
+  // final pass holds z[R2 n1 + n2] in res[n1] (mapping chosen by out_r_fastest).
+  using T2 = typename C2<T>::t;
+  constexpr int M = R1 * R2;
+  const int t = threadIdx.x;
+  const int P = rpb + 1;
+  T2 v[R1];
+  const bool p1 = t < rpb * R2;
+  const int r1 = t / R2, n21 = t % R2;
+  if (p1 && r1 < nr) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) v[n1] = buf[r1 * M + R2 * n1 + n21];
+  }
+  __syncthreads();  // natural-order data consumed; buf becomes the exchange area
+  if (p1 && r1 < nr) {
+    dft_reg<T2, R1, false>(v);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      const T2 w = k1 == 0 ? v[k1] : cmul(v[k1], twM[(n21 * k1) % M]);
+      buf[(k1 * R2 + n21) * P + r1] = w;
+    }
+  }
+  __syncthreads();
+  const int r2 = t % rpb, k1 = t / rpb;
+  T2 y[R2];
+  const bool p2 = t < rpb * R1;
+  if (p2 && r2 < nr) {
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) y[n2] = buf[(k1 * R2 + n2) * P + r2];
+  }
+  __syncthreads();  // exchange consumed before it is rewritten
+  if (p2 && r2 < nr) {
+    dft_reg<T2, R2, false>(y);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) y[k2] = cmul(y[k2], bh[k1 + R1 * k2]);
+    dft_reg<T2, R2, true>(y);
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+      const T2 w = n2 == 0 ? y[n2] : cmul(y[n2], conjc(twM[(n2 * k1) % M]));
+      buf[(k1 * R2 + n2) * P + r2] = w;
+    }
+  }
+  __syncthreads();
+  const int rB = out_r_fastest ? t % rpb : t / R2;
+  const int n2B = out_r_fastest ? t / rpb : t % R2;
+  if (t < rpb * R2 && rB < nr) {
+#pragma unroll
+    for (int q = 0; q < R1; ++q) res[q] = buf[(q * R2 + n2B) * P + rB];
+    dft_reg<T2, R1, true>(res);
+  }
+}
+
+template <typename T, int R1, int R2, bool RAW>
+__device__ inline void fwd_blue(const ClassDesc& C, int j, int col0, int nr, int rpb,
+                                const typename C2<T>::t* __restrict__ samples, typename C2<T>::t* buf,
+                                const typename C2<T>::t* twM, const typename C2<T>::t* chirp,
+                                const typename C2<T>::t* bh) {
+  using T2 = typename C2<T>::t;
+  constexpr int M = R1 * R2;
+  const int L = C.L, B = C.B;
+  for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
+    const int r = e / M, k = e - r * M;
+    T2 v;
+    v.x = 0;
+    v.y = 0;
+    if (k < L) {
+      const int col = col0 + r;
+      const int b = col / L, i = col - b * L;
+      v = cmul(samples[C.soff[b] + ((int64_t)i * L + j) * L + k], chirp[k]);
+      if (RAW) {
+        const T sg = (T)C.sigma[i];
+        v.x *= sg;
+        v.y *= sg;
+      }
+    }
+    buf[r * M + k] = v;
+  }
+  __syncthreads();
+  T2 z[R1];
+  blue_core<T, R1, R2, false>(rpb, nr, buf, twM, bh, 1, z);
+  const int t = threadIdx.x;
+  const int r = t % rpb, n2 = t / rpb;
+  if (t < rpb * R2 && r < nr) {
+    const T wj = (T)C.btilde[j];
+    const int ncol = C.nf * L;
+    T2* F = reinterpret_cast<T2*>(C.F);
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+      const int idx = R2 * n1 + n2;
+      if (idx >= L || idx == B) continue;
+      const int mi = (idx < B ? idx : idx - L) + B - 1;
+      T2 o = cmul(z[n1], chirp[idx]);
+      o.x *= wj;
+      o.y *= wj;
+      F[((int64_t)mi * L + j) * ncol + col0 + r] = o;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int R1, int R2, bool RAW>
+__device__ inline void inv_blue(const ClassDesc& C, int j, int col0, int nr, int rpb,
+                                typename C2<T>::t* __restrict__ samples, typename C2<T>::t* buf,
+                                const typename C2<T>::t* twM, const typename C2<T>::t* chirp,
+                                const typename C2<T>::t* bh) {
+  using T2 = typename C2<T>::t;
+  constexpr int M = R1 * R2;
+  const int L = C.L, B = C.B;
+  const int ncol = C.nf * L;
+  const T2* F = reinterpret_cast<const T2*>(C.F);
+  // bins p < L in the ring-fastest order of F rows, twisted by conj(c_p)
+  for (int e = threadIdx.x; e < nr * L; e += blockDim.x) {
+    const int p = e / nr, r = e - p * nr;
+    T2 v;
+    v.x = 0;
+    v.y = 0;
+    if (p != B) {
+      const int mi = (p < B ? p : p - L) + B - 1;
+      v = cmul(F[((int64_t)mi * L + j) * ncol + col0 + r], conjc(chirp[p]));
+    }
+    buf[r * M + p] = v;
+  }
+  for (int e = threadIdx.x; e < nr * (M - L); e += blockDim.x) {
+    const int r = e / (M - L), p = L + e - r * (M - L);
+    T2 z;
+    z.x = 0;
+    z.y = 0;
+    buf[r * M + p] = z;
+  }
+  __syncthreads();
+  T2 z[R1];
+  blue_core<T, R1, R2, true>(rpb, nr, buf, twM, bh, 0, z);
+  const int t = threadIdx.x;
+  const int r = t / R2, n2 = t % R2;
+  if (t < rpb * R2 && r < nr) {
+    const int col = col0 + r;
+    const int b = col / L, i = col - b * L;
+    T2* dst = samples + C.soff[b] + ((int64_t)i * L + j) * L;
+    const T sg = RAW ? (T)(1.0 / C.sigma[i]) : (T)1;
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+      const int idx = R2 * n1 + n2;
+      if (idx >= L) continue;
+      T2 o = cmul(z[n1], conjc(chirp[idx]));
+      if (RAW) {
+        o.x *= sg;
+        o.y *= sg;
+      }
+      dst[idx] = o;
+    }
+  }
+  __syncthreads();
+}
+
+// MODE 0: power-of-two rings up to 256 points and the generic path; MODE 1: the
+// 32 x 16 register FFT (512-point rings, Bluestein length 512); MODE 2:
+// Bluestein rings with M <= 256.  Each mode is its own kernel so that it gets
+// only the registers its FFT size needs.
+template <typename T, bool RAW, int MODE>
 __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                                      int nwork, const void* __restrict__ samples_v) {
   using T2 = typename C2<T>::t;
@@ -298,7 +470,7 @@ __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict
     const int rpb = it.w;
     const int col0 = it.z * rpb;
     const int nr = min(rpb, ncol - col0);
-    if (fft_pow2_path(L)) {
+    if (MODE != 2 && fft_pow2_path(L)) {
       T2* twl = smem + L * (rpb + 1);
       if (it.x != tw_cls) {
         const T2* tw = reinterpret_cast<const T2*>(C.tw);
@@ -306,10 +478,10 @@ __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict
         __syncthreads();
         tw_cls = it.x;
       }
-      if constexpr (BIG) {
+      if constexpr (MODE == 1) {
         fwd_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, twl);
       } else {
-        switch (L) {
+        if constexpr (MODE == 0) switch (L) {
           case 16: fwd_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
           case 32: fwd_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
           case 64: fwd_pow2<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
@@ -319,6 +491,37 @@ __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict
       }
       continue;
     }
+    if (MODE != 0 && C.M) {
+      const int M = C.M;
+      T2* tws = smem + M * (rpb + 1);
+      T2* chs = tws + M;
+      T2* bhs = chs + L;
+      if (it.x != tw_cls) {
+        const T2* tw = reinterpret_cast<const T2*>(C.twM);
+        const T2* ch = reinterpret_cast<const T2*>(C.chirp);
+        const T2* bh = reinterpret_cast<const T2*>(C.bhf);
+        for (int q = threadIdx.x; q < M; q += blockDim.x) {
+          tws[q] = tw[q];
+          bhs[q] = bh[q];
+        }
+        for (int q = threadIdx.x; q < L; q += blockDim.x) chs[q] = ch[q];
+        __syncthreads();
+        tw_cls = it.x;
+      }
+      if constexpr (MODE == 1) {
+        fwd_blue<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs);
+      } else {
+        if constexpr (MODE == 2) switch (M) {
+          case 16: fwd_blue<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+          case 32: fwd_blue<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+          case 64: fwd_blue<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+          case 128: fwd_blue<T, 16, 8, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+          default: fwd_blue<T, 16, 16, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+        }
+      }
+      continue;
+    }
+    if constexpr (MODE != 0) continue;
     T2* buf0 = smem;
     T2* buf1 = smem + rpb * L;
     for (int e = threadIdx.x; e < nr * L; e += blockDim.x) {
@@ -363,7 +566,7 @@ __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict
   }
 }
 
-template <typename T, bool RAW, bool BIG>
+template <typename T, bool RAW, int MODE>
 __global__ void __launch_bounds__(256) k_fft_inverse(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                                      int nwork, void* __restrict__ samples_v) {
   using T2 = typename C2<T>::t;
@@ -379,7 +582,7 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const ClassDesc* __restrict
     const int rpb = it.w;
     const int col0 = it.z * rpb;
     const int nr = min(rpb, ncol - col0);
-    if (fft_pow2_path(L)) {
+    if (MODE != 2 && fft_pow2_path(L)) {
       T2* twl = smem + L * (rpb + 1);
       if (it.x != tw_cls) {
         const T2* tw = reinterpret_cast<const T2*>(C.tw);
@@ -387,10 +590,10 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const ClassDesc* __restrict
         __syncthreads();
         tw_cls = it.x;
       }
-      if constexpr (BIG) {
+      if constexpr (MODE == 1) {
         inv_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, twl);
       } else {
-        switch (L) {
+        if constexpr (MODE == 0) switch (L) {
           case 16: inv_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
           case 32: inv_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
           case 64: inv_pow2<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
@@ -400,6 +603,37 @@ __global__ void __launch_bounds__(256) k_fft_inverse(const ClassDesc* __restrict
       }
       continue;
     }
+    if (MODE != 0 && C.M) {
+      const int M = C.M;
+      T2* tws = smem + M * (rpb + 1);
+      T2* chs = tws + M;
+      T2* bhs = chs + L;
+      if (it.x != tw_cls) {
+        const T2* tw = reinterpret_cast<const T2*>(C.twM);
+        const T2* ch = reinterpret_cast<const T2*>(C.chirp);
+        const T2* bh = reinterpret_cast<const T2*>(C.bhi);
+        for (int q = threadIdx.x; q < M; q += blockDim.x) {
+          tws[q] = tw[q];
+          bhs[q] = bh[q];
+        }
+        for (int q = threadIdx.x; q < L; q += blockDim.x) chs[q] = ch[q];
+        __syncthreads();
+        tw_cls = it.x;
+      }
+      if constexpr (MODE == 1) {
+        inv_blue<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs);
+      } else {
+        if constexpr (MODE == 2) switch (M) {
+          case 16: inv_blue<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+          case 32: inv_blue<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+          case 64: inv_blue<T, 8, 8, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+          case 128: inv_blue<T, 16, 8, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+          default: inv_blue<T, 16, 16, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
+        }
+      }
+      continue;
+    }
+    if constexpr (MODE != 0) continue;
     T2* buf0 = smem;
     T2* buf1 = smem + rpb * L;
     const T2* F = reinterpret_cast<const T2*>(C.F);
@@ -458,6 +692,7 @@ inline int grid_for(int nwork, int max_grid) {
 static size_t fft_lds_bytes(int prec, int rpb, int L) {
   const size_t es = prec == PREC_F64 ? sizeof(double2) : sizeof(float2);
   if (fft_pow2_path(L)) return (size_t)L * (rpb + 2) * es;  // exchange buffer + twiddle table
+  if (const int M = fft_bluestein_m(L)) return ((size_t)M * (rpb + 3) + L) * es;  // buffer + tw, kernel, chirp
   return (size_t)2 * rpb * L * es;
 }
 
@@ -467,60 +702,62 @@ static void allow_lds(K kernel, int bytes) {
                                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-template <bool BIG>
+template <int MODE>
 static hipError_t fft_fwd(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork, int lds,
                           const void* samples, int max_grid, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   dim3 grid(grid_for(nwork, max_grid)), block(256);
   if (prec == PREC_F64 && raw)
-    hipLaunchKernelGGL((k_fft_forward<double, true, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
+    hipLaunchKernelGGL((k_fft_forward<double, true, MODE>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   else if (prec == PREC_F64)
-    hipLaunchKernelGGL((k_fft_forward<double, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
+    hipLaunchKernelGGL((k_fft_forward<double, false, MODE>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   else
-    hipLaunchKernelGGL((k_fft_forward<float, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
+    hipLaunchKernelGGL((k_fft_forward<float, false, MODE>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   return hipGetLastError();
 }
 
-template <bool BIG>
+template <int MODE>
 static hipError_t fft_inv(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork, int lds,
                           void* samples, int max_grid, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   dim3 grid(grid_for(nwork, max_grid)), block(256);
   if (prec == PREC_F64 && raw)
-    hipLaunchKernelGGL((k_fft_inverse<double, true, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
+    hipLaunchKernelGGL((k_fft_inverse<double, true, MODE>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   else if (prec == PREC_F64)
-    hipLaunchKernelGGL((k_fft_inverse<double, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
+    hipLaunchKernelGGL((k_fft_inverse<double, false, MODE>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   else
-    hipLaunchKernelGGL((k_fft_inverse<float, false, BIG>), grid, block, lds, s, d_cls, d_work, nwork, samples);
+    hipLaunchKernelGGL((k_fft_inverse<float, false, MODE>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   return hipGetLastError();
 }
 
 // Allow the dynamic LDS the FFT launches of a plan need (set once, at plan time).
-void prepare_fft_kernels(int lds_small, int lds_big) {
-  allow_lds(k_fft_forward<double, true, false>, lds_small);
-  allow_lds(k_fft_forward<double, false, false>, lds_small);
-  allow_lds(k_fft_forward<float, false, false>, lds_small);
-  allow_lds(k_fft_inverse<double, true, false>, lds_small);
-  allow_lds(k_fft_inverse<double, false, false>, lds_small);
-  allow_lds(k_fft_inverse<float, false, false>, lds_small);
-  allow_lds(k_fft_forward<double, true, true>, lds_big);
-  allow_lds(k_fft_forward<double, false, true>, lds_big);
-  allow_lds(k_fft_forward<float, false, true>, lds_big);
-  allow_lds(k_fft_inverse<double, true, true>, lds_big);
-  allow_lds(k_fft_inverse<double, false, true>, lds_big);
-  allow_lds(k_fft_inverse<float, false, true>, lds_big);
+template <int MODE>
+static void allow_mode(int lds) {
+  allow_lds(k_fft_forward<double, true, MODE>, lds);
+  allow_lds(k_fft_forward<double, false, MODE>, lds);
+  allow_lds(k_fft_forward<float, false, MODE>, lds);
+  allow_lds(k_fft_inverse<double, true, MODE>, lds);
+  allow_lds(k_fft_inverse<double, false, MODE>, lds);
+  allow_lds(k_fft_inverse<float, false, MODE>, lds);
+}
+void prepare_fft_kernels(const int* lds_per_mode) {
+  allow_mode<0>(lds_per_mode[0]);
+  allow_mode<1>(lds_per_mode[1]);
+  allow_mode<2>(lds_per_mode[2]);
 }
 
 hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, bool big, const void* samples, int max_grid, hipStream_t s) {
-  return big ? fft_fwd<true>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s)
-             : fft_fwd<false>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
+                              int lds_bytes, int mode, const void* samples, int max_grid, hipStream_t s) {
+  if (mode == 1) return fft_fwd<1>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
+  if (mode == 2) return fft_fwd<2>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
+  return fft_fwd<0>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
 }
 
 hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, bool big, void* samples, int max_grid, hipStream_t s) {
-  return big ? fft_inv<true>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s)
-             : fft_inv<false>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
+                              int lds_bytes, int mode, void* samples, int max_grid, hipStream_t s) {
+  if (mode == 1) return fft_inv<1>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
+  if (mode == 2) return fft_inv<2>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
+  return fft_inv<0>(prec, raw, d_cls, d_work, nwork, lds_bytes, samples, max_grid, s);
 }
 
 size_t fft_lds_bytes_for(int prec, int rpb, int L) { return fft_lds_bytes(prec, rpb, L); }

@@ -65,6 +65,15 @@ struct ClassDesc {
   const double* btilde; // b~_j, 2B
   const double* sigma;  // sigma_i, 2B (raw-sample scaling)
   const void* tw;       // twiddles exp(-2 pi i q / L), q < L (double2 or float2)
+  // Bluestein rings (lengths other than powers of two, 6 <= L <= 256): M is the
+  // power-of-two convolution length >= 2L - 1 (0 if unused), chirp[p] =
+  // exp(-i pi p^2 / L) (p < L), bhf / bhi the spectra of the forward / inverse
+  // chirp kernels divided by M (M values), twM the M-point twiddles.
+  int M;
+  const void* chirp;
+  const void* bhf;
+  const void* bhi;
+  const void* twM;
   void* F;              // stage (a)/(b) workspace, [(2B-1)][2B][nf*2B] complex
   void* g;              // stage (b)/(c) workspace, [l][b][m+l][2B] complex, block l at l^2 nf 2B
 };
@@ -75,19 +84,34 @@ struct ClassDesc {
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_SPLIT = 2 };
 
 // Stage kernels (defined in sgl_fft.hip / sgl_gemm.hip)
-// stage (a) work items carry the rings per block in .w; lds_bytes = 2 * rpb * L * sizeof(complex)
-// Rings of length 512 (B = 256) run in a kernel of their own (big = true) so that
-// their register footprint does not lower the occupancy of the other lengths.
-// max_grid bounds the persistent grid (0 = the default bound).
+// stage (a) work items carry the rings per block in .w; lds_bytes is the largest
+// fft_lds_bytes_for over the rings of the launch
+// Stage (a) runs as up to three kernels by ring-length family (mode 0: power-of-two
+// rings up to 256 points and the generic path; mode 1: 32 x 16 register FFTs,
+// i.e. 512-point rings and Bluestein length 512; mode 2: Bluestein with M <= 256)
+// so that each gets only the registers its FFT size needs.  max_grid bounds the
+// persistent grid (0 = the default bound).
 hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, bool big, const void* samples, int max_grid, hipStream_t s);
+                              int lds_bytes, int mode, const void* samples, int max_grid, hipStream_t s);
 hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
-                              int lds_bytes, bool big, void* samples, int max_grid, hipStream_t s);
-void prepare_fft_kernels(int lds_small, int lds_big);
+                              int lds_bytes, int mode, void* samples, int max_grid, hipStream_t s);
+void prepare_fft_kernels(const int* lds_per_mode);
 size_t fft_lds_bytes_for(int prec, int rpb, int L);
 // power-of-two ring lengths 16..512 take the register four-step path; its rings
 // per block are 256 / R1 with L = R1 * R2, R1 = R2 or 2 R2.
 __host__ __device__ inline bool fft_pow2_path(int L) { return L >= 16 && L <= 512 && (L & (L - 1)) == 0; }
+// Bluestein convolution length for ring length L (0 if L takes another path)
+__host__ __device__ inline int fft_bluestein_m(int L) {
+  if (fft_pow2_path(L) || L < 6 || L > 256 || (L & (L - 1)) == 0) return 0;
+  int M = 16;
+  while (M < 2 * L - 1) M <<= 1;
+  return M;
+}
+inline int fft_mode(int L) {
+  if (L == 512) return 1;
+  const int M = fft_bluestein_m(L);
+  return M == 0 ? 0 : (M == 512 ? 1 : 2);
+}
 inline int fft_pow2_rpb(int L) {
   int r1 = 1;
   while (r1 * r1 < L) r1 <<= 1;  // R1 = sqrt(L) or sqrt(2L)
@@ -117,6 +141,9 @@ sgl_status_t build_grid(GridBuild& g, hipStream_t s);
 hipError_t build_tables(int B, const double* r, const double* log_sig, const double* theta, double* P64,
                         double* R64, hipStream_t s);
 hipError_t build_twiddles(int L, void* tw, bool f32, hipStream_t s);
+// FP64 Bluestein tables for ring length L and convolution length M (see ClassDesc),
+// written in FP64 (f32 = false) or rounded to FP32.
+hipError_t build_bluestein(int L, int M, void* chirp, void* bhf, void* bhi, bool f32, hipStream_t s);
 hipError_t convert_table_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 hipError_t convert_table_split(const double* src, uint16_t* dst, int64_t n, hipStream_t s);
 // Pack an FP64 natural table (Legendre for kind 0/1, radial for kind 2/3) into the

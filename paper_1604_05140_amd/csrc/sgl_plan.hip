@@ -33,6 +33,11 @@ struct ClassHost {
   int64_t* coff = nullptr;
   int rpb = 1;
   std::vector<int> radices;
+  int M = 0;  // Bluestein length (0 = not used)
+  void* twM = nullptr;
+  void* chirp = nullptr;
+  void* bhf = nullptr;
+  void* bhi = nullptr;
 };
 
 std::vector<int> fft_radices(int L) {
@@ -63,10 +68,10 @@ struct sgl_plan_s {
   ClassDesc* d_cls = nullptr;
   int4* d_work = nullptr;
   int off_a = 0, n_a = 0, off_bf = 0, n_bf = 0, off_bi = 0, n_bi = 0, off_cf = 0, n_cf = 0, off_ci = 0, n_ci = 0;
-  int off_a2 = 0, n_a2 = 0;  // stage (a) items of length-512 rings
-  int lds_a = 0, lds_a2 = 0;
+  // stage (a) work by FFT mode (see fft_mode): offsets, counts, LDS bytes
+  int off_am[3] = {0, 0, 0}, n_am[3] = {0, 0, 0}, lds_am[3] = {0, 0, 0};
   // persistent grid bound per launch slot (0 = kernel default; set by the autotuner)
-  int grid[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int grid[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // captured launch sequences, keyed by (direction, input, output)
   struct GraphEntry {
     int dir;
@@ -147,8 +152,18 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
     SGL_HIP_TRY(pack_table(B, kind, prec, kind < 2 ? c.P64 : c.R64, c.Aoff[kind], c.A[kind], tot, s));
   }
   const bool f32 = p->dtype != SGL_F64;
-  SGL_TRY(p->alloc(&c.tw, (size_t)L * (f32 ? sizeof(float2) : sizeof(double2))));
+  const size_t ces = f32 ? sizeof(float2) : sizeof(double2);
+  SGL_TRY(p->alloc(&c.tw, (size_t)L * ces));
   SGL_HIP_TRY(build_twiddles(L, c.tw, f32, s));
+  c.M = fft_bluestein_m(L);
+  if (c.M) {
+    SGL_TRY(p->alloc(&c.twM, (size_t)c.M * ces));
+    SGL_HIP_TRY(build_twiddles(c.M, c.twM, f32, s));
+    SGL_TRY(p->alloc(&c.chirp, (size_t)L * ces));
+    SGL_TRY(p->alloc(&c.bhf, (size_t)c.M * ces));
+    SGL_TRY(p->alloc(&c.bhi, (size_t)c.M * ces));
+    SGL_HIP_TRY(build_bluestein(L, c.M, c.chirp, c.bhf, c.bhi, f32, s));
+  }
   c.radices = fft_radices(L);
   if ((int)c.radices.size() > kMaxRadices) {
     set_error("FFT length has too many factors");
@@ -168,6 +183,8 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
   SGL_HIP_TRY(hipMemcpyAsync(c.coff, co.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice, s));
   if (fft_pow2_path(L)) {
     c.rpb = fft_pow2_rpb(L);
+  } else if (c.M) {
+    c.rpb = fft_pow2_rpb(c.M);
   } else {
     // rings per generic-FFT block: 64 KB of LDS for the ping-pong buffers
     const int cap = (int)(65536 / (2 * (size_t)L * es));
@@ -178,20 +195,19 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
 
 sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
   const int BM = gemm_tile_m(), BNC = gemm_tile_n_complex();
-  std::vector<int4> wa, wa2, wbf, wbi, wcf, wci;
+  std::vector<int4> wam[3], wbf, wbi, wcf, wci;
   struct Item { int cost; int4 w; };
   std::vector<Item> bf, bi, cf, ci;
-  int lds = 0, lds2 = 0;
+  int ldsm[3] = {0, 0, 0};
   for (int ci_ = 0; ci_ < (int)p->classes.size(); ++ci_) {
     const ClassHost& c = p->classes[ci_];
     const int B = c.B, L = 2 * B, nf = (int)c.funcs.size();
     const int ncol = nf * L;
     const int ncb = (ncol + c.rpb - 1) / c.rpb;
-    std::vector<int4>& dst = L == 512 ? wa2 : wa;
+    const int mode = fft_mode(L);
     for (int j = 0; j < L; ++j)
-      for (int cb = 0; cb < ncb; ++cb) dst.push_back(make_int4(ci_, j, cb, c.rpb));
-    int& lmax = L == 512 ? lds2 : lds;
-    lmax = std::max(lmax, (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
+      for (int cb = 0; cb < ncb; ++cb) wam[mode].push_back(make_int4(ci_, j, cb, c.rpb));
+    ldsm[mode] = std::max(ldsm[mode], (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
     for (int m = 0; m < B; ++m) {
       const int rows = B - m;
       const int ncc = (m ? 2 : 1) * nf * L;
@@ -222,16 +238,19 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
   order(cf, wcf);
   order(ci, wci);
   std::vector<int4> all;
-  p->off_a = 0; p->n_a = (int)wa.size(); all.insert(all.end(), wa.begin(), wa.end());
-  p->off_a2 = (int)all.size(); p->n_a2 = (int)wa2.size(); all.insert(all.end(), wa2.begin(), wa2.end());
+  for (int md = 0; md < 3; ++md) {
+    p->off_am[md] = (int)all.size();
+    p->n_am[md] = (int)wam[md].size();
+    p->lds_am[md] = ldsm[md];
+    all.insert(all.end(), wam[md].begin(), wam[md].end());
+  }
   p->off_bf = (int)all.size(); p->n_bf = (int)wbf.size(); all.insert(all.end(), wbf.begin(), wbf.end());
   p->off_bi = (int)all.size(); p->n_bi = (int)wbi.size(); all.insert(all.end(), wbi.begin(), wbi.end());
   p->off_cf = (int)all.size(); p->n_cf = (int)wcf.size(); all.insert(all.end(), wcf.begin(), wcf.end());
   p->off_ci = (int)all.size(); p->n_ci = (int)wci.size(); all.insert(all.end(), wci.begin(), wci.end());
   SGL_TRY(p->alloc((void**)&p->d_work, all.size() * sizeof(int4)));
   SGL_HIP_TRY(hipMemcpyAsync(p->d_work, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-  p->lds_a = lds;
-  p->lds_a2 = lds2;
+
   return SGL_OK;
 }
 
@@ -265,6 +284,11 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
     d.btilde = c.grid + 5 * d.L;
     d.sigma = c.grid + 3 * d.L;
     d.tw = c.tw;
+    d.M = c.M;
+    d.twM = c.twM;
+    d.chirp = c.chirp;
+    d.bhf = c.bhf;
+    d.bhi = c.bhi;
     d.F = c.F;
     d.g = c.g;
     descs.push_back(d);
@@ -272,7 +296,7 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
   SGL_TRY(p->alloc((void**)&p->d_cls, descs.size() * sizeof(ClassDesc)));
   SGL_HIP_TRY(hipMemcpyAsync(p->d_cls, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice, s));
   SGL_TRY(build_work(p, s));
-  prepare_fft_kernels(p->lds_a, p->lds_a2);
+  prepare_fft_kernels(p->lds_am);
   if (p->flags & SGL_GRAPHS) SGL_HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
   SGL_HIP_TRY(hipStreamSynchronize(s));
   return SGL_OK;
@@ -315,15 +339,20 @@ sgl_status_t check_call(sgl_plan_t plan, const void* in, size_t nin, const void*
   return SGL_OK;
 }
 
-enum Slot { S_FFT_F = 0, S_FFT_F_BIG, S_LEG_F, S_RAD_F, S_RAD_I, S_LEG_I, S_FFT_I, S_FFT_I_BIG, NSLOT };
+enum Slot {
+  S_FFT_F0 = 0, S_FFT_F1, S_FFT_F2, S_LEG_F, S_RAD_F,
+  S_RAD_I, S_LEG_I, S_FFT_I0, S_FFT_I1, S_FFT_I2, NSLOT
+};
 // launch order and timing stage of each direction
-const int kSeq[2][4] = {{S_FFT_F, S_FFT_F_BIG, S_LEG_F, S_RAD_F}, {S_RAD_I, S_LEG_I, S_FFT_I, S_FFT_I_BIG}};
-const int kStage[2][4] = {{0, 0, 1, 2}, {3, 4, 5, 5}};
+const int kSeq[2][5] = {{S_FFT_F0, S_FFT_F1, S_FFT_F2, S_LEG_F, S_RAD_F},
+                        {S_RAD_I, S_LEG_I, S_FFT_I0, S_FFT_I1, S_FFT_I2}};
+const int kStage[2][5] = {{0, 0, 0, 1, 2}, {3, 4, 5, 5, 5}};
 
 int slot_work(const sgl_plan_s* p, int slot) {
   switch (slot) {
-    case S_FFT_F: case S_FFT_I: return p->n_a;
-    case S_FFT_F_BIG: case S_FFT_I_BIG: return p->n_a2;
+    case S_FFT_F0: case S_FFT_I0: return p->n_am[0];
+    case S_FFT_F1: case S_FFT_I1: return p->n_am[1];
+    case S_FFT_F2: case S_FFT_I2: return p->n_am[2];
     case S_LEG_F: return p->n_bf;
     case S_LEG_I: return p->n_bi;
     case S_RAD_F: return p->n_cf;
@@ -337,28 +366,30 @@ hipError_t launch_slot(sgl_plan_s* p, int slot, const void* in, void* out, hipSt
   const bool raw = (p->flags & SGL_SAMPLES_RAW) != 0;
   const int g = p->grid[slot];
   switch (slot) {
-    case S_FFT_F:
-      return launch_fft_forward(prec, raw, p->d_cls, p->d_work + p->off_a, p->n_a, p->lds_a, false, in, g, s);
-    case S_FFT_F_BIG:
-      return launch_fft_forward(prec, raw, p->d_cls, p->d_work + p->off_a2, p->n_a2, p->lds_a2, true, in, g, s);
+    case S_FFT_F0: case S_FFT_F1: case S_FFT_F2: {
+      const int md = slot - S_FFT_F0;
+      return launch_fft_forward(prec, raw, p->d_cls, p->d_work + p->off_am[md], p->n_am[md], p->lds_am[md], md, in,
+                                g, s);
+    }
+    case S_FFT_I0: case S_FFT_I1: case S_FFT_I2: {
+      const int md = slot - S_FFT_I0;
+      return launch_fft_inverse(prec, raw, p->d_cls, p->d_work + p->off_am[md], p->n_am[md], p->lds_am[md], md, out,
+                                g, s);
+    }
     case S_LEG_F:
       return launch_legendre(prec, false, p->d_cls, p->d_work + p->off_bf, p->n_bf, g, s);
     case S_RAD_F:
       return launch_radial(prec, false, p->d_cls, p->d_work + p->off_cf, p->n_cf, nullptr, out, g, s);
     case S_RAD_I:
       return launch_radial(prec, true, p->d_cls, p->d_work + p->off_ci, p->n_ci, in, nullptr, g, s);
-    case S_LEG_I:
-      return launch_legendre(prec, true, p->d_cls, p->d_work + p->off_bi, p->n_bi, g, s);
-    case S_FFT_I:
-      return launch_fft_inverse(prec, raw, p->d_cls, p->d_work + p->off_a, p->n_a, p->lds_a, false, out, g, s);
     default:
-      return launch_fft_inverse(prec, raw, p->d_cls, p->d_work + p->off_a2, p->n_a2, p->lds_a2, true, out, g, s);
+      return launch_legendre(prec, true, p->d_cls, p->d_work + p->off_bi, p->n_bi, g, s);
   }
 }
 
 hipError_t launch_sequence(sgl_plan_s* p, int dir, const void* in, void* out, hipStream_t s, bool timed) {
   int open_stage = -1;
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < 5; ++q) {
     const int slot = kSeq[dir][q];
     if (slot_work(p, slot) == 0) continue;
     const int st = kStage[dir][q];
@@ -437,7 +468,7 @@ sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
   for (int slot = 0; slot < NSLOT && st == SGL_OK; ++slot) {
     const int n = slot_work(p, slot);
     if (n == 0) continue;
-    const bool inv = slot >= S_RAD_I;
+    const bool inv = slot >= S_RAD_I;  // inverse slots read coefficients, write samples
     const void* in = inv ? tout : tin;
     void* out = inv ? tin : tout;
     std::vector<int> cand;

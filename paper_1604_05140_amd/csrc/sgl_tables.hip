@@ -339,6 +339,41 @@ __global__ void k_twiddles_f32(int L, float2* tw) {
   tw[q] = make_float2((float)cospi(a), (float)-sinpi(a));
 }
 
+// Bluestein tables: chirp c_p = exp(-i pi p^2 / L); kernel spectra
+//   bhf[q] = (1/M) sum_n conj(c_|n|) exp(-2 pi i q n / M),  bhi[q] = (1/M) sum_n c_|n| exp(...),
+// with the kernel index n wrapped cyclically (|n| < L, zero elsewhere).
+// Angles are reduced in integers (p^2 mod 2L, qn mod M) before sincospi.
+template <typename T2>
+__global__ void k_bluestein(int L, int M, T2* chirp, T2* bhf, T2* bhi) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < L) {
+    const double a = (double)(((int64_t)q * q) % (2 * L)) / L;
+    chirp[q].x = cospi(a);
+    chirp[q].y = -sinpi(a);
+  }
+  if (q >= M) return;
+  double fr = 0, fi = 0, ir = 0, ii = 0;
+  for (int n = 0; n < M; ++n) {
+    int t;
+    if (n < L) t = n;
+    else if (n > M - L) t = M - n;
+    else continue;
+    const double ca = (double)(((int64_t)t * t) % (2 * L)) / L;  // c_t = exp(-i pi ca)
+    const double cr = cospi(ca), ci = -sinpi(ca);
+    const double wa = 2.0 * (double)(((int64_t)q * n) % M) / M;  // exp(-i pi wa)
+    const double wr = cospi(wa), wi = -sinpi(wa);
+    // forward kernel conj(c_t), inverse kernel c_t
+    fr += cr * wr + ci * wi;
+    fi += cr * wi - ci * wr;
+    ir += cr * wr - ci * wi;
+    ii += cr * wi + ci * wr;
+  }
+  bhf[q].x = fr / M;
+  bhf[q].y = fi / M;
+  bhi[q].x = ir / M;
+  bhi[q].y = ii / M;
+}
+
 __global__ void k_to_f32(const double* src, float* dst, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (float)src[i];
@@ -484,6 +519,17 @@ hipError_t build_twiddles(int L, void* tw, bool f32, hipStream_t s) {
     hipLaunchKernelGGL(k_twiddles_f32, dim3(nblk(L, 128)), dim3(128), 0, s, L, (float2*)tw);
   else
     hipLaunchKernelGGL(k_twiddles, dim3(nblk(L, 128)), dim3(128), 0, s, L, (double2*)tw);
+  return hipGetLastError();
+}
+
+hipError_t build_bluestein(int L, int M, void* chirp, void* bhf, void* bhi, bool f32, hipStream_t s) {
+  const int n = L > M ? L : M;
+  if (f32)
+    hipLaunchKernelGGL(k_bluestein<float2>, dim3(nblk(n, 64)), dim3(64), 0, s, L, M, (float2*)chirp, (float2*)bhf,
+                       (float2*)bhi);
+  else
+    hipLaunchKernelGGL(k_bluestein<double2>, dim3(nblk(n, 64)), dim3(64), 0, s, L, M, (double2*)chirp,
+                       (double2*)bhf, (double2*)bhi);
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ SGL_SAMPLES_RAW = 1
 SGL_GRAPHS = 2
 SGL_AUTOTUNE = 4
 SGL_MAX_B = 256
+SGL_NUM_SLOTS = 10
 DTYPES = {"f64": SGL_F64, "f32": SGL_F32, "split_bf16": SGL_SPLIT_BF16}
 
 _lib = None
@@ -159,7 +160,7 @@ class Plan:
         return out
 
     def launch_grids(self):
-        g = (ctypes.c_int * 8)()
+        g = (ctypes.c_int * SGL_NUM_SLOTS)()
         _check(_load().sgl_launch_grids(self._h, g), "sgl_launch_grids")
         return list(g)
 

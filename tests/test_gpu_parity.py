@@ -319,7 +319,10 @@ def test_autotuned_plan_matches_default():
         p0 = sgl.sgl_plan(B, batch, dtype)
         p1 = sgl.sgl_plan_ex([B] * batch, dtype, sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS)
         grids = p1.launch_grids()
-        assert all(g >= 1 for g in grids[:1] + grids[2:6]), grids
+        assert len(grids) == sgl.SGL_NUM_SLOTS
+        # B = 16: 32-point rings (slot 0 / 7); no 512-point or Bluestein rings
+        assert all(g >= 1 for g in grids[:1] + grids[3:8]), grids
+        assert grids[1] == grids[2] == grids[8] == grids[9] == 0, grids
         assert torch.equal(gpu_forward(p0, s), gpu_forward(p1, s))
         assert torch.equal(gpu_inverse(p0, c), gpu_inverse(p1, c))
 
