@@ -24,12 +24,13 @@
 //     of chunk c, so each load has two MFMA phases to arrive;
 //   * the table operand comes pre-packed per direction (row-major, K padded to
 //     a multiple of 64 with zeros), so every table load is a 16-byte vector;
-//   * data-operand loads follow the layout the previous stage wrote (16-byte
-//     runs along the contiguous index), are transposed in registers so that
-//     each lane holds 8 consecutive k of one column, and go to LDS as [column][k]
-//     (one 16-byte LDS store per column and bf16 plane);
-//   * the epilogue stages the tile through LDS and writes the next stage's
-//     layout with coalesced 16-byte stores:
+//   * data-operand loads follow the layout the previous stage wrote: each
+//     lane holds 8 consecutive k of one column (index offsets in 32-bit
+//     arithmetic from a per-column pointer), and the chunk goes to LDS as
+//     [column][k] (one 16-byte LDS store per column and bf16 plane); loads
+//     past the group are clamped instead of branched around;
+//   * the epilogue writes the accumulators straight into the next stage's
+//     layout (each store instruction covers 64-byte runs of 4 rows):
 //       F    [(m+B-1)][j][b*2B+i]                 (stage a <-> b)
 //       g    [l][b][m+l][i], block l at l^2 nf 2B  (stage b <-> c)
 //       fhat [b][omega]                             (stage c <-> caller)
@@ -51,13 +52,13 @@ constexpr int BK = 64;       // contraction chunk
 constexpr int NT = 512;      // 8 waves, 2 x 4 layout of 64 x 32
 constexpr int PS = BK + 8;   // bf16 LDS pitch (80 bytes)
 constexpr int PF = BK + 4;   // f32/f64 LDS pitch in elements
-constexpr int EP = BN + 1;   // epilogue tile pitch (elements)
 
 enum Kind { K_B_FWD = 0, K_B_INV = 1, K_C_FWD = 2, K_C_INV = 3, K_DEBUG = 4 };
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));  // 16-byte operand vector
 
 template <int PREC> struct DT { using t = float; };
 template <> struct DT<PREC_F64> { using t = double; };
@@ -74,14 +75,12 @@ __device__ inline float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) 
 template <int PREC> struct Lds {
   static constexpr int a = BM * PF * (int)sizeof(typename DT<PREC>::t);
   static constexpr int x = BN * PF * (int)sizeof(typename DT<PREC>::t);
-  static constexpr int ep = 64 * EP * (int)sizeof(typename DT<PREC>::t);
-  static constexpr int total = (a + x) > ep ? (a + x) : ep;
+  static constexpr int total = a + x;
 };
 template <> struct Lds<PREC_SPLIT> {
   static constexpr int a = 3 * BM * PS * 2;
   static constexpr int x = 3 * BN * PS * 2;
-  static constexpr int ep = 64 * EP * 4;
-  static constexpr int total = (a + x) > ep ? (a + x) : ep;
+  static constexpr int total = a + x;
 };
 
 struct DebugArgs {
@@ -97,54 +96,92 @@ struct Tile {
   int q;           // m (stage b) or l (stage c)
   int pitch;       // packed table row pitch
   const ClassDesc* C;
+  const void* tab;  // packed table block (stage kinds)
+  int64_t plane;    // split-plane stride of the packed table (elements)
 };
 
-__device__ inline int64_t gbase(int l, int nf, int L) { return (int64_t)l * l * nf * L; }
+template <int PREC, int KIND>
+__device__ inline Tile make_tile(const ClassDesc* cls, const int4* work, int w, const DebugArgs& dbg) {
+  using T = typename DT<PREC>::t;
+  Tile t;
+  if constexpr (KIND == K_DEBUG) {
+    const int ntn = (dbg.N + BN - 1) / BN;
+    t.M = dbg.M;
+    t.K = dbg.K;
+    t.Ncc = (dbg.N + 1) / 2;
+    t.row0 = (w / ntn) * BM;
+    t.col0 = (w % ntn) * BNC;
+    t.q = 0;
+    t.pitch = 0;
+    t.C = nullptr;
+    t.tab = nullptr;
+    t.plane = 0;
+  } else {
+    const int4 it = work[w];
+    const ClassDesc& C = cls[it.x];
+    t.C = &C;
+    t.q = it.y;
+    const int B = C.B, L = C.L;
+    const int rows = B - t.q;
+    if constexpr (KIND == K_B_FWD || KIND == K_B_INV)
+      t.Ncc = (t.q ? 2 : 1) * C.nf * L;
+    else
+      t.Ncc = (2 * t.q + 1) * C.nf;
+    constexpr bool fwd = KIND == K_B_FWD || KIND == K_C_FWD;
+    t.M = fwd ? rows : L;
+    t.K = fwd ? L : rows;
+    t.pitch = (t.K + BK - 1) / BK * BK;
+    t.plane = C.Aplane[KIND];
+    t.tab = reinterpret_cast<const unsigned char*>(C.A[KIND]) +
+            C.Aoff[KIND][t.q] * (int64_t)(PREC == PREC_SPLIT ? 2 : sizeof(T));
+    t.row0 = it.z * BM;
+    t.col0 = it.w * BNC;
+  }
+  return t;
+}
 
 // ---- per-thread register staging of one K chunk -----------------------------
-// A: split -> 6 x uint4 (3 planes x 2 vectors); f32 -> 4 x float4; f64 -> 8 x double2.
+// A: split -> 6 x 16 bytes (3 planes x 2 vectors); f32 -> 4 x float4; f64 -> 8 x double2.
 // X: 8 consecutive k of one complex column -> 8 complex values.
 template <int PREC> struct Stage {
   static constexpr int NA = PREC == PREC_SPLIT ? 6 : (PREC == PREC_F32 ? 4 : 8);
-  uint4 a[NA];
+  u4 a[NA];
   typename DT<PREC>::t xr[8], xi[8];
 };
 
-// A chunk: BM rows x BK (padded, zero filled) from a packed table block.
+// A chunk: BM rows x BK from a packed table block.  Rows past the block are
+// clamped to its last row: they feed only output rows that are never stored.
 template <int PREC>
-__device__ inline void load_a(Stage<PREC>& st, const Tile& t, const void* tab, int64_t plane, int k0, int tid) {
+__device__ inline void load_a(Stage<PREC>& st, const Tile& t, int k0, int tid) {
+  const int rmax = t.M - 1;
   if constexpr (PREC == PREC_SPLIT) {
     // 3 planes x 128 rows x 8 vectors of 8 bf16
+    const uint16_t* tab = reinterpret_cast<const uint16_t*>(t.tab);
+#pragma unroll
     for (int v = 0; v < 6; ++v) {
       const int e = tid + v * NT;  // 0..3071
       const int p = e >> 10, rem = e & 1023;
       const int r = rem >> 3, kg = rem & 7;
-      const int gr = t.row0 + r;
-      uint4 z = make_uint4(0, 0, 0, 0);
-      if (gr < t.M)
-        z = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint16_t*>(tab) + p * plane +
-                                            (int64_t)gr * t.pitch + k0 + kg * 8);
-      st.a[v] = z;
+      const int gr = min(t.row0 + r, rmax);
+      st.a[v] = *reinterpret_cast<const u4*>(tab + p * t.plane + (int64_t)gr * t.pitch + k0 + kg * 8);
     }
   } else if constexpr (PREC == PREC_F32) {
+    const float* tab = reinterpret_cast<const float*>(t.tab);
+#pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int e = tid + v * NT;  // 128 rows x 16 vectors of 4 floats
       const int r = e >> 4, kg = e & 15;
-      const int gr = t.row0 + r;
-      uint4 z = make_uint4(0, 0, 0, 0);
-      if (gr < t.M)
-        z = *reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(tab) + (int64_t)gr * t.pitch + k0 + kg * 4);
-      st.a[v] = z;
+      const int gr = min(t.row0 + r, rmax);
+      st.a[v] = *reinterpret_cast<const u4*>(tab + (int64_t)gr * t.pitch + k0 + kg * 4);
     }
   } else {
+    const double* tab = reinterpret_cast<const double*>(t.tab);
+#pragma unroll
     for (int v = 0; v < 8; ++v) {
       const int e = tid + v * NT;  // 128 rows x 32 vectors of 2 doubles
       const int r = e >> 5, kg = e & 31;
-      const int gr = t.row0 + r;
-      uint4 z = make_uint4(0, 0, 0, 0);
-      if (gr < t.M)
-        z = *reinterpret_cast<const uint4*>(reinterpret_cast<const double*>(tab) + (int64_t)gr * t.pitch + k0 + kg * 2);
-      st.a[v] = z;
+      const int gr = min(t.row0 + r, rmax);
+      st.a[v] = *reinterpret_cast<const u4*>(tab + (int64_t)gr * t.pitch + k0 + kg * 2);
     }
   }
 }
@@ -153,98 +190,109 @@ template <int PREC>
 __device__ inline void store_a(const Stage<PREC>& st, unsigned char* sm, int tid) {
   if constexpr (PREC == PREC_SPLIT) {
     uint16_t* As = reinterpret_cast<uint16_t*>(sm);
+#pragma unroll
     for (int v = 0; v < 6; ++v) {
       const int e = tid + v * NT;
       const int p = e >> 10, rem = e & 1023;
       const int r = rem >> 3, kg = rem & 7;
-      *reinterpret_cast<uint4*>(&As[(p * BM + r) * PS + kg * 8]) = st.a[v];
+      *reinterpret_cast<u4*>(&As[(p * BM + r) * PS + kg * 8]) = st.a[v];
     }
   } else if constexpr (PREC == PREC_F32) {
     float* As = reinterpret_cast<float*>(sm);
+#pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int e = tid + v * NT;
       const int r = e >> 4, kg = e & 15;
-      *reinterpret_cast<uint4*>(&As[r * PF + kg * 4]) = st.a[v];
+      *reinterpret_cast<u4*>(&As[r * PF + kg * 4]) = st.a[v];
     }
   } else {
     double* As = reinterpret_cast<double*>(sm);
+#pragma unroll
     for (int v = 0; v < 8; ++v) {
       const int e = tid + v * NT;
       const int r = e >> 5, kg = e & 31;
-      *reinterpret_cast<uint4*>(&As[r * PF + kg * 2]) = st.a[v];
+      *reinterpret_cast<u4*>(&As[r * PF + kg * 2]) = st.a[v];
     }
   }
 }
 
-// Per-thread decode of one data-operand column, done once per tile: the complex
-// index of element (k, c) is then a cheap function of k.
+// One complex column of a stage operand (the data operand X of a kind, or the
+// output of the opposite kind, which has the same layout): element (k, c) sits
+// at p[2 * off(k)], p[2 * off(k) + 1] with a 32-bit offset off(k) (x_off) from a
+// 64-bit column pointer.  Class workspaces hold fewer than 2^31 complex values.
+//   K_B_FWD  F[(m+B-1)][j = k][b 2B + i]:   off = k * a,              a = nf 2B
+//   K_B_INV  g[l = m + k][b][m + l][i]:     off = l (l a + b),        a = nf 2B, b = (2b+1) 2B
+//   K_C_FWD  g[l][b][m + l][i = k]:         off = k
+//   K_C_INV  fhat[b][omega(n = l+1+k, l, m)]: off = n (n-1) (2n-1) / 6
+template <typename T>
 struct XCol {
-  int64_t base;  // index at k = 0 (linear kinds) or the constant term
-  int64_t s1;    // linear coefficient
-  int64_t s2;    // quadratic coefficient (stage-b inverse)
-  int ok;        // column inside the group
+  T* p;
+  int a, b;
+  T sgn;  // (-1)^m on the -m segment of stage b, else 1
 };
 
-template <int KIND>
-__device__ inline XCol x_col(const Tile& t, int c) {
-  XCol x{0, 0, 0, c < t.Ncc};
-  if constexpr (KIND != K_DEBUG) {
-    if (!x.ok) return x;
-    const ClassDesc& C = *t.C;
-    const int B = C.B, L = C.L, nf = C.nf;
+template <int KIND, typename T>
+__device__ inline XCol<T> x_col(const Tile& t, int c, T* base) {
+  XCol<T> x{base, 0, 0, (T)1};
+  const ClassDesc& C = *t.C;
+  const int B = C.B, L = C.L, nf = C.nf;
+  if constexpr (KIND == K_B_FWD || KIND == K_B_INV) {
+    const int ncf = nf * L;
+    const int seg = c >= ncf;
+    const int cp = c - seg * ncf;
+    const int mp = seg ? -t.q : t.q;
+    if (seg && (t.q & 1)) x.sgn = (T)-1;
     if constexpr (KIND == K_B_FWD) {
-      const int ncf = nf * L;
-      const int seg = c >= ncf;
-      const int cp = c - seg * ncf;
-      const int mp = seg ? -t.q : t.q;
-      x.base = (int64_t)(mp + B - 1) * L * ncf + cp;  // + k * ncf
-      x.s1 = ncf;
-    } else if constexpr (KIND == K_B_INV) {
-      // element (k, c) sits at g[l][b][mp+l][i], l = q + k:
-      //   l^2 nf L + (2b+1) L l + (b+mp) L + i
-      const int ncf = nf * L;
-      const int seg = c >= ncf;
-      const int cp = c - seg * ncf;
-      const int mp = seg ? -t.q : t.q;
+      x.p = base + 2 * ((int64_t)(mp + B - 1) * L * ncf + cp);
+      x.a = ncf;
+    } else {
       const int b = cp / L, i = cp - b * L;
-      x.s2 = (int64_t)nf * L;
-      x.s1 = (int64_t)(2 * b + 1) * L;
-      x.base = (int64_t)(b + mp) * L + i;
-    } else if constexpr (KIND == K_C_FWD) {
-      x.base = gbase(t.q, nf, L) + (int64_t)c * L;  // + k
-      x.s1 = 1;
-    } else {  // K_C_INV: coefficient (n = q+1+k, q, m) of function b
-      const int l = t.q;
-      const int b = c / (2 * l + 1);
-      const int m = c - b * (2 * l + 1) - l;
-      x.base = C.coff[b] + (int64_t)l * (l + 1) + m;  // + omega(n, 0, 0)
+      x.p = base + 2 * ((int64_t)(b + mp) * L + i);
+      x.a = nf * L;
+      x.b = (2 * b + 1) * L;
     }
+  } else if constexpr (KIND == K_C_FWD) {
+    x.p = base + 2 * ((int64_t)t.q * t.q * nf * L + (int64_t)c * L);
+  } else {  // K_C_INV
+    const int l = t.q;
+    const int b = c / (2 * l + 1);
+    const int m = c - b * (2 * l + 1) - l;
+    x.p = base + 2 * (C.coff[b] + (int64_t)l * (l + 1) + m);
   }
   return x;
 }
 
-template <int KIND>
-__device__ inline int64_t x_at(const Tile& t, const XCol& x, int k) {
-  if constexpr (KIND == K_B_INV) {
-    const int64_t l = t.q + k;
-    return x.base + l * (x.s1 + l * x.s2);
-  } else if constexpr (KIND == K_C_INV) {
-    const int64_t n = t.q + 1 + k;
-    return x.base + n * (n - 1) * (2 * n - 1) / 6;
+template <int KIND, typename T>
+__device__ inline int x_off(const Tile& t, const XCol<T>& x, int k) {
+  if constexpr (KIND == K_B_FWD) {
+    return k * x.a;
+  } else if constexpr (KIND == K_B_INV) {
+    const int l = t.q + k;
+    return l * (l * x.a + x.b);
+  } else if constexpr (KIND == K_C_FWD) {
+    return k;
   } else {
-    return x.base + (int64_t)k * x.s1;
+    const int n = t.q + 1 + k;
+    return n * (n - 1) * (2 * n - 1) / 6;
   }
 }
 
-// X chunk: thread -> (complex column cc = tid & 63, k group kg = tid >> 6 of 8 rows)
+template <typename T> struct V2 { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+// X chunk: thread -> (complex column cc = tid & 63, k group kg = tid >> 6 of 8
+// rows).  Columns and rows past the group are clamped to its last ones: the
+// packed tables are zero past K, and extra columns are never stored.
 template <int PREC, int KIND>
-__device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol& xc, const void* xbase,
+__device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol<typename DT<PREC>::t>& xc,
                               const DebugArgs& dbg, int k0, int tid) {
   using T = typename DT<PREC>::t;
-  const int cc = tid & 63, kg = tid >> 6;
-  const int c = t.col0 + cc;
+  using T2 = typename V2<T>::t;
+  const int kg = tid >> 6;
   const int kb = k0 + kg * 8;
   if constexpr (KIND == K_DEBUG) {
+    const int c = t.col0 + (tid & 63);
+#pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int k = kb + u;
       const int n0 = 2 * c, n1 = 2 * c + 1;
@@ -253,34 +301,28 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol& xc, co
       st.xi[u] = (ok && n1 < dbg.N) ? (T)dbg.X[(int64_t)k * dbg.N + n1] : (T)0;
     }
   } else {
-    const T* X = reinterpret_cast<const T*>(xbase);
-    if (xc.ok) {
-      if constexpr (KIND == K_C_FWD) {
+    const int kmax = t.K - 1;
+    if constexpr (KIND == K_C_FWD && PREC != PREC_F64) {
+      if (kb + 8 <= t.K) {
         // 8 consecutive k of one column are contiguous (g rows run along i)
-        const int64_t ix = x_at<KIND>(t, xc, kb);
-        for (int u = 0; u < 8; ++u) {
-          const bool ok = kb + u < t.K;
-          st.xr[u] = ok ? X[2 * (ix + u)] : (T)0;
-          st.xi[u] = ok ? X[2 * (ix + u) + 1] : (T)0;
+        const float4* src = reinterpret_cast<const float4*>(xc.p + 2 * kb);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float4 v = src[u];
+          st.xr[2 * u] = v.x;
+          st.xi[2 * u] = v.y;
+          st.xr[2 * u + 1] = v.z;
+          st.xi[2 * u + 1] = v.w;
         }
-      } else {
-        for (int u = 0; u < 8; ++u) {
-          const int k = kb + u;
-          if (k < t.K) {
-            const int64_t ix = x_at<KIND>(t, xc, k);
-            st.xr[u] = X[2 * ix];
-            st.xi[u] = X[2 * ix + 1];
-          } else {
-            st.xr[u] = 0;
-            st.xi[u] = 0;
-          }
-        }
+        return;
       }
-    } else {
-      for (int u = 0; u < 8; ++u) {
-        st.xr[u] = 0;
-        st.xi[u] = 0;
-      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = min(kb + u, kmax);
+      const T2 v = *reinterpret_cast<const T2*>(xc.p + 2 * x_off<KIND>(t, xc, k));
+      st.xr[u] = v.x;
+      st.xi[u] = v.y;
     }
   }
 }
@@ -298,43 +340,59 @@ __device__ inline void split3(float v, uint32_t& h0, uint32_t& h1, uint32_t& h2)
 // pack the high halves of two FP32 patterns into one dword (lo element first)
 __device__ inline uint32_t pack_hi(uint32_t lo, uint32_t hi) { return __builtin_amdgcn_perm(hi, lo, 0x07060302u); }
 
+// X chunk to LDS as [column][k]; sgn carries the (-1)^m of the -m segment.
 template <int PREC>
-__device__ inline void store_x(const Stage<PREC>& st, unsigned char* sm, int tid) {
+__device__ inline void store_x(const Stage<PREC>& st, typename DT<PREC>::t sgn, unsigned char* sm, int tid) {
   const int cc = tid & 63, kg = tid >> 6;
   if constexpr (PREC == PREC_SPLIT) {
     uint16_t* Xs = reinterpret_cast<uint16_t*>(sm + Lds<PREC>::a);
+#pragma unroll
     for (int part = 0; part < 2; ++part) {
       uint32_t h[3][8];
-      for (int u = 0; u < 8; ++u) split3(part ? st.xi[u] : st.xr[u], h[0][u], h[1][u], h[2][u]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) split3(sgn * (part ? st.xi[u] : st.xr[u]), h[0][u], h[1][u], h[2][u]);
+#pragma unroll
       for (int p = 0; p < 3; ++p) {
-        uint4 w;
-        w.x = pack_hi(h[p][0], h[p][1]);
-        w.y = pack_hi(h[p][2], h[p][3]);
-        w.z = pack_hi(h[p][4], h[p][5]);
-        w.w = pack_hi(h[p][6], h[p][7]);
-        *reinterpret_cast<uint4*>(&Xs[(p * BN + 2 * cc + part) * PS + kg * 8]) = w;
+        const u4 w = {pack_hi(h[p][0], h[p][1]), pack_hi(h[p][2], h[p][3]), pack_hi(h[p][4], h[p][5]),
+                      pack_hi(h[p][6], h[p][7])};
+        *reinterpret_cast<u4*>(&Xs[(p * BN + 2 * cc + part) * PS + kg * 8]) = w;
       }
     }
   } else if constexpr (PREC == PREC_F32) {
     float* Xs = reinterpret_cast<float*>(sm + Lds<PREC>::a);
     float* r0 = &Xs[(2 * cc) * PF + kg * 8];
     float* r1 = &Xs[(2 * cc + 1) * PF + kg * 8];
-    *reinterpret_cast<float4*>(r0) = make_float4(st.xr[0], st.xr[1], st.xr[2], st.xr[3]);
-    *reinterpret_cast<float4*>(r0 + 4) = make_float4(st.xr[4], st.xr[5], st.xr[6], st.xr[7]);
-    *reinterpret_cast<float4*>(r1) = make_float4(st.xi[0], st.xi[1], st.xi[2], st.xi[3]);
-    *reinterpret_cast<float4*>(r1 + 4) = make_float4(st.xi[4], st.xi[5], st.xi[6], st.xi[7]);
+    *reinterpret_cast<float4*>(r0) = make_float4(sgn * st.xr[0], sgn * st.xr[1], sgn * st.xr[2], sgn * st.xr[3]);
+    *reinterpret_cast<float4*>(r0 + 4) = make_float4(sgn * st.xr[4], sgn * st.xr[5], sgn * st.xr[6], sgn * st.xr[7]);
+    *reinterpret_cast<float4*>(r1) = make_float4(sgn * st.xi[0], sgn * st.xi[1], sgn * st.xi[2], sgn * st.xi[3]);
+    *reinterpret_cast<float4*>(r1 + 4) = make_float4(sgn * st.xi[4], sgn * st.xi[5], sgn * st.xi[6], sgn * st.xi[7]);
   } else {
     double* Xs = reinterpret_cast<double*>(sm + Lds<PREC>::a);
     double* r0 = &Xs[(2 * cc) * PF + kg * 8];
     double* r1 = &Xs[(2 * cc + 1) * PF + kg * 8];
+#pragma unroll
     for (int u = 0; u < 8; u += 2) {
-      *reinterpret_cast<double2*>(r0 + u) = make_double2(st.xr[u], st.xr[u + 1]);
-      *reinterpret_cast<double2*>(r1 + u) = make_double2(st.xi[u], st.xi[u + 1]);
+      *reinterpret_cast<double2*>(r0 + u) = make_double2(sgn * st.xr[u], sgn * st.xr[u + 1]);
+      *reinterpret_cast<double2*>(r1 + u) = make_double2(sgn * st.xi[u], sgn * st.xi[u + 1]);
     }
   }
 }
 
+template <int PREC, int KIND>
+__device__ inline typename DT<PREC>::t* x_base(const Tile& t, const void* cin) {
+  using T = typename DT<PREC>::t;
+  if constexpr (KIND == K_B_FWD) return reinterpret_cast<T*>(t.C->F);
+  else if constexpr (KIND == K_C_INV) return const_cast<T*>(reinterpret_cast<const T*>(cin));
+  else if constexpr (KIND == K_DEBUG) return nullptr;
+  else return reinterpret_cast<T*>(t.C->g);
+}
+
 // ---- the kernel ------------------------------------------------------------
+// Persistent blocks walk the work list.  Per item: K in chunks of BK through
+// LDS with two register stages; before an item's outputs are written, the
+// first two chunks of the block's next item are already being loaded, so the
+// load latency of short contractions overlaps the stores.  Outputs go straight
+// from the accumulators to the next stage's layout.
 template <int PREC, int KIND>
 __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                              int nwork, const void* __restrict__ cin, void* __restrict__ cout,
@@ -348,47 +406,39 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
   const int lr = lane & 15, lk = lane >> 4;
 
   const int nitems = KIND == K_DEBUG ? ((dbg.M + BM - 1) / BM) * ((dbg.N + BN - 1) / BN) : nwork;
-  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-    Tile t;
-    const void* tab = nullptr;
-    int64_t plane = 0;
-    const void* xbase = nullptr;
-    if constexpr (KIND == K_DEBUG) {
-      const int ntn = (dbg.N + BN - 1) / BN;
-      t.M = dbg.M;
-      t.K = dbg.K;
-      t.Ncc = (dbg.N + 1) / 2;
-      t.row0 = (w / ntn) * BM;
-      t.col0 = (w % ntn) * BNC;
-      t.q = 0;
-      t.pitch = 0;
-      t.C = nullptr;
-    } else {
-      const int4 it = work[w];
-      const ClassDesc& C = cls[it.x];
-      t.C = &C;
-      t.q = it.y;
-      const int B = C.B, L = C.L;
-      const int rows = B - t.q;
-      constexpr int kind = KIND;
-      if constexpr (KIND == K_B_FWD || KIND == K_B_INV)
-        t.Ncc = (t.q ? 2 : 1) * C.nf * L;
-      else
-        t.Ncc = (2 * t.q + 1) * C.nf;
-      const bool fwd = KIND == K_B_FWD || KIND == K_C_FWD;
-      t.M = fwd ? rows : L;
-      t.K = fwd ? L : rows;
-      t.pitch = (t.K + BK - 1) / BK * BK;
-      plane = C.Aplane[kind];
-      tab = reinterpret_cast<const unsigned char*>(C.A[kind]) + C.Aoff[kind][t.q] * (int64_t)(PREC == PREC_SPLIT ? 2 : sizeof(T));
-      t.row0 = it.z * BM;
-      t.col0 = it.w * BNC;
-      xbase = KIND == K_B_FWD ? C.F : (KIND == K_C_INV ? cin : C.g);
-    }
+  int w = blockIdx.x;
+  if (w >= nitems) return;
 
+  auto column = [&](const Tile& tt) {
+    XCol<T> x{nullptr, 0, 0, (T)1};
+    if constexpr (KIND != K_DEBUG) x = x_col<KIND>(tt, min(tt.col0 + (tid & 63), tt.Ncc - 1), x_base<PREC, KIND>(tt, cin));
+    return x;
+  };
+  auto fetch = [&](Stage<PREC>& st, const Tile& tt, const XCol<T>& x, int k0) {
+    if constexpr (KIND != K_DEBUG) load_a<PREC>(st, tt, k0, tid);
+    load_x<PREC, KIND>(st, tt, x, dbg, k0, tid);
+  };
+
+  Tile t = make_tile<PREC, KIND>(cls, work, w, dbg);
+  XCol<T> xc = column(t);
+  Stage<PREC> s0, s1;
+  if constexpr (KIND == K_DEBUG) {
+    for (int v = 0; v < Stage<PREC>::NA; ++v) s0.a[v] = s1.a[v] = u4{0, 0, 0, 0};
+  }
+  // FP64 stages are twice as large: only the first chunk of the next item is
+  // prefetched across the epilogue (the second loads at the item's start).
+  constexpr bool kAhead2 = PREC != PREC_F64;
+  fetch(s0, t, xc, 0);
+  if (kAhead2 && BK < t.K) fetch(s1, t, xc, BK);
+
+  for (;;) {
+    if (!kAhead2 && BK < t.K) fetch(s1, t, xc, BK);
     AccT acc[4][2], acc2[4][2];
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
       for (int b = 0; b < 2; ++b)
+#pragma unroll
         for (int v = 0; v < 4; ++v) {
           acc[a][b][v] = 0;
           if constexpr (PREC == PREC_SPLIT) acc2[a][b][v] = 0;
@@ -424,12 +474,7 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
       } else {
         store_a<PREC>(st, sm, tid);
       }
-      store_x<PREC>(st, sm, tid);
-    };
-    const XCol xc = x_col<KIND>(t, t.col0 + (tid & 63));
-    auto fetch = [&](Stage<PREC>& st, int k0) {
-      if constexpr (KIND != K_DEBUG) load_a<PREC>(st, t, tab, plane, k0, tid);
-      load_x<PREC, KIND>(st, t, xc, xbase, dbg, k0, tid);
+      store_x<PREC>(st, xc.sgn, sm, tid);
     };
     // MFMAs of the chunk in LDS; k sub-steps wholly beyond K are skipped
     auto compute = [&](int k0) {
@@ -440,15 +485,20 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
         for (int kk = 0; kk < BK; kk += 32) {
           if (kk >= kend) break;
           bf8 b[2][3];
+#pragma unroll
           for (int j = 0; j < 2; ++j)
             if (j < nbj)
+#pragma unroll
               for (int p = 0; p < 3; ++p)
                 b[j][p] = *reinterpret_cast<const bf8*>(&Xs[(p * BN + wc + j * 16 + lr) * PS + kk + 8 * lk]);
+#pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (i >= nbi) continue;
             bf8 a[3];
+#pragma unroll
             for (int p = 0; p < 3; ++p)
               a[p] = *reinterpret_cast<const bf8*>(&As[(p * BM + wr + i * 16 + lr) * PS + kk + 8 * lk]);
+#pragma unroll
             for (int j = 0; j < 2; ++j) {
               if (j >= nbj) continue;
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc[i][j], 0, 0, 0);
@@ -466,10 +516,14 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
         for (int kk = 0; kk < BK; kk += 4) {
           if (kk >= kend) break;
           T a[4], b[2];
+#pragma unroll
           for (int i = 0; i < 4; ++i) a[i] = As[(wr + i * 16 + lr) * PF + kk + lk];
+#pragma unroll
           for (int j = 0; j < 2; ++j) b[j] = Xs[(wc + j * 16 + lr) * PF + kk + lk];
+#pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (i >= nbi) continue;
+#pragma unroll
             for (int j = 0; j < 2; ++j) {
               if (j >= nbj) continue;
               if constexpr (PREC == PREC_F64)
@@ -482,131 +536,122 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
       }
     };
 
-    Stage<PREC> s0, s1;
-    if constexpr (KIND == K_DEBUG) {
-      for (int v = 0; v < Stage<PREC>::NA; ++v) s0.a[v] = s1.a[v] = make_uint4(0, 0, 0, 0);
-    }
-    fetch(s0, 0);
-    if (BK < t.K) fetch(s1, BK);
     for (int k0 = 0; k0 < t.K; k0 += 2 * BK) {
       __syncthreads();  // the previous chunk's MFMAs are done with LDS
       to_lds(s0, k0);
       __syncthreads();
-      if (k0 + 2 * BK < t.K) fetch(s0, k0 + 2 * BK);
+      if (k0 + 2 * BK < t.K) fetch(s0, t, xc, k0 + 2 * BK);
       compute(k0);
       if (k0 + BK >= t.K) break;
       __syncthreads();
       to_lds(s1, k0 + BK);
       __syncthreads();
-      if (k0 + 3 * BK < t.K) fetch(s1, k0 + 3 * BK);
+      if (k0 + 3 * BK < t.K) fetch(s1, t, xc, k0 + 3 * BK);
       compute(k0 + BK);
     }
 
-    // ---- epilogue through LDS, one 64-row half at a time.  Lane layout of a
-    // 16 x 16 block: real column lane%16; rows 4*(lane/16)+v (f32 MFMAs) or
-    // 4*v+lane/16 (f64 MFMA).
-    T* E = reinterpret_cast<T*>(sm);
-    for (int half = 0; half < 2; ++half) {
-      if (t.row0 + half * 64 >= t.M) break;
-      __syncthreads();
-      if (wr == half * 64) {
+    // the block's next item: its first chunks load while this one is written
+    const int wn = w + gridDim.x;
+    const bool more = wn < nitems;
+    Tile tn = t;
+    XCol<T> xn = xc;
+    if (more) {
+      tn = make_tile<PREC, KIND>(cls, work, wn, dbg);
+      xn = column(tn);
+      fetch(s0, tn, xn, 0);
+      if (kAhead2 && BK < tn.K) fetch(s1, tn, xn, BK);
+    }
+
+    // ---- epilogue: accumulators straight to the output layout.  Lane layout
+    // of a 16 x 16 block: real column lane%16; rows 4*(lane/16)+v (f32 MFMAs)
+    // or 4*v+lane/16 (f64 MFMA).  The output of a kind has the layout of the
+    // opposite kind's operand (KIND ^ 1), except stage c inverse, whose g
+    // output is column-major (rows along i).
+    auto value = [&](int i, int j, int v) -> T {
+      if constexpr (PREC == PREC_SPLIT)
+        return acc[i][j][v] + acc2[i][j][v];
+      else
+        return acc[i][j][v];
+    };
+    auto row_of = [&](int i, int v) { return t.row0 + wr + i * 16 + (PREC == PREC_F64 ? 4 * v + lk : 4 * lk + v); };
+    if constexpr (KIND == K_DEBUG) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int nr = 2 * t.col0 + wc + j * 16 + lr;
+        if (j >= nbj || nr >= dbg.N) continue;
+#pragma unroll
         for (int i = 0; i < 4; ++i)
-          for (int j = 0; j < 2; ++j)
-            for (int v = 0; v < 4; ++v) {
-              const int rin = PREC == PREC_F64 ? 4 * v + lk : 4 * lk + v;
-              T val;
-              if constexpr (PREC == PREC_SPLIT)
-                val = acc[i][j][v] + acc2[i][j][v];
-              else
-                val = acc[i][j][v];
-              E[(i * 16 + rin) * EP + wc + j * 16 + lr] = val;
-            }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = row_of(i, v);
+            if (i < nbi && row < t.M) dbg.C[(int64_t)row * dbg.N + nr] = (double)value(i, j, v);
+          }
       }
-      __syncthreads();
-      const int rbase = t.row0 + half * 64;
-      if constexpr (KIND == K_DEBUG) {
-        for (int e = tid; e < 64 * BN; e += NT) {
-          const int r = e / BN, n = e - r * BN;
-          const int row = rbase + r, nr = 2 * t.col0 + n;
-          if (row < t.M && nr < dbg.N) dbg.C[(int64_t)row * dbg.N + nr] = (double)E[r * EP + n];
-        }
-      } else if constexpr (KIND == K_C_INV) {
-        // column-major output (g rows run along i = tile row): pairs of rows;
-        // the output index of (row, c) is the stage-c forward operand index
-        T* out = reinterpret_cast<T*>(t.C->g);
-        const int cc = tid >> 3;            // 64 columns, 8 threads each
-        const int c = t.col0 + cc;
-        const XCol oc = x_col<K_C_FWD>(t, c);
-        if (oc.ok) {
-          for (int rp = (tid & 7) * 2; rp < 64; rp += 16) {
-            const int row = rbase + rp;
-            if (row >= t.M) break;
-            const int64_t ix = x_at<K_C_FWD>(t, oc, row);
-            const T r0 = E[rp * EP + 2 * cc], i0 = E[rp * EP + 2 * cc + 1];
-            if (row + 1 < t.M) {
-              const T r1 = E[(rp + 1) * EP + 2 * cc], i1 = E[(rp + 1) * EP + 2 * cc + 1];
-              if constexpr (PREC == PREC_F64) {
-                reinterpret_cast<double2*>(out)[ix] = make_double2(r0, i0);
-                reinterpret_cast<double2*>(out)[ix + 1] = make_double2(r1, i1);
-              } else {
-                *reinterpret_cast<float4*>(out + 2 * ix) = make_float4(r0, i0, r1, i1);
+    } else if constexpr (KIND == K_C_INV) {
+      T* gout = reinterpret_cast<T*>(t.C->g);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int rc = wc + j * 16 + lr;  // real column in the tile
+        const int c = t.col0 + (rc >> 1);
+        if (j >= nbj) continue;
+        const XCol<T> oc = x_col<K_C_FWD>(t, min(c, t.Ncc - 1), gout);
+        const bool okc = c < t.Ncc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i >= nbi) continue;
+          if constexpr (PREC == PREC_F64) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = row_of(i, v);
+              if (okc && row < t.M) oc.p[2 * row + (rc & 1)] = value(i, j, v);
+            }
+          } else {
+            // lanes lr and lr^1 hold re / im of the same column for rows
+            // r0..r0+3: swap halves so that each lane stores two complex values
+            const int r0 = row_of(i, 0);
+            const bool even = (rc & 1) == 0;
+            const T v0 = value(i, j, 0), v1 = value(i, j, 1), v2 = value(i, j, 2), v3 = value(i, j, 3);
+            const T send0 = even ? v2 : v0, send1 = even ? v3 : v1;
+            const T got0 = __shfl_xor(send0, 1), got1 = __shfl_xor(send1, 1);
+            const int rs = even ? r0 : r0 + 2;  // first of the two rows this lane stores
+            const float4 o = even ? make_float4(v0, got0, v1, got1) : make_float4(got0, v2, got1, v3);
+            if (okc) {
+              if (rs + 1 < t.M) {
+                *reinterpret_cast<float4*>(oc.p + 2 * rs) = o;
+              } else if (rs < t.M) {
+                *reinterpret_cast<float2*>(oc.p + 2 * rs) = make_float2(o.x, o.y);
               }
-            } else {
-              out[2 * ix] = r0;
-              out[2 * ix + 1] = i0;
             }
           }
         }
-      } else {
-        // row-major outputs: each thread owns a pair of consecutive complex
-        // columns (decoded once) and walks rows.  The output index of (row, c)
-        // is the operand index of the opposite direction: stage-b forward
-        // writes where stage-b inverse reads, and so on.
-        constexpr int DUAL = KIND ^ 1;
-        T* out = reinterpret_cast<T*>(KIND == K_B_FWD ? t.C->g : (KIND == K_B_INV ? t.C->F : cout));
-        const int cp = (tid & 31) * 2;
-        const int c = t.col0 + cp;
-        const XCol o0 = x_col<DUAL>(t, c);
-        const XCol o1 = x_col<DUAL>(t, c + 1);
-        T s0 = 1, s1 = 1;
-        if constexpr (KIND == K_B_FWD || KIND == K_B_INV) {
-          const int ncf = t.C->nf * t.C->L;
-          if ((t.q & 1) && c >= ncf) s0 = -1;
-          if ((t.q & 1) && c + 1 >= ncf) s1 = -1;
-        }
-        if (o0.ok) {
-          for (int r = tid >> 5; r < 64; r += NT / 32) {
-            const int row = rbase + r;
-            if (row >= t.M) break;
-            const int64_t i0 = x_at<DUAL>(t, o0, row);
-            const T re0 = s0 * E[r * EP + 2 * cp], im0 = s0 * E[r * EP + 2 * cp + 1];
-            if (o1.ok) {
-              const int64_t i1 = x_at<DUAL>(t, o1, row);
-              const T re1 = s1 * E[r * EP + 2 * cp + 2], im1 = s1 * E[r * EP + 2 * cp + 3];
-              if constexpr (PREC != PREC_F64) {
-                if (i1 == i0 + 1 && ((reinterpret_cast<uintptr_t>(out + 2 * i0) & 15) == 0)) {
-                  *reinterpret_cast<float4*>(out + 2 * i0) = make_float4(re0, im0, re1, im1);
-                  continue;
-                }
-              }
-              if constexpr (PREC == PREC_F64) {
-                reinterpret_cast<double2*>(out)[i1] = make_double2(re1, im1);
-              } else {
-                out[2 * i1] = re1;
-                out[2 * i1 + 1] = im1;
-              }
-            }
-            if constexpr (PREC == PREC_F64) {
-              reinterpret_cast<double2*>(out)[i0] = make_double2(re0, im0);
-            } else {
-              out[2 * i0] = re0;
-              out[2 * i0 + 1] = im0;
-            }
+      }
+    } else {
+      constexpr int DUAL = KIND ^ 1;
+      T* obase = KIND == K_B_FWD ? reinterpret_cast<T*>(t.C->g)
+                                 : (KIND == K_B_INV ? reinterpret_cast<T*>(t.C->F) : reinterpret_cast<T*>(cout));
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int rc = wc + j * 16 + lr;
+        const int c = t.col0 + (rc >> 1);
+        if (j >= nbj) continue;
+        const XCol<T> oc = x_col<DUAL>(t, min(c, t.Ncc - 1), obase);
+        T* op = oc.p + (rc & 1);
+        const bool okc = c < t.Ncc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i >= nbi) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = row_of(i, v);
+            if (okc && row < t.M) op[2 * x_off<DUAL>(t, oc, row)] = value(i, j, v);
           }
         }
       }
     }
-    __syncthreads();
+    if (!more) break;
+    w = wn;
+    t = tn;
+    xc = xn;
   }
 }
 

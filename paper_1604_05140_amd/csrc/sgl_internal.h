@@ -39,6 +39,13 @@ __host__ __device__ inline int64_t table_block(int B, int q) {
   return 2ll * B * ((int64_t)q * B - (int64_t)q * (q - 1) / 2);
 }
 __host__ __device__ inline int64_t table_size(int B) { return (int64_t)B * B * (B + 1); }
+// Functions per bandlimit class: the spectrum workspace (2B-1) (2B)^2 nf, the
+// largest per-class buffer, stays below 2^31 complex values.
+inline int class_capacity(int B) {
+  const int64_t per = (int64_t)(2 * B - 1) * 4 * B * B;
+  const int64_t cap = ((int64_t(1) << 31) - 1) / per;
+  return (int)(cap < 1 ? 1 : (cap > (1 << 20) ? (1 << 20) : cap));
+}
 
 // ---------------------------------------------------------------------------
 // Device-side description of one bandlimit class (all functions sharing B)

@@ -122,9 +122,31 @@ namespace {
     if (st_ != SGL_OK) return st_;  \
   } while (0)
 
-sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
+sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t s);
+
+// Build one class.  `share` (may be null) is an earlier class of the same
+// bandlimit whose grid, tables and FFT constants are reused.
+sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hipStream_t s) {
   const int B = c.B, L = 2 * B, nf = (int)c.funcs.size();
   const int64_t ts = table_size(B);
+  if (share) {
+    c.grid = share->grid;
+    c.P64 = share->P64;
+    c.R64 = share->R64;
+    for (int k = 0; k < 4; ++k) {
+      c.A[k] = share->A[k];
+      c.Aoff[k] = share->Aoff[k];
+      c.Aplane[k] = share->Aplane[k];
+    }
+    c.tw = share->tw;
+    c.M = share->M;
+    c.twM = share->twM;
+    c.chirp = share->chirp;
+    c.bhf = share->bhf;
+    c.bhi = share->bhi;
+    c.radices = share->radices;
+    return build_class_data(p, c, s);
+  }
   SGL_TRY(p->alloc((void**)&c.grid, 6 * (size_t)L * sizeof(double)));
   GridBuild gb{B, c.grid, c.grid + L, c.grid + 2 * L, c.grid + 3 * L, c.grid + 4 * L, c.grid + 5 * L};
   SGL_TRY(build_grid(gb, s));
@@ -169,6 +191,12 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
     set_error("FFT length has too many factors");
     return SGL_ERR_UNSUPPORTED;
   }
+  return build_class_data(p, c, s);
+}
+
+// Per-class workspace, function offsets and FFT blocking (not shared).
+sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
+  const int B = c.B, L = 2 * B, nf = (int)c.funcs.size();
   const size_t es = p->esz();
   SGL_TRY(p->alloc(&c.F, (size_t)(2 * B - 1) * L * nf * L * es));
   SGL_TRY(p->alloc(&c.g, (size_t)B * B * nf * L * es));
@@ -257,14 +285,23 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
 sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
   std::map<int, std::vector<int>> byB;
   for (int f = 0; f < (int)p->Bs.size(); ++f) byB[p->Bs[f]].push_back(f);
-  // largest bandlimit first
+  // largest bandlimit first; a class holds at most class_capacity(B) functions
+  // so that its workspaces stay below 2^31 complex values (the stage kernels
+  // index them with 32-bit offsets)
   for (auto it = byB.rbegin(); it != byB.rend(); ++it) {
-    ClassHost c;
-    c.B = it->first;
-    c.funcs = it->second;
-    p->classes.push_back(c);
+    const int cap = class_capacity(it->first);
+    for (size_t f0 = 0; f0 < it->second.size(); f0 += cap) {
+      ClassHost c;
+      c.B = it->first;
+      const size_t f1 = std::min(it->second.size(), f0 + (size_t)cap);
+      c.funcs.assign(it->second.begin() + f0, it->second.begin() + f1);
+      p->classes.push_back(c);
+    }
   }
-  for (auto& c : p->classes) SGL_TRY(build_class(p, c, s));
+  for (size_t q = 0; q < p->classes.size(); ++q) {
+    const ClassHost* share = (q > 0 && p->classes[q - 1].B == p->classes[q].B) ? &p->classes[q - 1] : nullptr;
+    SGL_TRY(build_class(p, p->classes[q], share, s));
+  }
   std::vector<ClassDesc> descs;
   for (auto& c : p->classes) {
     ClassDesc d;
