@@ -70,10 +70,11 @@ def time_steps(torch, sgl, plan, c_in, s_in, cout, sout, steps):
     return e0.elapsed_time(e1) / steps
 
 
-def run_form(sgl, torch, plan, c_in, s_in, steps, warmup, graph_steps=0):
-    """Timed region: `steps` forward+inverse pairs with per-stage HIP events
-    recorded on the launch stream.  With graph_steps > 0 (plan built with
-    SGL_GRAPHS) a second timed loop replays the captured graphs without events."""
+def run_form(sgl, torch, plan, c_in, s_in, steps, warmup):
+    """Two timed regions of `steps` forward+inverse pairs each: the first with
+    plain calls (graph replays when the plan was made with SGL_GRAPHS) gives
+    ms_per_step; the second records HIP events around every stage launch on the
+    launch stream (eager launches) and gives the per-stage kernel times."""
     dev = c_in.device
     cout = torch.empty(plan.total_coeffs, dtype=plan.complex_dtype, device=dev)
     sout = torch.empty(plan.total_samples, dtype=plan.complex_dtype, device=dev)
@@ -81,14 +82,67 @@ def run_form(sgl, torch, plan, c_in, s_in, steps, warmup, graph_steps=0):
         sgl.sgl_forward(plan, s_in, cout)
         sgl.sgl_inverse(plan, c_in, sout)
     torch.cuda.synchronize()
+    ms = time_steps(torch, sgl, plan, c_in, s_in, cout, sout, steps)
     plan.stage_times()  # reset
     plan.set_timing(True)
-    ms = time_steps(torch, sgl, plan, c_in, s_in, cout, sout, steps)
+    ms_inst = time_steps(torch, sgl, plan, c_in, s_in, cout, sout, steps)
     st_ms, st_cnt = plan.stage_times()
     plan.set_timing(False)
     per_stage = {STAGES[q]: (st_ms[q] / st_cnt[q] if st_cnt[q] else None) for q in range(6)}
-    graph_ms = time_steps(torch, sgl, plan, c_in, s_in, cout, sout, graph_steps) if graph_steps else None
-    return ms, per_stage, cout, sout, graph_ms
+    return ms, ms_inst, per_stage, cout, sout
+
+
+def measured_traffic(kernel_stage, dtype, B, nf):
+    """HBM bytes per launch of a stage kernel from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
+    when no summary covers this workload or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{dtype}_b{B}_batch{nf}.txt")
+    if not os.path.exists(path):
+        return None
+    rows, src_hash = {}, {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("source_sha256"):
+            _, f, h = line.split()
+            src_hash[f] = h
+        elif line.startswith("stage="):
+            kv = dict(x.split("=", 1) for x in line.split())
+            rows[kv["stage"]] = kv
+    r = rows.get(kernel_stage)
+    if r is None:
+        return None
+    f = os.path.join(ROOT, "paper_1604_05140_amd", "csrc", r["source"])
+    if not os.path.exists(f) or hashlib.sha256(open(f, "rb").read()).hexdigest() != src_hash.get(r["source"]):
+        return None
+    return float(r["traffic_bytes"])
+
+
+def roofline(form, dtype, B, nf):
+    """Roofline position of the dominant (longest) stage kernel of a form.  The
+    bound is whichever of HBM (algorithmic bytes at 8 TB/s) or the matrix cores
+    (issued flops at the dtype's dense peak; the split form issues six bf16
+    products per multiply-add) gives the longer ideal time; `achieved` is the
+    algorithmic bytes or flops of one launch over the measured launch time."""
+    work = stage_work(B, nf, dtype)
+    dom = max((k for k in STAGES if form["stage_ms"][k]), key=lambda k: form["stage_ms"][k])
+    flops, nbytes = work[dom]
+    t_s = form["stage_ms"][dom] / 1000.0
+    pk = {"f64": PEAK["f64"], "f32": PEAK["f32"], "split_bf16": PEAK["bf16"]}[dtype]
+    t_hbm = nbytes / (PEAK["hbm_GBs"] * 1e9)
+    t_mfma = 0.0 if "fft" in dom else flops / (pk * 1e12)
+    mult = 6 if dtype == "split_bf16" else 1
+    if t_hbm >= t_mfma:
+        roof = {"bound": "hbm", "achieved": nbytes / t_s / 1e9, "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": flops / mult / t_s / 1e12, "peak": pk / mult, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(dom, dtype, B, nf)
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = form["stage_ms"][dom]
+    roof["algorithmic_bytes"] = nbytes
+    roof["algorithmic_flops"] = flops // mult
+    return roof
 
 
 def cpu_baseline(B, n_coef, n_pts, seed):
@@ -132,8 +186,7 @@ def bench_batched(args, torch, sgl, synth, dev):
     c_in = torch.from_numpy(np.concatenate(cs)).to(dev, ct)
     s_in = torch.empty(plan.total_samples, dtype=ct, device=dev)
     sgl.sgl_inverse(plan, c_in, s_in)
-    ms, per_stage, _, _, graph_ms = run_form(sgl, torch, plan, c_in, s_in, args.steps, args.warmup,
-                                             graph_steps=args.steps)
+    ms, ms_inst, per_stage, _, _ = run_form(sgl, torch, plan, c_in, s_in, args.steps, args.warmup)
     out = {
         "metric": "SGL fwd+inv transforms/s, 256 functions with B uniform in {16..96} (batched form)",
         "value": 256 * 1000.0 / ms,
@@ -145,7 +198,7 @@ def bench_batched(args, torch, sgl, synth, dev):
         "config": {"workload": "SGL forward+inverse, 256 functions, B uniform in {16..96}, complex-normal/n "
                                "coefficients", "form": dtype, "total_coeffs": plan.total_coeffs,
                    "total_samples": plan.total_samples},
-        "stage_ms": per_stage, "graph_ms_per_step": graph_ms, "launch_grids": plan.launch_grids(),
+        "stage_ms": per_stage, "ms_per_step_with_stage_events": ms_inst, "launch_grids": plan.launch_grids(),
     }
     print(json.dumps(out), flush=True)
 
@@ -181,10 +234,17 @@ def main():
         src = torch.ones(n, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        dst.copy_(src)
+        e0.record()
         for _ in range(3):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": n, "launches": 3}), flush=True)
+        ms = e0.elapsed_time(e1) / 3
+        print(json.dumps({"copy_probe_bytes": n, "launches": 4, "ms_per_copy": ms,
+                          "copy_GBps": 2 * n / ms / 1e6}), flush=True)
         return
     if args.workload == "batched":
         return bench_batched(args, torch, sgl, synth, dev)
@@ -217,40 +277,27 @@ def main():
         steps = args.steps if head_form else max(3, args.steps // 4)
         warm = args.warmup if head_form else 2
         print(f"[bench] timing {dtype}: {warm} warmup + {steps} steps", file=sys.stderr, flush=True)
-        ms, per_stage, cout, sout, graph_ms = run_form(sgl, torch, plan, c_in, s_in, steps, warm,
-                                                       graph_steps=steps if head_form else 0)
+        ms, ms_inst, per_stage, cout, sout = run_form(sgl, torch, plan, c_in, s_in, steps, warm)
         forms[dtype] = {
             "ms_per_step": ms,
             "transforms_per_s": nf * 1000.0 / ms,
+            "graphs": head_form,
+            "ms_per_step_with_stage_events": ms_inst,
             "stage_ms": per_stage,
             "steps": steps,
             "e_inf_forward_vs_f64": einf(c_ref, cout, nc),
             "e_inf_inverse_vs_f64": einf(s128, sout, ns),
         }
         if head_form:
-            forms[dtype]["graph_ms_per_step"] = graph_ms
             forms[dtype]["launch_grids"] = plan.launch_grids()
-        print(f"[bench] {dtype}: {ms:.3f} ms/step, {nf * 1000.0 / ms:.1f} transforms/s", file=sys.stderr,
-              flush=True)
+        print(f"[bench] {dtype}: {ms:.3f} ms/step, {nf * 1000.0 / ms:.1f} transforms/s "
+              f"(stage-timed pass {ms_inst:.3f} ms/step)", file=sys.stderr, flush=True)
         del cout, sout
         if plan is not p64:
             plan.destroy()
 
     head = forms[args.dtype]
-    # roofline of the dominant kernel of the headline form
-    work = stage_work(B, nf, args.dtype)
-    dom = max((k for k in STAGES if head["stage_ms"][k]), key=lambda k: head["stage_ms"][k])
-    flops, nbytes = work[dom]
-    t_s = head["stage_ms"][dom] / 1000.0
-    if "fft" in dom:
-        roof = {"bound": "hbm", "achieved": nbytes / t_s / 1e9, "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
-    else:
-        pk = {"f64": PEAK["f64"], "f32": PEAK["f32"], "split_bf16": PEAK["bf16"]}[args.dtype]
-        roof = {"bound": "mfma", "achieved": flops / t_s / 1e12, "peak": pk, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom
-    roof["avg_launch_ms"] = head["stage_ms"][dom]
+    roof = roofline(head, args.dtype, B, nf)
 
     out = {
         "metric": "SGL fwd+inv transforms/s at B=128 (MFMA split vs FP64), rel err <=1e-6",

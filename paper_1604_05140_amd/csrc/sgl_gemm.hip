@@ -48,10 +48,7 @@ namespace {
 constexpr int BM = 128;      // rows per tile
 constexpr int BN = 128;      // real columns per tile
 constexpr int BNC = BN / 2;  // complex columns per tile
-constexpr int BK = 64;       // contraction chunk
 constexpr int NT = 512;      // 8 waves, 2 x 4 layout of 64 x 32
-constexpr int PS = BK + 8;   // bf16 LDS pitch (80 bytes)
-constexpr int PF = BK + 4;   // f32/f64 LDS pitch in elements
 
 enum Kind { K_B_FWD = 0, K_B_INV = 1, K_C_FWD = 2, K_C_INV = 3, K_DEBUG = 4 };
 
@@ -59,6 +56,24 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));  // 16-byte operand vector
+
+// Contraction chunk per precision: 32 for the bf16-split and FP32 forms (two
+// blocks of 60 KB LDS fit a CU), 64 for FP64.  The packed tables pad K to it.
+template <int PREC> struct Cfg {
+  static constexpr int BK = PREC == PREC_F64 ? 64 : 32;
+  static constexpr int PS = BK + 8;  // bf16 LDS pitch (elements)
+  static constexpr int PF = BK + 4;  // f32/f64 LDS pitch (elements)
+  static constexpr int XN = BK / 8;  // k per thread in the data-operand staging (8 k groups)
+  // 16-byte table vectors per row and per thread
+  static constexpr int VR = PREC == PREC_SPLIT ? BK / 8 : (PREC == PREC_F32 ? BK / 4 : BK / 2);
+  static constexpr int NA = (PREC == PREC_SPLIT ? 3 : 1) * BM * VR / NT;
+  // register stages of the operand pipeline (loads run 1 or 2 chunks ahead):
+  // one keeps the split form within 128 registers (4 waves per SIMD) and FP64
+  // free of spills; FP32 has room for two
+  static constexpr int NS = PREC == PREC_F32 ? 2 : 1;
+  // waves per SIMD the register allocation is held to
+  static constexpr int WAVES = PREC == PREC_F64 ? 2 : 4;
+};
 
 template <int PREC> struct DT { using t = float; };
 template <> struct DT<PREC_F64> { using t = double; };
@@ -73,13 +88,13 @@ __device__ inline uint16_t f2bf(float f) {
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 template <int PREC> struct Lds {
-  static constexpr int a = BM * PF * (int)sizeof(typename DT<PREC>::t);
-  static constexpr int x = BN * PF * (int)sizeof(typename DT<PREC>::t);
+  static constexpr int a = BM * Cfg<PREC>::PF * (int)sizeof(typename DT<PREC>::t);
+  static constexpr int x = BN * Cfg<PREC>::PF * (int)sizeof(typename DT<PREC>::t);
   static constexpr int total = a + x;
 };
 template <> struct Lds<PREC_SPLIT> {
-  static constexpr int a = 3 * BM * PS * 2;
-  static constexpr int x = 3 * BN * PS * 2;
+  static constexpr int a = 3 * BM * Cfg<PREC_SPLIT>::PS * 2;
+  static constexpr int x = 3 * BN * Cfg<PREC_SPLIT>::PS * 2;
   static constexpr int total = a + x;
 };
 
@@ -130,6 +145,7 @@ __device__ inline Tile make_tile(const ClassDesc* cls, const int4* work, int w, 
     constexpr bool fwd = KIND == K_B_FWD || KIND == K_C_FWD;
     t.M = fwd ? rows : L;
     t.K = fwd ? L : rows;
+    constexpr int BK = Cfg<PREC>::BK;
     t.pitch = (t.K + BK - 1) / BK * BK;
     t.plane = C.Aplane[KIND];
     t.tab = reinterpret_cast<const unsigned char*>(C.A[KIND]) +
@@ -141,78 +157,47 @@ __device__ inline Tile make_tile(const ClassDesc* cls, const int4* work, int w, 
 }
 
 // ---- per-thread register staging of one K chunk -----------------------------
-// A: split -> 6 x 16 bytes (3 planes x 2 vectors); f32 -> 4 x float4; f64 -> 8 x double2.
-// X: 8 consecutive k of one complex column -> 8 complex values.
+// A: NA 16-byte table vectors; X: XN consecutive k of one complex column.
 template <int PREC> struct Stage {
-  static constexpr int NA = PREC == PREC_SPLIT ? 6 : (PREC == PREC_F32 ? 4 : 8);
+  static constexpr int NA = Cfg<PREC>::NA;
   u4 a[NA];
-  typename DT<PREC>::t xr[8], xi[8];
+  typename DT<PREC>::t xr[Cfg<PREC>::XN], xi[Cfg<PREC>::XN];
 };
 
 // A chunk: BM rows x BK from a packed table block.  Rows past the block are
 // clamped to its last row: they feed only output rows that are never stored.
 template <int PREC>
 __device__ inline void load_a(Stage<PREC>& st, const Tile& t, int k0, int tid) {
+  using C = Cfg<PREC>;
   const int rmax = t.M - 1;
-  if constexpr (PREC == PREC_SPLIT) {
-    // 3 planes x 128 rows x 8 vectors of 8 bf16
-    const uint16_t* tab = reinterpret_cast<const uint16_t*>(t.tab);
+  constexpr int EV = PREC == PREC_SPLIT ? 8 : (PREC == PREC_F32 ? 4 : 2);  // elements per vector
+  constexpr int ES = PREC == PREC_SPLIT ? 2 : (PREC == PREC_F32 ? 4 : 8);  // element bytes
+  const unsigned char* tab = reinterpret_cast<const unsigned char*>(t.tab);
 #pragma unroll
-    for (int v = 0; v < 6; ++v) {
-      const int e = tid + v * NT;  // 0..3071
-      const int p = e >> 10, rem = e & 1023;
-      const int r = rem >> 3, kg = rem & 7;
-      const int gr = min(t.row0 + r, rmax);
-      st.a[v] = *reinterpret_cast<const u4*>(tab + p * t.plane + (int64_t)gr * t.pitch + k0 + kg * 8);
-    }
-  } else if constexpr (PREC == PREC_F32) {
-    const float* tab = reinterpret_cast<const float*>(t.tab);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int e = tid + v * NT;  // 128 rows x 16 vectors of 4 floats
-      const int r = e >> 4, kg = e & 15;
-      const int gr = min(t.row0 + r, rmax);
-      st.a[v] = *reinterpret_cast<const u4*>(tab + (int64_t)gr * t.pitch + k0 + kg * 4);
-    }
-  } else {
-    const double* tab = reinterpret_cast<const double*>(t.tab);
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const int e = tid + v * NT;  // 128 rows x 32 vectors of 2 doubles
-      const int r = e >> 5, kg = e & 31;
-      const int gr = min(t.row0 + r, rmax);
-      st.a[v] = *reinterpret_cast<const u4*>(tab + (int64_t)gr * t.pitch + k0 + kg * 2);
-    }
+  for (int v = 0; v < C::NA; ++v) {
+    const int e = tid + v * NT;  // plane, row, vector
+    const int p = PREC == PREC_SPLIT ? e / (BM * C::VR) : 0;
+    const int rem = e - p * (BM * C::VR);
+    const int r = rem / C::VR, kg = rem - r * C::VR;
+    const int gr = min(t.row0 + r, rmax);
+    const int64_t off = (int64_t)gr * t.pitch + k0 + kg * EV;
+    st.a[v] = *reinterpret_cast<const u4*>(tab + ES * (PREC == PREC_SPLIT ? p * t.plane + off : off));
   }
 }
 
 template <int PREC>
 __device__ inline void store_a(const Stage<PREC>& st, unsigned char* sm, int tid) {
-  if constexpr (PREC == PREC_SPLIT) {
-    uint16_t* As = reinterpret_cast<uint16_t*>(sm);
+  using C = Cfg<PREC>;
+  constexpr int EV = PREC == PREC_SPLIT ? 8 : (PREC == PREC_F32 ? 4 : 2);
+  constexpr int ES = PREC == PREC_SPLIT ? 2 : (PREC == PREC_F32 ? 4 : 8);
+  constexpr int P = PREC == PREC_SPLIT ? C::PS : C::PF;
 #pragma unroll
-    for (int v = 0; v < 6; ++v) {
-      const int e = tid + v * NT;
-      const int p = e >> 10, rem = e & 1023;
-      const int r = rem >> 3, kg = rem & 7;
-      *reinterpret_cast<u4*>(&As[(p * BM + r) * PS + kg * 8]) = st.a[v];
-    }
-  } else if constexpr (PREC == PREC_F32) {
-    float* As = reinterpret_cast<float*>(sm);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int e = tid + v * NT;
-      const int r = e >> 4, kg = e & 15;
-      *reinterpret_cast<u4*>(&As[r * PF + kg * 4]) = st.a[v];
-    }
-  } else {
-    double* As = reinterpret_cast<double*>(sm);
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const int e = tid + v * NT;
-      const int r = e >> 5, kg = e & 31;
-      *reinterpret_cast<u4*>(&As[r * PF + kg * 2]) = st.a[v];
-    }
+  for (int v = 0; v < C::NA; ++v) {
+    const int e = tid + v * NT;
+    const int p = PREC == PREC_SPLIT ? e / (BM * C::VR) : 0;
+    const int rem = e - p * (BM * C::VR);
+    const int r = rem / C::VR, kg = rem - r * C::VR;
+    *reinterpret_cast<u4*>(sm + ES * ((p * BM + r) * P + kg * EV)) = st.a[v];
   }
 }
 
@@ -288,12 +273,13 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol<typenam
                               const DebugArgs& dbg, int k0, int tid) {
   using T = typename DT<PREC>::t;
   using T2 = typename V2<T>::t;
+  constexpr int XN = Cfg<PREC>::XN;
   const int kg = tid >> 6;
-  const int kb = k0 + kg * 8;
+  const int kb = k0 + kg * XN;
   if constexpr (KIND == K_DEBUG) {
     const int c = t.col0 + (tid & 63);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < XN; ++u) {
       const int k = kb + u;
       const int n0 = 2 * c, n1 = 2 * c + 1;
       const bool ok = k < t.K;
@@ -303,11 +289,11 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol<typenam
   } else {
     const int kmax = t.K - 1;
     if constexpr (KIND == K_C_FWD && PREC != PREC_F64) {
-      if (kb + 8 <= t.K) {
-        // 8 consecutive k of one column are contiguous (g rows run along i)
+      if (kb + XN <= t.K) {
+        // XN consecutive k of one column are contiguous (g rows run along i)
         const float4* src = reinterpret_cast<const float4*>(xc.p + 2 * kb);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < XN / 2; ++u) {
           const float4 v = src[u];
           st.xr[2 * u] = v.x;
           st.xi[2 * u] = v.y;
@@ -318,7 +304,7 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol<typenam
       }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < XN; ++u) {
       const int k = min(kb + u, kmax);
       const T2 v = *reinterpret_cast<const T2*>(xc.p + 2 * x_off<KIND>(t, xc, k));
       st.xr[u] = v.x;
@@ -343,35 +329,38 @@ __device__ inline uint32_t pack_hi(uint32_t lo, uint32_t hi) { return __builtin_
 // X chunk to LDS as [column][k]; sgn carries the (-1)^m of the -m segment.
 template <int PREC>
 __device__ inline void store_x(const Stage<PREC>& st, typename DT<PREC>::t sgn, unsigned char* sm, int tid) {
+  using C = Cfg<PREC>;
+  constexpr int XN = C::XN;
   const int cc = tid & 63, kg = tid >> 6;
   if constexpr (PREC == PREC_SPLIT) {
+    static_assert(XN == 4, "split staging holds 4 k per thread");
     uint16_t* Xs = reinterpret_cast<uint16_t*>(sm + Lds<PREC>::a);
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
-      uint32_t h[3][8];
+      uint32_t h[3][XN];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) split3(sgn * (part ? st.xi[u] : st.xr[u]), h[0][u], h[1][u], h[2][u]);
+      for (int u = 0; u < XN; ++u) split3(sgn * (part ? st.xi[u] : st.xr[u]), h[0][u], h[1][u], h[2][u]);
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
-        const u4 w = {pack_hi(h[p][0], h[p][1]), pack_hi(h[p][2], h[p][3]), pack_hi(h[p][4], h[p][5]),
-                      pack_hi(h[p][6], h[p][7])};
-        *reinterpret_cast<u4*>(&Xs[(p * BN + 2 * cc + part) * PS + kg * 8]) = w;
+        uint2 w;
+        w.x = pack_hi(h[p][0], h[p][1]);
+        w.y = pack_hi(h[p][2], h[p][3]);
+        *reinterpret_cast<uint2*>(&Xs[(p * BN + 2 * cc + part) * C::PS + kg * XN]) = w;
       }
     }
   } else if constexpr (PREC == PREC_F32) {
+    static_assert(XN == 4, "f32 staging holds 4 k per thread");
     float* Xs = reinterpret_cast<float*>(sm + Lds<PREC>::a);
-    float* r0 = &Xs[(2 * cc) * PF + kg * 8];
-    float* r1 = &Xs[(2 * cc + 1) * PF + kg * 8];
-    *reinterpret_cast<float4*>(r0) = make_float4(sgn * st.xr[0], sgn * st.xr[1], sgn * st.xr[2], sgn * st.xr[3]);
-    *reinterpret_cast<float4*>(r0 + 4) = make_float4(sgn * st.xr[4], sgn * st.xr[5], sgn * st.xr[6], sgn * st.xr[7]);
-    *reinterpret_cast<float4*>(r1) = make_float4(sgn * st.xi[0], sgn * st.xi[1], sgn * st.xi[2], sgn * st.xi[3]);
-    *reinterpret_cast<float4*>(r1 + 4) = make_float4(sgn * st.xi[4], sgn * st.xi[5], sgn * st.xi[6], sgn * st.xi[7]);
+    *reinterpret_cast<float4*>(&Xs[(2 * cc) * C::PF + kg * XN]) =
+        make_float4(sgn * st.xr[0], sgn * st.xr[1], sgn * st.xr[2], sgn * st.xr[3]);
+    *reinterpret_cast<float4*>(&Xs[(2 * cc + 1) * C::PF + kg * XN]) =
+        make_float4(sgn * st.xi[0], sgn * st.xi[1], sgn * st.xi[2], sgn * st.xi[3]);
   } else {
     double* Xs = reinterpret_cast<double*>(sm + Lds<PREC>::a);
-    double* r0 = &Xs[(2 * cc) * PF + kg * 8];
-    double* r1 = &Xs[(2 * cc + 1) * PF + kg * 8];
+    double* r0 = &Xs[(2 * cc) * C::PF + kg * XN];
+    double* r1 = &Xs[(2 * cc + 1) * C::PF + kg * XN];
 #pragma unroll
-    for (int u = 0; u < 8; u += 2) {
+    for (int u = 0; u < XN; u += 2) {
       *reinterpret_cast<double2*>(r0 + u) = make_double2(sgn * st.xr[u], sgn * st.xr[u + 1]);
       *reinterpret_cast<double2*>(r1 + u) = make_double2(sgn * st.xi[u], sgn * st.xi[u + 1]);
     }
@@ -394,11 +383,12 @@ __device__ inline typename DT<PREC>::t* x_base(const Tile& t, const void* cin) {
 // load latency of short contractions overlaps the stores.  Outputs go straight
 // from the accumulators to the next stage's layout.
 template <int PREC, int KIND>
-__global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PREC>::WAVES))) k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                              int nwork, const void* __restrict__ cin, void* __restrict__ cout,
                                              DebugArgs dbg) {
   using T = typename DT<PREC>::t;
   using AccT = typename Acc<PREC>::t;
+  constexpr int BK = Cfg<PREC>::BK, PS = Cfg<PREC>::PS, PF = Cfg<PREC>::PF;
   __shared__ __align__(16) unsigned char sm[Lds<PREC>::total];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -425,14 +415,23 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
   if constexpr (KIND == K_DEBUG) {
     for (int v = 0; v < Stage<PREC>::NA; ++v) s0.a[v] = s1.a[v] = u4{0, 0, 0, 0};
   }
-  // FP64 stages are twice as large: only the first chunk of the next item is
-  // prefetched across the epilogue (the second loads at the item's start).
-  constexpr bool kAhead2 = PREC != PREC_F64;
-  fetch(s0, t, xc, 0);
-  if (kAhead2 && BK < t.K) fetch(s1, t, xc, BK);
+  // FP64 stages are too large to stay live across the epilogue: its items load
+  // their first chunks at their start.
+  constexpr bool kAhead = PREC != PREC_F64;
+  constexpr int NS = Cfg<PREC>::NS;
+  // the split form accumulates its six products in one FP32 accumulator per
+  // output (a second one for the corrections would cost the occupancy)
+  constexpr bool kCorr = false;
+  if (kAhead) {
+    fetch(s0, t, xc, 0);
+    if (NS == 2 && BK < t.K) fetch(s1, t, xc, BK);
+  }
 
   for (;;) {
-    if (!kAhead2 && BK < t.K) fetch(s1, t, xc, BK);
+    if (!kAhead) {
+      fetch(s0, t, xc, 0);
+      if (NS == 2 && BK < t.K) fetch(s1, t, xc, BK);
+    }
     AccT acc[4][2], acc2[4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -441,7 +440,7 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           acc[a][b][v] = 0;
-          if constexpr (PREC == PREC_SPLIT) acc2[a][b][v] = 0;
+          if constexpr (kCorr) acc2[a][b][v] = 0;
         }
     // wave-uniform MFMA block masks (rows / columns beyond the group)
     int nbi = 0, nbj = 0;
@@ -501,12 +500,14 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
               if (j >= nbj) continue;
+              // smallest products first, the main product last
+              AccT& c2 = kCorr ? acc2[i][j] : acc[i][j];
+              c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][0], c2, 0, 0, 0);
+              c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][1], c2, 0, 0, 0);
+              c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][2], c2, 0, 0, 0);
+              c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][0], c2, 0, 0, 0);
+              c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][1], c2, 0, 0, 0);
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], acc[i][j], 0, 0, 0);
-              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][1], acc2[i][j], 0, 0, 0);
-              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][0], acc2[i][j], 0, 0, 0);
-              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][2], acc2[i][j], 0, 0, 0);
-              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][1], acc2[i][j], 0, 0, 0);
-              acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][0], acc2[i][j], 0, 0, 0);
             }
           }
         }
@@ -536,18 +537,28 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
       }
     };
 
-    for (int k0 = 0; k0 < t.K; k0 += 2 * BK) {
-      __syncthreads();  // the previous chunk's MFMAs are done with LDS
-      to_lds(s0, k0);
-      __syncthreads();
-      if (k0 + 2 * BK < t.K) fetch(s0, t, xc, k0 + 2 * BK);
-      compute(k0);
-      if (k0 + BK >= t.K) break;
-      __syncthreads();
-      to_lds(s1, k0 + BK);
-      __syncthreads();
-      if (k0 + 3 * BK < t.K) fetch(s1, t, xc, k0 + 3 * BK);
-      compute(k0 + BK);
+    if constexpr (NS == 2) {
+      for (int k0 = 0; k0 < t.K; k0 += 2 * BK) {
+        __syncthreads();  // the previous chunk's MFMAs are done with LDS
+        to_lds(s0, k0);
+        __syncthreads();
+        if (k0 + 2 * BK < t.K) fetch(s0, t, xc, k0 + 2 * BK);
+        compute(k0);
+        if (k0 + BK >= t.K) break;
+        __syncthreads();
+        to_lds(s1, k0 + BK);
+        __syncthreads();
+        if (k0 + 3 * BK < t.K) fetch(s1, t, xc, k0 + 3 * BK);
+        compute(k0 + BK);
+      }
+    } else {
+      for (int k0 = 0; k0 < t.K; k0 += BK) {
+        __syncthreads();  // the previous chunk's MFMAs are done with LDS
+        to_lds(s0, k0);
+        __syncthreads();
+        if (k0 + BK < t.K) fetch(s0, t, xc, k0 + BK);
+        compute(k0);
+      }
     }
 
     // the block's next item: its first chunks load while this one is written
@@ -558,8 +569,10 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
     if (more) {
       tn = make_tile<PREC, KIND>(cls, work, wn, dbg);
       xn = column(tn);
-      fetch(s0, tn, xn, 0);
-      if (kAhead2 && BK < tn.K) fetch(s1, tn, xn, BK);
+      if (kAhead) {
+        fetch(s0, tn, xn, 0);
+        if (NS == 2 && BK < tn.K) fetch(s1, tn, xn, BK);
+      }
     }
 
     // ---- epilogue: accumulators straight to the output layout.  Lane layout
@@ -568,7 +581,7 @@ __global__ void __launch_bounds__(NT) k_gemm(const ClassDesc* __restrict__ cls, 
     // opposite kind's operand (KIND ^ 1), except stage c inverse, whose g
     // output is column-major (rows along i).
     auto value = [&](int i, int j, int v) -> T {
-      if constexpr (PREC == PREC_SPLIT)
+      if constexpr (kCorr)
         return acc[i][j][v] + acc2[i][j][v];
       else
         return acc[i][j][v];
@@ -694,7 +707,9 @@ hipError_t launch_any(int prec, int kind, const ClassDesc* d_cls, const int4* d_
 
 int gemm_tile_m() { return BM; }
 int gemm_tile_n_complex() { return BNC; }
-int gemm_k_chunk() { return BK; }
+int gemm_k_chunk(int prec) {
+  return prec == PREC_F64 ? Cfg<PREC_F64>::BK : (prec == PREC_F32 ? Cfg<PREC_F32>::BK : Cfg<PREC_SPLIT>::BK);
+}
 
 hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
                            int max_grid, hipStream_t s) {

@@ -156,7 +156,7 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
   // packed GEMM operands, one per contraction direction
   const int prec = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
   const size_t el = prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2);
-  const int KC = gemm_k_chunk();
+  const int KC = gemm_k_chunk(prec);
   for (int kind = 0; kind < 4; ++kind) {
     const bool fwd = kind == 0 || kind == 2;
     std::vector<int64_t> offs(B);

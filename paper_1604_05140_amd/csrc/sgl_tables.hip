@@ -540,7 +540,7 @@ hipError_t convert_table_f32(const double* src, float* dst, int64_t n, hipStream
 
 hipError_t pack_table(int B, int kind, int prec, const double* T64, const int64_t* d_offs, void* dst,
                       int64_t plane, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack, dim3(64, B), dim3(256), 0, s, B, kind, prec, T64, d_offs, dst, plane, gemm_k_chunk());
+  hipLaunchKernelGGL(k_pack, dim3(64, B), dim3(256), 0, s, B, kind, prec, T64, d_offs, dst, plane, gemm_k_chunk(prec));
   return hipGetLastError();
 }
 
