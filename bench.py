@@ -145,6 +145,25 @@ def roofline(form, dtype, B, nf):
     return roof
 
 
+def stage_rooflines(form, dtype, B, nf):
+    """Every stage of a form against HBM (algorithmic bytes) and against its
+    dtype's dense MFMA peak (issued flops; stage (a) runs on the vector ALUs)."""
+    work = stage_work(B, nf, dtype)
+    pk = {"f64": PEAK["f64"], "f32": PEAK["f32"], "split_bf16": PEAK["bf16"]}[dtype]
+    out = {}
+    for st in STAGES:
+        t = form["stage_ms"][st]
+        if not t:
+            continue
+        flops, nbytes = work[st]
+        row = {"ms": t, "hbm_GBps": nbytes / t / 1e6, "hbm_frac": nbytes / t / 1e6 / PEAK["hbm_GBs"]}
+        if "fft" not in st:
+            row["mfma_TFLOPs_issued"] = flops / t / 1e9
+            row["mfma_frac"] = flops / t / 1e9 / pk
+        out[st] = row
+    return out
+
+
 def cpu_baseline(B, n_coef, n_pts, seed):
     """The oracle (plain direct quadrature sums) on a bounded sample, scaled to a full transform."""
     from oracle import direct as D
@@ -322,6 +341,8 @@ def main():
         "f64_round_trip_e_inf": rt64,
         "forms": forms,
         "roofline": roof,
+        "stage_roofline": stage_rooflines(head, args.dtype, B, nf),
+        "coefficients_per_s": head["transforms_per_s"] * nc,
     }
     if "f64" in forms and args.dtype != "f64":
         out["speedup_vs_f64"] = head["transforms_per_s"] / forms["f64"]["transforms_per_s"]
