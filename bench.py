@@ -141,7 +141,7 @@ def roofline(form, dtype, B, nf):
     roof["kernel"] = dom
     roof["avg_launch_ms"] = form["stage_ms"][dom]
     roof["algorithmic_bytes"] = nbytes
-    roof["algorithmic_flops"] = flops // mult
+    roof["algorithmic_flops"] = flops if "fft" in dom else flops // mult
     return roof
 
 

@@ -255,11 +255,49 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
         for (int t = 0; t < nt; ++t) ci.push_back({rows, make_int4(ci_, l, mt, t)});
     }
   }
-  // longest contraction first (persistent blocks then balance like LPT)
+  // XCD-aware order.  Blocks of a launch go round-robin to the chip's 8 XCDs
+  // (each with its own L2), and a persistent grid that is a multiple of 8
+  // keeps list position w on XCD w % 8.  All tiles of one (class, order) read
+  // the same table block, and the row tiles of one column tile the same data
+  // operand, so each (class, order) group goes to one XCD (groups assigned
+  // largest first to the least-loaded XCD) with its tiles adjacent in that
+  // XCD's queue; the queues are interleaved, larger groups first.
   auto order = [](std::vector<Item>& v, std::vector<int4>& out) {
-    std::stable_sort(v.begin(), v.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    constexpr int kXcd = 8;
+    std::map<std::pair<int, int>, std::vector<Item>> groups;
+    for (auto& it : v) groups[{it.w.x, it.w.y}].push_back(it);
+    struct G { int64_t cost; std::vector<Item>* items; };
+    std::vector<G> gs;
+    for (auto& kv : groups) {
+      int64_t c = 0;
+      for (auto& it : kv.second) c += it.cost;
+      std::stable_sort(kv.second.begin(), kv.second.end(),
+                       [](const Item& a, const Item& b) { return a.w.w != b.w.w ? a.w.w < b.w.w : a.w.z < b.w.z; });
+      gs.push_back({c, &kv.second});
+    }
+    std::stable_sort(gs.begin(), gs.end(), [](const G& a, const G& b) { return a.cost > b.cost; });
+    std::vector<std::vector<int4>> q(kXcd);
+    std::vector<int64_t> load(kXcd, 0);
+    for (auto& g : gs) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[x] += g.cost;
+      for (auto& it : *g.items) q[x].push_back(it.w);
+    }
     out.clear();
-    for (auto& it : v) out.push_back(it.w);
+    std::vector<size_t> pos(kXcd, 0);
+    for (size_t left = v.size(); left > 0;) {
+      for (int x = 0; x < kXcd; ++x) {
+        int src = x;
+        if (pos[src] == q[src].size()) {  // this queue ran dry: take from the longest
+          src = 0;
+          for (int y = 1; y < kXcd; ++y)
+            if (q[y].size() - pos[y] > q[src].size() - pos[src]) src = y;
+          if (pos[src] == q[src].size()) break;
+        }
+        out.push_back(q[src][pos[src]++]);
+        --left;
+      }
+    }
   };
   order(bf, wbf);
   order(bi, wbi);
