@@ -61,7 +61,7 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));  // 16-byte operand
 // blocks of 60 KB LDS fit a CU), 64 for FP64.  The packed tables pad K to it.
 template <int PREC> struct Cfg {
   static constexpr int BK = PREC == PREC_F64 ? 64 : 32;
-  static constexpr int PS = BK + 8;  // bf16 LDS pitch (elements)
+  static constexpr int PS = BK;      // bf16 LDS row (elements): unpadded, 16-byte slots swizzled (swz)
   static constexpr int PF = BK + 4;  // f32/f64 LDS pitch (elements)
   static constexpr int XN = BK / 8;  // k per thread in the data-operand staging (8 k groups)
   // 16-byte table vectors per row and per thread
@@ -73,7 +73,38 @@ template <int PREC> struct Cfg {
   static constexpr int NS = PREC == PREC_F32 ? 2 : 1;
   // waves per SIMD the register allocation is held to
   static constexpr int WAVES = PREC == PREC_F64 ? 2 : 4;
+  // Data-operand LDS rows per plane: the split form keeps real and imaginary
+  // parts in two halves 8 rows apart; FP32 and FP64 interleave them.
+  static constexpr int XPAD = PREC == PREC_SPLIT ? 8 : 0;
+  static constexpr int XROWS = 2 * BNC + XPAD;
 };
+
+// LDS row of real column (complex column cc, part re 0 / im 1) of the data operand
+template <int PREC>
+__device__ inline int xrow(int cc, int part) {
+  return PREC == PREC_SPLIT ? part * (BNC + Cfg<PREC>::XPAD) + cc : 2 * cc + part;
+}
+
+// Split-form LDS rows are 64 bytes (32 bf16) of four 16-byte slots; slot g of
+// row r sits at position g ^ ((r >> 2) & 3).  With 64 banks of 4 bytes, the
+// 16-byte table stores (4 lanes per row), the 8-byte data stores (x_thread)
+// and the MFMA operand reads (16 rows, one slot) then each touch every bank
+// at most once per pass.
+__device__ inline int swz(int r, int g) { return g ^ ((r >> 2) & 3); }
+
+// Thread -> (complex column cc, k group kg) of the data-operand staging.  In
+// the split form 32 lanes cover 16 columns x 2 k groups.
+template <int PREC>
+__device__ inline void x_thread(int tid, int& cc, int& kg) {
+  if constexpr (PREC == PREC_SPLIT) {
+    const int lane = tid & 63, wave = tid >> 6;
+    cc = (lane & 15) | ((lane >> 5) << 4) | ((wave & 1) << 5);
+    kg = ((wave >> 1) << 1) | ((lane >> 4) & 1);
+  } else {
+    cc = tid & 63;
+    kg = tid >> 6;
+  }
+}
 
 template <int PREC> struct DT { using t = float; };
 template <> struct DT<PREC_F64> { using t = double; };
@@ -89,12 +120,12 @@ __device__ inline float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) 
 
 template <int PREC> struct Lds {
   static constexpr int a = BM * Cfg<PREC>::PF * (int)sizeof(typename DT<PREC>::t);
-  static constexpr int x = BN * Cfg<PREC>::PF * (int)sizeof(typename DT<PREC>::t);
+  static constexpr int x = Cfg<PREC>::XROWS * Cfg<PREC>::PF * (int)sizeof(typename DT<PREC>::t);
   static constexpr int total = a + x;
 };
 template <> struct Lds<PREC_SPLIT> {
   static constexpr int a = 3 * BM * Cfg<PREC_SPLIT>::PS * 2;
-  static constexpr int x = 3 * BN * Cfg<PREC_SPLIT>::PS * 2;
+  static constexpr int x = 3 * Cfg<PREC_SPLIT>::XROWS * Cfg<PREC_SPLIT>::PS * 2;
   static constexpr int total = a + x;
 };
 
@@ -175,7 +206,7 @@ __device__ inline void load_a(Stage<PREC>& st, const Tile& t, int k0, int tid) {
   const unsigned char* tab = reinterpret_cast<const unsigned char*>(t.tab);
 #pragma unroll
   for (int v = 0; v < C::NA; ++v) {
-    const int e = tid + v * NT;  // plane, row, vector
+    const int e = tid + v * NT;  // plane, row, vector (a row's vectors in consecutive lanes)
     const int p = PREC == PREC_SPLIT ? e / (BM * C::VR) : 0;
     const int rem = e - p * (BM * C::VR);
     const int r = rem / C::VR, kg = rem - r * C::VR;
@@ -197,7 +228,8 @@ __device__ inline void store_a(const Stage<PREC>& st, unsigned char* sm, int tid
     const int p = PREC == PREC_SPLIT ? e / (BM * C::VR) : 0;
     const int rem = e - p * (BM * C::VR);
     const int r = rem / C::VR, kg = rem - r * C::VR;
-    *reinterpret_cast<u4*>(sm + ES * ((p * BM + r) * P + kg * EV)) = st.a[v];
+    const int slot = PREC == PREC_SPLIT ? swz(r, kg) : kg;
+    *reinterpret_cast<u4*>(sm + ES * ((p * BM + r) * P + slot * EV)) = st.a[v];
   }
 }
 
@@ -265,7 +297,7 @@ __device__ inline int x_off(const Tile& t, const XCol<T>& x, int k) {
 template <typename T> struct V2 { using t = float2; };
 template <> struct V2<double> { using t = double2; };
 
-// X chunk: thread -> (complex column cc = tid & 63, k group kg = tid >> 6 of 8
+// X chunk: thread -> (complex column cc, k group kg of XN rows), see x_thread.
 // rows).  Columns and rows past the group are clamped to its last ones: the
 // packed tables are zero past K, and extra columns are never stored.
 template <int PREC, int KIND>
@@ -274,10 +306,11 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol<typenam
   using T = typename DT<PREC>::t;
   using T2 = typename V2<T>::t;
   constexpr int XN = Cfg<PREC>::XN;
-  const int kg = tid >> 6;
+  int cc, kg;
+  x_thread<PREC>(tid, cc, kg);
   const int kb = k0 + kg * XN;
   if constexpr (KIND == K_DEBUG) {
-    const int c = t.col0 + (tid & 63);
+    const int c = t.col0 + cc;
 #pragma unroll
     for (int u = 0; u < XN; ++u) {
       const int k = kb + u;
@@ -331,7 +364,8 @@ template <int PREC>
 __device__ inline void store_x(const Stage<PREC>& st, typename DT<PREC>::t sgn, unsigned char* sm, int tid) {
   using C = Cfg<PREC>;
   constexpr int XN = C::XN;
-  const int cc = tid & 63, kg = tid >> 6;
+  int cc, kg;
+  x_thread<PREC>(tid, cc, kg);
   if constexpr (PREC == PREC_SPLIT) {
     static_assert(XN == 4, "split staging holds 4 k per thread");
     uint16_t* Xs = reinterpret_cast<uint16_t*>(sm + Lds<PREC>::a);
@@ -345,20 +379,21 @@ __device__ inline void store_x(const Stage<PREC>& st, typename DT<PREC>::t sgn, 
         uint2 w;
         w.x = pack_hi(h[p][0], h[p][1]);
         w.y = pack_hi(h[p][2], h[p][3]);
-        *reinterpret_cast<uint2*>(&Xs[(p * BN + 2 * cc + part) * C::PS + kg * XN]) = w;
+        const int row = xrow<PREC>(cc, part);
+        *reinterpret_cast<uint2*>(&Xs[(p * C::XROWS + row) * C::PS + swz(row, kg >> 1) * 8 + (kg & 1) * 4]) = w;
       }
     }
   } else if constexpr (PREC == PREC_F32) {
     static_assert(XN == 4, "f32 staging holds 4 k per thread");
     float* Xs = reinterpret_cast<float*>(sm + Lds<PREC>::a);
-    *reinterpret_cast<float4*>(&Xs[(2 * cc) * C::PF + kg * XN]) =
+    *reinterpret_cast<float4*>(&Xs[xrow<PREC>(cc, 0) * C::PF + kg * XN]) =
         make_float4(sgn * st.xr[0], sgn * st.xr[1], sgn * st.xr[2], sgn * st.xr[3]);
-    *reinterpret_cast<float4*>(&Xs[(2 * cc + 1) * C::PF + kg * XN]) =
+    *reinterpret_cast<float4*>(&Xs[xrow<PREC>(cc, 1) * C::PF + kg * XN]) =
         make_float4(sgn * st.xi[0], sgn * st.xi[1], sgn * st.xi[2], sgn * st.xi[3]);
   } else {
     double* Xs = reinterpret_cast<double*>(sm + Lds<PREC>::a);
-    double* r0 = &Xs[(2 * cc) * C::PF + kg * XN];
-    double* r1 = &Xs[(2 * cc + 1) * C::PF + kg * XN];
+    double* r0 = &Xs[xrow<PREC>(cc, 0) * C::PF + kg * XN];
+    double* r1 = &Xs[xrow<PREC>(cc, 1) * C::PF + kg * XN];
 #pragma unroll
     for (int u = 0; u < XN; u += 2) {
       *reinterpret_cast<double2*>(r0 + u) = make_double2(sgn * st.xr[u], sgn * st.xr[u + 1]);
@@ -401,7 +436,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
 
   auto column = [&](const Tile& tt) {
     XCol<T> x{nullptr, 0, 0, (T)1};
-    if constexpr (KIND != K_DEBUG) x = x_col<KIND>(tt, min(tt.col0 + (tid & 63), tt.Ncc - 1), x_base<PREC, KIND>(tt, cin));
+    if constexpr (KIND != K_DEBUG) {
+      int cc, kg;
+      x_thread<PREC>(tid, cc, kg);
+      x = x_col<KIND>(tt, min(tt.col0 + cc, tt.Ncc - 1), x_base<PREC, KIND>(tt, cin));
+    }
     return x;
   };
   auto fetch = [&](Stage<PREC>& st, const Tile& tt, const XCol<T>& x, int k0) {
@@ -463,9 +502,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
             const uint16_t h0 = f2bf((float)v);
             const double r1 = v - (double)bf2f(h0);
             const uint16_t h1 = f2bf((float)r1);
-            As[(0 * BM + r) * PS + k] = h0;
-            As[(1 * BM + r) * PS + k] = h1;
-            As[(2 * BM + r) * PS + k] = f2bf((float)(r1 - (double)bf2f(h1)));
+            const int ks = swz(r, k >> 3) * 8 + (k & 7);
+            As[(0 * BM + r) * PS + ks] = h0;
+            As[(1 * BM + r) * PS + ks] = h1;
+            As[(2 * BM + r) * PS + ks] = f2bf((float)(r1 - (double)bf2f(h1)));
           } else {
             reinterpret_cast<T*>(sm)[r * PF + k] = (T)v;
           }
@@ -481,22 +521,24 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
       if constexpr (PREC == PREC_SPLIT) {
         const uint16_t* As = reinterpret_cast<const uint16_t*>(sm);
         const uint16_t* Xs = reinterpret_cast<const uint16_t*>(sm + Lds<PREC>::a);
-        for (int kk = 0; kk < BK; kk += 32) {
-          if (kk >= kend) break;
+        static_assert(BK == 32, "one 16x16x32 MFMA step per chunk: lane slot lk covers k 8lk..8lk+7");
+        if (kend > 0) {
           bf8 b[2][3];
 #pragma unroll
           for (int j = 0; j < 2; ++j)
             if (j < nbj)
 #pragma unroll
-              for (int p = 0; p < 3; ++p)
-                b[j][p] = *reinterpret_cast<const bf8*>(&Xs[(p * BN + wc + j * 16 + lr) * PS + kk + 8 * lk]);
+              for (int p = 0; p < 3; ++p) {
+                const int row = xrow<PREC>((wc + j * 16 + lr) >> 1, lr & 1);
+                b[j][p] = *reinterpret_cast<const bf8*>(&Xs[(p * Cfg<PREC>::XROWS + row) * PS + swz(row, lk) * 8]);
+              }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (i >= nbi) continue;
             bf8 a[3];
 #pragma unroll
             for (int p = 0; p < 3; ++p)
-              a[p] = *reinterpret_cast<const bf8*>(&As[(p * BM + wr + i * 16 + lr) * PS + kk + 8 * lk]);
+              a[p] = *reinterpret_cast<const bf8*>(&As[(p * BM + wr + i * 16 + lr) * PS + swz(wr + i * 16 + lr, lk) * 8]);
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
               if (j >= nbj) continue;
@@ -520,7 +562,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
 #pragma unroll
           for (int i = 0; i < 4; ++i) a[i] = As[(wr + i * 16 + lr) * PF + kk + lk];
 #pragma unroll
-          for (int j = 0; j < 2; ++j) b[j] = Xs[(wc + j * 16 + lr) * PF + kk + lk];
+          for (int j = 0; j < 2; ++j) b[j] = Xs[xrow<PREC>((wc + j * 16 + lr) >> 1, lr & 1) * PF + kk + lk];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (i >= nbi) continue;
