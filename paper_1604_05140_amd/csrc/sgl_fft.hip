@@ -455,7 +455,7 @@ __device__ inline void inv_blue(const ClassDesc& C, int j, int col0, int nr, int
 // Bluestein rings with M <= 256.  Each mode is its own kernel so that it gets
 // only the registers its FFT size needs.
 template <typename T, bool RAW, int MODE>
-__global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
+__global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_forward(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                                      int nwork, const void* __restrict__ samples_v) {
   using T2 = typename C2<T>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(256) k_fft_forward(const ClassDesc* __restrict
 }
 
 template <typename T, bool RAW, int MODE>
-__global__ void __launch_bounds__(256) k_fft_inverse(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
+__global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_inverse(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                                      int nwork, void* __restrict__ samples_v) {
   using T2 = typename C2<T>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -706,7 +706,7 @@ template <int MODE>
 static hipError_t fft_fwd(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork, int lds,
                           const void* samples, int max_grid, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
-  dim3 grid(grid_for(nwork, max_grid)), block(256);
+  dim3 grid(grid_for(nwork, max_grid)), block(fft_threads(MODE, prec == PREC_F64));
   if (prec == PREC_F64 && raw)
     hipLaunchKernelGGL((k_fft_forward<double, true, MODE>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   else if (prec == PREC_F64)
@@ -720,7 +720,7 @@ template <int MODE>
 static hipError_t fft_inv(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork, int lds,
                           void* samples, int max_grid, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
-  dim3 grid(grid_for(nwork, max_grid)), block(256);
+  dim3 grid(grid_for(nwork, max_grid)), block(fft_threads(MODE, prec == PREC_F64));
   if (prec == PREC_F64 && raw)
     hipLaunchKernelGGL((k_fft_inverse<double, true, MODE>), grid, block, lds, s, d_cls, d_work, nwork, samples);
   else if (prec == PREC_F64)

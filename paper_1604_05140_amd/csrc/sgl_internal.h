@@ -119,10 +119,15 @@ inline int fft_mode(int L) {
   const int M = fft_bluestein_m(L);
   return M == 0 ? 0 : (M == 512 ? 1 : 2);
 }
-inline int fft_pow2_rpb(int L) {
+// Threads per stage-(a) block: 512 for the single-precision power-of-two
+// family (32 rings per block at L = 256, so spectrum rows are read and written
+// in 256-byte runs), 256 for FP64 (LDS) and the 32 x 16 and Bluestein kernels.
+__host__ __device__ constexpr int fft_threads(int mode, bool f64) { return mode == 0 && !f64 ? 512 : 256; }
+// Rings per block of the register four-step FFT of length L = R1 R2.
+inline int fft_pow2_rpb(int L, int threads) {
   int r1 = 1;
   while (r1 * r1 < L) r1 <<= 1;  // R1 = sqrt(L) or sqrt(2L)
-  return 256 / r1;
+  return threads / r1;
 }
 hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
                            int max_grid, hipStream_t s);

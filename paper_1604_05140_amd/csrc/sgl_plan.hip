@@ -210,9 +210,9 @@ sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
   SGL_HIP_TRY(hipMemcpyAsync(c.soff, so.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice, s));
   SGL_HIP_TRY(hipMemcpyAsync(c.coff, co.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice, s));
   if (fft_pow2_path(L)) {
-    c.rpb = fft_pow2_rpb(L);
+    c.rpb = fft_pow2_rpb(L, fft_threads(fft_mode(L), p->dtype == SGL_F64));
   } else if (c.M) {
-    c.rpb = fft_pow2_rpb(c.M);
+    c.rpb = fft_pow2_rpb(c.M, fft_threads(fft_mode(L), p->dtype == SGL_F64));
   } else {
     // rings per generic-FFT block: 64 KB of LDS for the ping-pong buffers
     const int cap = (int)(65536 / (2 * (size_t)L * es));
