@@ -125,6 +125,16 @@ sgl_status_t sgl_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs,
 /* Inverse transform (Alg. 4): d_coeffs (const) -> d_samples (written). */
 sgl_status_t sgl_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
 
+/* The naive transforms (Alg. 1 forward, Alg. 2 inverse) of every function of
+ * an SGL_F64 plan, same buffers and layouts as sgl_forward / sgl_inverse:
+ * every coefficient is the full quadrature sum over all (2B)^3 grid points
+ * and every sample the full synthesis sum over all coefficients, in FP64, with
+ * basis values from the plan's FP64 tables (O(B^6) work per function; meant
+ * for B <= 64).  SGL_ERR_UNSUPPORTED for other precisions.  Stream-ordered,
+ * no allocation, no synchronization; honours SGL_SAMPLES_RAW. */
+sgl_status_t sgl_naive_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs, void* stream);
+sgl_status_t sgl_naive_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
+
 /* Free everything the plan owns (NULL is accepted). */
 sgl_status_t sgl_plan_destroy(sgl_plan_t plan);
 

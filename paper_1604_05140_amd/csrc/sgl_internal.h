@@ -83,6 +83,11 @@ struct ClassDesc {
   const void* twM;
   void* F;              // stage (a)/(b) workspace, [(2B-1)][2B][nf*2B] complex
   void* g;              // stage (b)/(c) workspace, [l][b][m+l][2B] complex, block l at l^2 nf 2B
+  // FP64 master tables (Legendre blocks by order, radial blocks by degree)
+  const double* P64;
+  const double* R64;
+  // naive forward transform: prefix over l of (2l+1) ceil((B-l)/naive_group()), B+1 entries
+  const int* naive_loff;
 };
 
 // Work items (int4): stage a {class, j, col block, 0}; stage b {class, m, row tile, col tile};
@@ -133,6 +138,13 @@ hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const
                            int max_grid, hipStream_t s);
 hipError_t launch_radial(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
                          const void* coeffs_in, void* coeffs_out, int max_grid, hipStream_t s);
+// Naive transforms (Alg. 1, Alg. 2) of every function of an FP64 plan; d_pre
+// holds the per-class prefix of work items (ncls + 1 entries).
+int naive_group();
+hipError_t launch_naive_forward(const ClassDesc* d_cls, const int64_t* d_pre, int ncls, int64_t nitems,
+                                const void* samples, void* coeffs, bool raw, hipStream_t s);
+hipError_t launch_naive_inverse(const ClassDesc* d_cls, const int64_t* d_pre, int ncls, int64_t nitems,
+                                const void* coeffs, void* samples, bool raw, hipStream_t s);
 hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, const double* X, double* C,
                              hipStream_t s);
 int gemm_tile_m();

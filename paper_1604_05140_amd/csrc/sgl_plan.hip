@@ -33,6 +33,8 @@ struct ClassHost {
   int64_t* coff = nullptr;
   int rpb = 1;
   std::vector<int> radices;
+  int* naive_loff = nullptr;  // see ClassDesc
+  int naive_per = 0;          // naive forward items per function
   int M = 0;  // Bluestein length (0 = not used)
   void* twM = nullptr;
   void* chirp = nullptr;
@@ -67,6 +69,8 @@ struct sgl_plan_s {
   std::vector<void*> allocs;
   ClassDesc* d_cls = nullptr;
   int4* d_work = nullptr;
+  int64_t* d_naive_pre = nullptr;  // [forward prefix (ncls + 1)][inverse prefix (ncls + 1)]
+  int64_t n_naive_f = 0, n_naive_i = 0;
   int off_a = 0, n_a = 0, off_bf = 0, n_bf = 0, off_bi = 0, n_bi = 0, off_cf = 0, n_cf = 0, off_ci = 0, n_ci = 0;
   // stage (a) work by FFT mode (see fft_mode): offsets, counts, LDS bytes
   int off_am[3] = {0, 0, 0}, n_am[3] = {0, 0, 0}, lds_am[3] = {0, 0, 0};
@@ -145,6 +149,8 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
     c.bhf = share->bhf;
     c.bhi = share->bhi;
     c.radices = share->radices;
+    c.naive_loff = share->naive_loff;
+    c.naive_per = share->naive_per;
     return build_class_data(p, c, s);
   }
   SGL_TRY(p->alloc((void**)&c.grid, 6 * (size_t)L * sizeof(double)));
@@ -185,6 +191,14 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
     SGL_TRY(p->alloc(&c.bhf, (size_t)c.M * ces));
     SGL_TRY(p->alloc(&c.bhi, (size_t)c.M * ces));
     SGL_HIP_TRY(build_bluestein(L, c.M, c.chirp, c.bhf, c.bhi, f32, s));
+  }
+  {
+    const int G = naive_group();
+    std::vector<int> lo(B + 1, 0);
+    for (int l = 0; l < B; ++l) lo[l + 1] = lo[l] + (2 * l + 1) * ((B - l + G - 1) / G);
+    c.naive_per = lo[B];
+    SGL_TRY(p->alloc((void**)&c.naive_loff, (B + 1) * sizeof(int)));
+    SGL_HIP_TRY(hipMemcpyAsync(c.naive_loff, lo.data(), (B + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   }
   c.radices = fft_radices(L);
   if ((int)c.radices.size() > kMaxRadices) {
@@ -366,7 +380,25 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
     d.bhi = c.bhi;
     d.F = c.F;
     d.g = c.g;
+    d.P64 = c.P64;
+    d.R64 = c.R64;
+    d.naive_loff = c.naive_loff;
     descs.push_back(d);
+  }
+  {
+    // per-class prefix of naive work items (forward: (function, l, m, n group); inverse: (function, ring))
+    std::vector<int64_t> pf(1, 0), pi(1, 0);
+    for (auto& c : p->classes) {
+      const int64_t nf = (int64_t)c.funcs.size(), L = 2 * c.B;
+      pf.push_back(pf.back() + nf * c.naive_per);
+      pi.push_back(pi.back() + nf * L * L);
+    }
+    p->n_naive_f = pf.back();
+    p->n_naive_i = pi.back();
+    SGL_TRY(p->alloc((void**)&p->d_naive_pre, 2 * pf.size() * sizeof(int64_t)));
+    SGL_HIP_TRY(hipMemcpyAsync(p->d_naive_pre, pf.data(), pf.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    SGL_HIP_TRY(hipMemcpyAsync(p->d_naive_pre + pf.size(), pi.data(), pi.size() * sizeof(int64_t),
+                               hipMemcpyHostToDevice, s));
   }
   SGL_TRY(p->alloc((void**)&p->d_cls, descs.size() * sizeof(ClassDesc)));
   SGL_HIP_TRY(hipMemcpyAsync(p->d_cls, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice, s));
@@ -668,6 +700,26 @@ sgl_status_t sgl_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs,
   if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
   SGL_TRY(check_call(plan, d_samples, plan->tot_s * plan->esz(), d_coeffs, plan->tot_c * plan->esz()));
   return run_direction(plan, 0, d_samples, d_coeffs, (hipStream_t)stream);
+}
+
+sgl_status_t sgl_naive_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  SGL_TRY(check_call(plan, d_samples, plan->tot_s * plan->esz(), d_coeffs, plan->tot_c * plan->esz()));
+  if (plan->dtype != SGL_F64) { set_error("the naive transforms run in SGL_F64 plans only"); return SGL_ERR_UNSUPPORTED; }
+  const int ncls = (int)plan->classes.size();
+  SGL_HIP_TRY(launch_naive_forward(plan->d_cls, plan->d_naive_pre, ncls, plan->n_naive_f, d_samples, d_coeffs,
+                                   (plan->flags & SGL_SAMPLES_RAW) != 0, (hipStream_t)stream));
+  return SGL_OK;
+}
+
+sgl_status_t sgl_naive_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  SGL_TRY(check_call(plan, d_coeffs, plan->tot_c * plan->esz(), d_samples, plan->tot_s * plan->esz()));
+  if (plan->dtype != SGL_F64) { set_error("the naive transforms run in SGL_F64 plans only"); return SGL_ERR_UNSUPPORTED; }
+  const int ncls = (int)plan->classes.size();
+  SGL_HIP_TRY(launch_naive_inverse(plan->d_cls, plan->d_naive_pre + ncls + 1, ncls, plan->n_naive_i, d_coeffs,
+                                   d_samples, (plan->flags & SGL_SAMPLES_RAW) != 0, (hipStream_t)stream));
+  return SGL_OK;
 }
 
 sgl_status_t sgl_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples, void* stream) {

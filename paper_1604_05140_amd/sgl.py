@@ -50,6 +50,8 @@ def _load():
                          ctypes.c_uint], ctypes.c_int),
         "sgl_forward": ([P, P, P, P], ctypes.c_int),
         "sgl_inverse": ([P, P, P, P], ctypes.c_int),
+        "sgl_naive_forward": ([P, P, P, P], ctypes.c_int),
+        "sgl_naive_inverse": ([P, P, P, P], ctypes.c_int),
         "sgl_plan_destroy": ([P], ctypes.c_int),
         "sgl_num_samples": ([ctypes.c_int], ctypes.c_int64),
         "sgl_num_coeffs": ([ctypes.c_int], ctypes.c_int64),
@@ -83,7 +85,7 @@ _HEADER_NAMES = [
     "sgl_plan", "sgl_plan_ex", "sgl_forward", "sgl_inverse", "sgl_plan_destroy", "sgl_num_samples",
     "sgl_num_coeffs", "sgl_coeff_index", "sgl_plan_info", "sgl_offsets", "sgl_grid", "sgl_table",
     "sgl_set_timing", "sgl_stage_times", "sgl_debug_gemm", "sgl_status_string", "sgl_last_error",
-    "sgl_launch_grids",
+    "sgl_launch_grids", "sgl_naive_forward", "sgl_naive_inverse",
 ]
 
 
@@ -227,6 +229,22 @@ def sgl_inverse(plan: Plan, coeffs, samples, stream=None):
     plan._check_tensor(samples, plan.total_samples, "samples")
     _check(_load().sgl_inverse(plan.handle, ctypes.c_void_p(coeffs.data_ptr()), ctypes.c_void_p(samples.data_ptr()),
                                _stream_handle(stream)), "sgl_inverse")
+
+
+def sgl_naive_forward(plan: Plan, samples, coeffs, stream=None):
+    """Alg. 1 (every coefficient as the full quadrature sum), SGL_F64 plans."""
+    plan._check_tensor(samples, plan.total_samples, "samples")
+    plan._check_tensor(coeffs, plan.total_coeffs, "coeffs")
+    _check(_load().sgl_naive_forward(plan.handle, ctypes.c_void_p(samples.data_ptr()),
+                                     ctypes.c_void_p(coeffs.data_ptr()), _stream_handle(stream)), "sgl_naive_forward")
+
+
+def sgl_naive_inverse(plan: Plan, coeffs, samples, stream=None):
+    """Alg. 2 (every sample as the full synthesis sum), SGL_F64 plans."""
+    plan._check_tensor(coeffs, plan.total_coeffs, "coeffs")
+    plan._check_tensor(samples, plan.total_samples, "samples")
+    _check(_load().sgl_naive_inverse(plan.handle, ctypes.c_void_p(coeffs.data_ptr()),
+                                     ctypes.c_void_p(samples.data_ptr()), _stream_handle(stream)), "sgl_naive_inverse")
 
 
 def sgl_plan_destroy(plan: Plan):
