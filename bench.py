@@ -222,6 +222,51 @@ def bench_batched(args, torch, sgl, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_naive(args, torch, sgl, synth, dev):
+    """The paper's Sect. 4 protocol on the GPU, naive (Alg. 1/2) beside fast
+    (Alg. 3/4), both plain FP64: coefficients with real and imaginary parts
+    uniform on (-1, 1), one inverse then one forward transform, errors of the
+    recovered coefficients (maximum absolute and maximum relative, averaged over
+    10 functions), and transforms/s of each."""
+    import numpy as np
+    rows = []
+    for B in [b for b in (2, 4, 8, 16, 32, 64) if b <= args.naive_max_b]:
+        nf = 10
+        c = synth.uniform_coeffs(B, nf, seed=synth.BASE_SEED + 60 + B)
+        plan = sgl.sgl_plan(B, nf, "f64")
+        c_in = torch.from_numpy(c.reshape(-1)).to(dev)
+        s = torch.empty(plan.total_samples, dtype=torch.complex128, device=dev)
+        c_out = torch.empty_like(c_in)
+        row = {"B": B, "functions": nf}
+        for name, inv, fwd in (("naive", sgl.sgl_naive_inverse, sgl.sgl_naive_forward),
+                               ("fast", sgl.sgl_inverse, sgl.sgl_forward)):
+            inv(plan, c_in, s)
+            fwd(plan, s, c_out)
+            torch.cuda.synchronize()
+            reps = 1 if name == "naive" and B >= 32 else 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                inv(plan, c_in, s)
+                fwd(plan, s, c_out)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            got = c_out.cpu().numpy().reshape(nf, -1)
+            d = np.abs(got - c)
+            row[name] = {"ms_per_pair_of_all": dt * 1e3, "transforms_per_s": nf / dt,
+                         "avg_max_abs_err": float(d.max(axis=1).mean()),
+                         "avg_max_rel_err": float((d / np.abs(c)).max(axis=1).mean())}
+        print(f"[bench] naive B={B}: naive {row['naive']['ms_per_pair_of_all']:.2f} ms, "
+              f"fast {row['fast']['ms_per_pair_of_all']:.3f} ms for {nf} pairs", file=sys.stderr, flush=True)
+        rows.append(row)
+        plan.destroy()
+    print(json.dumps({
+        "metric": "naive (Alg. 1/2) vs fast (Alg. 3/4) FP64 SGL transforms on the GPU, Sect. 4 protocol",
+        "unit": "transforms/s", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "inverse then forward transform of 10 functions per bandlimit, coefficients "
+                               "with Re, Im uniform on (-1, 1)"},
+        "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,8 +277,10 @@ def main():
     ap.add_argument("--dtype", default="split_bf16", choices=["split_bf16", "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and FP32 side runs")
-    ap.add_argument("--workload", default="b128", choices=["b128", "batched"],
-                    help="b128: B=128 batch 4 (headline); batched: 256 functions, B uniform in {16..96}")
+    ap.add_argument("--workload", default="b128", choices=["b128", "batched", "naive"],
+                    help="b128: B=128 batch 4 (headline); batched: 256 functions, B uniform in {16..96}; "
+                         "naive: naive vs fast FP64 transforms at B = 2..32 (the paper's Sect. 4 protocol)")
+    ap.add_argument("--naive-max-b", type=int, default=32, help="largest bandlimit of the naive workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -267,6 +314,8 @@ def main():
         return
     if args.workload == "batched":
         return bench_batched(args, torch, sgl, synth, dev)
+    if args.workload == "naive":
+        return bench_naive(args, torch, sgl, synth, dev)
     B, nf = args.B, args.batch
     ns, nc = 8 * B ** 3, num_coeffs(B)
     print(f"[bench] B={B} batch={nf} form={args.dtype}: building inputs", file=sys.stderr, flush=True)
