@@ -91,11 +91,18 @@ def _as_grid(samples: np.ndarray, B: int) -> np.ndarray:
     return s.reshape(2 * B, 2 * B, 2 * B)
 
 
-def forward(samples, B: int, omegas=None, raw: bool = False, i_chunk: int = 64) -> np.ndarray:
+def forward(samples, B: int, omegas=None, raw: bool = False, i_chunk: int = 64,
+            radial_scale: float = 1.0) -> np.ndarray:
     """Forward SGL transform by the quadrature sum of Thm. 3.4.
 
     samples: 8B^3 complex values in psi order; scaled (s = sigma f) unless raw.
     omegas:  optional list of coefficient indices; default all Omega.
+    radial_scale: the radially scaled basis H^s_nlm(x) = s^(-3/2) H_nlm(x/s)
+             (orthonormal on R^3 for every s > 0; the radially scaled SGL
+             functions named in Sect. 5).  Its samples are taken at radii
+             s r_i, and the change of variables x = s y turns the integral of
+             f conj(H^s) into s^(3/2) times the unit-basis quadrature sum of the
+             same sample values.
     Returns complex128 coefficients for the requested omegas.
     """
     bs = get_basis(B)
@@ -114,14 +121,19 @@ def forward(samples, B: int, omegas=None, raw: bool = False, i_chunk: int = 64) 
             h = bs.scaled_function(n, l, m, sl)
             acc += np.sum(w * s[sl] * np.conj(h))
         out[q] = acc
+    if radial_scale != 1.0:
+        out = out * radial_scale ** 1.5
     return out
 
 
-def inverse(coeffs, B: int, points=None, raw: bool = False) -> np.ndarray:
+def inverse(coeffs, B: int, points=None, raw: bool = False, radial_scale: float = 1.0) -> np.ndarray:
     """Inverse SGL transform by direct synthesis (Alg. 2).
 
     coeffs: Omega complex values in omega order.
     points: optional array of (i, j, k) triples; default the full grid.
+    radial_scale: synthesis in the radially scaled basis H^s_nlm(x) =
+             s^(-3/2) H_nlm(x/s) at the points (s r_i, th_j, ph_k): the unit
+             synthesis times s^(-3/2).
     Returns scaled samples s = sigma f (raw f if raw) for the requested points,
     as a flat psi-ordered array for the full grid.
     """
@@ -129,6 +141,8 @@ def inverse(coeffs, B: int, points=None, raw: bool = False) -> np.ndarray:
     c = np.asarray(coeffs, dtype=np.complex128)
     if c.size != num_coeffs(B):
         raise ValueError("expected Omega coefficients")
+    if radial_scale != 1.0:
+        c = c * radial_scale ** -1.5
     g = bs.grid
     if points is None:
         out = np.zeros((2 * B, 2 * B, 2 * B), dtype=np.complex128)
@@ -176,10 +190,11 @@ def error_metrics(ref: np.ndarray, got: np.ndarray) -> dict:
     }
 
 
-def sample_grid_points(B: int):
-    """Cartesian coordinates (x, y, z) of every grid point, psi order, shape (8B^3, 3)."""
+def sample_grid_points(B: int, radial_scale: float = 1.0):
+    """Cartesian coordinates (x, y, z) of every grid point, psi order, shape (8B^3, 3)
+    (radii s r_i for the radially scaled basis)."""
     g = quadrature.sgl_grid(B)
-    r = g["r"][:, None, None]
+    r = radial_scale * g["r"][:, None, None]
     th = g["theta"][None, :, None]
     ph = g["phi"][None, None, :]
     x = r * np.sin(th) * np.cos(ph)

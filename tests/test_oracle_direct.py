@@ -47,6 +47,31 @@ def test_closed_form_coefficients(B):
         assert np.abs(fh - ref).max() < 1e-13 * 4, (B, name)
 
 
+_DEGREE = {"1": 0, "z": 1, "x+iy": 1, "x-iy": 1, "r2": 2}
+
+
+@pytest.mark.parametrize("B,s", [(3, 0.6), (5, 1.9), (8, 3.25)])
+def test_radially_scaled_closed_forms(B, s):
+    """Radially scaled basis H^s_nlm(x) = s^(-3/2) H_nlm(x/s), orthonormal for the
+    weight exp(-|x|^2/s^2), sampled at radii s r_i.  For a homogeneous polynomial
+    p of degree d, <p, H^s_nlm>_s = s^(3/2 + d) <p, H_nlm> by the substitution
+    x = s y in the Gaussian integral (e.g. <1, H^s_100>_s = s^(-3/2) pi^(-3/4)
+    (pi s^2)^(3/2) = s^(3/2) pi^(3/4)); the unit values are the golden closed
+    forms.  Forward and synthesis both."""
+    rows = _load_closed_forms()
+    x, y, z = D.sample_grid_points(B, radial_scale=s).T
+    for name in sorted({r[0] for r in rows}):
+        f = _poly(name, x, y, z)
+        ref = np.zeros(D.num_coeffs(B), dtype=np.complex128)
+        for (nm, n, l, m, v) in rows:
+            if nm == name:
+                ref[D.omega(n, l, m)] = v * s ** (1.5 + _DEGREE[name])
+        fh = D.forward(D.scale_raw(f, B), B, radial_scale=s)
+        assert np.abs(fh - ref).max() < 4e-13 * max(1.0, np.abs(ref).max()), (B, s, name)
+        back = D.inverse(ref, B, raw=True, radial_scale=s)
+        assert np.abs(back - f).max() < 4e-13 * max(1.0, np.abs(f).max()), (B, s, name)
+
+
 @pytest.mark.parametrize("B", [1, 2, 4, 6])
 def test_sgl_gram_is_identity(B):
     """Thm. 3.4 applied to products of basis functions: sum_psi w_psi H_w conj(H_w') = delta."""
