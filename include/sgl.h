@@ -105,6 +105,21 @@ sgl_status_t sgl_plan(sgl_plan_t* out, int B, int batch, int dtype);
  * (order, bandlimit).  flags: any of SGL_SAMPLES_RAW, SGL_GRAPHS, SGL_AUTOTUNE. */
 sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtype, unsigned flags);
 
+/* Like sgl_plan_ex for the radially scaled basis of scale s = radial_scale > 0
+ * (the radially scaled SGL functions named in Sect. 5):
+ *     H^s_nlm(x) = s^(-3/2) H_nlm(x / s),
+ * orthonormal for the weight exp(-|x|^2 / s^2).  Samples are taken at the radii
+ * s r_i (same theta_j, phi_k); the scaled-sample convention keeps the sigma_i of
+ * the unit rule (scaled samples sigma_i f(s r_i, th_j, ph_k); SGL_SAMPLES_RAW:
+ * f(s r_i, th_j, ph_k)).  By the substitution x = s y the transform is the unit
+ * transform with forward coefficients times s^(3/2) (inverse inputs divided by
+ * it); the factor is folded into the packed radial tables at plan time, so the
+ * kernels and their cost are those of s = 1.  sgl_grid returns the radii s r_i;
+ * its log_a, log_sigma and sgl_table stay those of the unit rule.
+ * SGL_ERR_INVALID_ARG for s <= 0 or non-finite s. */
+sgl_status_t sgl_plan_scaled(sgl_plan_t* out, const int* B_list, int nfunc, int dtype, unsigned flags,
+                             double radial_scale);
+
 /* The persistent grid (blocks) of each of the SGL_NUM_SLOTS launch slots, in
  * order: forward FFT of power-of-two rings up to 256 points (and other
  * lengths outside the two Bluestein families), forward FFT of 512-point rings

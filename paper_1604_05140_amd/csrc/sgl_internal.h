@@ -88,6 +88,9 @@ struct ClassDesc {
   const double* R64;
   // naive forward transform: prefix over l of (2l+1) ceil((B-l)/naive_group()), B+1 entries
   const int* naive_loff;
+  // radially scaled basis: coefficient factors of the forward (s^(3/2)) and
+  // inverse (s^(-3/2)) naive transforms (the packed radial tables carry them)
+  double rs_fwd, rs_inv;
 };
 
 // Work items (int4): stage a {class, j, col block, 0}; stage b {class, m, row tile, col tile};
@@ -171,8 +174,9 @@ hipError_t build_bluestein(int L, int M, void* chirp, void* bhf, void* bhi, bool
 hipError_t convert_table_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 hipError_t convert_table_split(const double* src, uint16_t* dst, int64_t n, hipStream_t s);
 // Pack an FP64 natural table (Legendre for kind 0/1, radial for kind 2/3) into the
-// GEMM operand layout of `kind` in precision `prec` (see ClassDesc::A).
+// GEMM operand layout of `kind` in precision `prec` (see ClassDesc::A), every
+// value multiplied by `scale` before rounding.
 hipError_t pack_table(int B, int kind, int prec, const double* T64, const int64_t* d_offs, void* dst,
-                      int64_t plane, hipStream_t s);
+                      int64_t plane, double scale, hipStream_t s);
 
 }  // namespace sgl

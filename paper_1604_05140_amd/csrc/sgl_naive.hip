@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(NT) k_naive_forward(const ClassDesc* __restric
     for (int g = 0; g < nn; ++g) {
       const double sr = block_sum(ar[g], red);
       const double si = block_sum(ai[g], red);
-      if (threadIdx.x == 0) coeffs[C.coff[b] + omega(n0 + g, l, m)] = make_double2(sr, si);
+      if (threadIdx.x == 0) coeffs[C.coff[b] + omega(n0 + g, l, m)] = make_double2(sr * C.rs_fwd, si * C.rs_fwd);
     }
     __syncthreads();
   }
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(NT) k_naive_inverse(const ClassDesc* __restric
         decode_omega(w0 + e, n, l, m);
         const int am = m < 0 ? -m : m;
         const double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
-        const double f = sg * C.R64[table_block(B, l) + (int64_t)(n - l - 1) * L + i] *
+        const double f = sg * C.rs_inv * C.R64[table_block(B, l) + (int64_t)(n - l - 1) * L + i] *
                          C.P64[table_block(B, am) + (int64_t)(l - am) * L + j];
         const double2 x = coeffs[C.coff[b] + w0 + e];
         Q[e] = make_double2(f * x.x, f * x.y);

@@ -2,6 +2,7 @@
 // tables on the GPU, workspace, work lists) and the stream-ordered forward /
 // inverse entry points.  See include/sgl.h for the contract.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -62,6 +63,7 @@ using namespace sgl;
 struct sgl_plan_s {
   int dtype = 0;
   unsigned flags = 0;
+  double rscale = 1.0;  // radial scale s of the basis (1 = the unit SGL basis)
   std::vector<int> Bs;
   std::vector<int64_t> soff, coff;
   int64_t tot_s = 0, tot_c = 0;
@@ -177,7 +179,10 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
     SGL_HIP_TRY(hipMemcpyAsync(c.Aoff[kind], offs.data(), B * sizeof(int64_t), hipMemcpyHostToDevice, s));
     SGL_TRY(p->alloc(&c.A[kind], (size_t)tot * el * (prec == PREC_SPLIT ? 3 : 1)));
     c.Aplane[kind] = tot;
-    SGL_HIP_TRY(pack_table(B, kind, prec, kind < 2 ? c.P64 : c.R64, c.Aoff[kind], c.A[kind], tot, s));
+    // the radially scaled basis H^s = s^(-3/2) H(x/s) multiplies forward coefficients
+    // by s^(3/2) and divides inverse inputs by it: folded into the radial operands
+    const double sc = kind == 2 ? std::pow(p->rscale, 1.5) : (kind == 3 ? std::pow(p->rscale, -1.5) : 1.0);
+    SGL_HIP_TRY(pack_table(B, kind, prec, kind < 2 ? c.P64 : c.R64, c.Aoff[kind], c.A[kind], tot, sc, s));
   }
   const bool f32 = p->dtype != SGL_F64;
   const size_t ces = f32 ? sizeof(float2) : sizeof(double2);
@@ -383,6 +388,8 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
     d.P64 = c.P64;
     d.R64 = c.R64;
     d.naive_loff = c.naive_loff;
+    d.rs_fwd = std::pow(p->rscale, 1.5);
+    d.rs_inv = std::pow(p->rscale, -1.5);
     descs.push_back(d);
   }
   {
@@ -642,8 +649,17 @@ int64_t sgl_coeff_index(int n, int l, int m) {
 }
 
 sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtype, unsigned flags) {
+  return sgl_plan_scaled(out, B_list, nfunc, dtype, flags, 1.0);
+}
+
+sgl_status_t sgl_plan_scaled(sgl_plan_t* out, const int* B_list, int nfunc, int dtype, unsigned flags,
+                             double radial_scale) {
   if (!out) { set_error("null output pointer"); return SGL_ERR_INVALID_ARG; }
   *out = nullptr;
+  if (!(radial_scale > 0.0) || !std::isfinite(radial_scale)) {
+    set_error("radial scale must be positive and finite");
+    return SGL_ERR_INVALID_ARG;
+  }
   if (!B_list || nfunc < 1) { set_error("need at least one function"); return SGL_ERR_INVALID_ARG; }
   if (dtype != SGL_F64 && dtype != SGL_F32 && dtype != SGL_SPLIT_BF16) {
     set_error("unknown dtype");
@@ -664,6 +680,7 @@ sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtyp
   if (!p) { set_error("host allocation failed"); return SGL_ERR_OOM; }
   p->dtype = dtype;
   p->flags = flags;
+  p->rscale = radial_scale;
   p->Bs.assign(B_list, B_list + nfunc);
   for (int f = 0; f < nfunc; ++f) {
     p->soff.push_back(p->tot_s);
@@ -758,6 +775,8 @@ sgl_status_t sgl_grid(sgl_plan_t plan, int B, double* r, double* log_a, double* 
   double* dst[6] = {r, log_a, log_sigma, nullptr, theta, btilde};
   for (int q = 0; q < 6; ++q)
     if (dst[q]) SGL_HIP_TRY(hipMemcpy(dst[q], c->grid + q * L, L * sizeof(double), hipMemcpyDeviceToHost));
+  if (r && plan->rscale != 1.0)
+    for (int i = 0; i < L; ++i) r[i] *= plan->rscale;  // sampling radii of the scaled basis
   return SGL_OK;
 }
 

@@ -403,7 +403,7 @@ __global__ void k_to_split(const double* src, uint16_t* dst, int64_t n) {
 
 // Packed GEMM operand from a natural FP64 table (see ClassDesc::A).
 __global__ void k_pack(int B, int kind, int prec, const double* T64, const int64_t* offs, void* dst,
-                       int64_t plane, int kchunk) {
+                       int64_t plane, int kchunk, double scale) {
   const int q = blockIdx.y;
   const bool fwd = kind == 0 || kind == 2;
   const int L = 2 * B;
@@ -416,7 +416,7 @@ __global__ void k_pack(int B, int kind, int prec, const double* T64, const int64
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     const int r = (int)(e / pitch), k = (int)(e - (int64_t)r * pitch);
     double v = 0.0;
-    if (k < K) v = fwd ? src[(int64_t)r * L + k] : src[(int64_t)k * L + r];
+    if (k < K) v = scale * (fwd ? src[(int64_t)r * L + k] : src[(int64_t)k * L + r]);
     if (prec == PREC_F64) {
       reinterpret_cast<double*>(dst)[base + e] = v;
     } else if (prec == PREC_F32) {
@@ -539,8 +539,9 @@ hipError_t convert_table_f32(const double* src, float* dst, int64_t n, hipStream
 }
 
 hipError_t pack_table(int B, int kind, int prec, const double* T64, const int64_t* d_offs, void* dst,
-                      int64_t plane, hipStream_t s) {
-  hipLaunchKernelGGL(k_pack, dim3(64, B), dim3(256), 0, s, B, kind, prec, T64, d_offs, dst, plane, gemm_k_chunk(prec));
+                      int64_t plane, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(64, B), dim3(256), 0, s, B, kind, prec, T64, d_offs, dst, plane, gemm_k_chunk(prec),
+                     scale);
   return hipGetLastError();
 }
 

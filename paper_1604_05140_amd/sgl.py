@@ -48,6 +48,8 @@ def _load():
         "sgl_plan": ([ctypes.POINTER(P), ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "sgl_plan_ex": ([ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
                          ctypes.c_uint], ctypes.c_int),
+        "sgl_plan_scaled": ([ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                             ctypes.c_uint, ctypes.c_double], ctypes.c_int),
         "sgl_forward": ([P, P, P, P], ctypes.c_int),
         "sgl_inverse": ([P, P, P, P], ctypes.c_int),
         "sgl_naive_forward": ([P, P, P, P], ctypes.c_int),
@@ -85,7 +87,7 @@ _HEADER_NAMES = [
     "sgl_plan", "sgl_plan_ex", "sgl_forward", "sgl_inverse", "sgl_plan_destroy", "sgl_num_samples",
     "sgl_num_coeffs", "sgl_coeff_index", "sgl_plan_info", "sgl_offsets", "sgl_grid", "sgl_table",
     "sgl_set_timing", "sgl_stage_times", "sgl_debug_gemm", "sgl_status_string", "sgl_last_error",
-    "sgl_launch_grids", "sgl_naive_forward", "sgl_naive_inverse",
+    "sgl_launch_grids", "sgl_naive_forward", "sgl_naive_inverse", "sgl_plan_scaled",
 ]
 
 
@@ -214,6 +216,17 @@ def sgl_plan_ex(B_list, dtype=SGL_F64, flags: int = 0) -> Plan:
     arr = (ctypes.c_int * len(B_list))(*[int(b) for b in B_list])
     h = ctypes.c_void_p()
     _check(lib.sgl_plan_ex(ctypes.byref(h), arr, len(B_list), int(dtype), ctypes.c_uint(flags)), "sgl_plan_ex")
+    return Plan(h, dtype)
+
+
+def sgl_plan_scaled(B_list, dtype=SGL_F64, flags: int = 0, radial_scale: float = 1.0) -> Plan:
+    """Plan for the radially scaled basis H^s_nlm(x) = s^(-3/2) H_nlm(x/s)."""
+    lib = _load()
+    dtype = DTYPES.get(dtype, dtype)
+    arr = (ctypes.c_int * len(B_list))(*[int(b) for b in B_list])
+    h = ctypes.c_void_p()
+    _check(lib.sgl_plan_scaled(ctypes.byref(h), arr, len(B_list), int(dtype), ctypes.c_uint(flags),
+                               ctypes.c_double(radial_scale)), "sgl_plan_scaled")
     return Plan(h, dtype)
 
 

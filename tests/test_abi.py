@@ -78,3 +78,11 @@ def test_null_plan_calls_are_rejected():
     assert lib.sgl_inverse(None, None, None, None) == 1
     assert lib.sgl_plan_destroy(None) == 0
     assert lib.sgl_status_string(4) == b"SGL_ERR_OOM"
+
+
+@pytest.mark.parametrize("scale", [0.0, -1.0, float("nan"), float("inf")])
+def test_scaled_plan_rejects_bad_scale(scale):
+    """Argument checks run before any device work."""
+    with pytest.raises(sgl.SglError) as e:
+        sgl.sgl_plan_scaled([4], "f64", 0, scale)
+    assert e.value.status == 1

@@ -7,30 +7,9 @@ import mpmath as mp
 import numpy as np
 import pytest
 
+from closed_forms import DEGREE as _DEGREE, GOLDEN, load_closed_forms as _load_closed_forms, poly as _poly
 from oracle import direct as D, mp_direct, quadrature as Q
 from paper_1604_05140_amd import synth
-
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-
-
-def _load_closed_forms():
-    rows = []
-    with open(os.path.join(GOLDEN, "closed_form_transforms.txt")) as fh:
-        for line in fh:
-            line = line.strip()
-            if not line or line.startswith("#"):
-                continue
-            name, n, l, m, expr = line.split(None, 4)
-            with mp.workdps(30):
-                val = float(eval(expr, {"__builtins__": {}}, {"pi": mp.pi, "sqrt": mp.sqrt}))
-            rows.append((name, int(n), int(l), int(m), val))
-    return rows
-
-
-def _poly(name, x, y, z):
-    return {"1": np.ones_like(x), "z": z, "x+iy": x + 1j * y, "x-iy": x - 1j * y,
-            "r2": x * x + y * y + z * z}[name]
-
 
 @pytest.mark.parametrize("B", [2, 3, 5, 8])
 def test_closed_form_coefficients(B):
@@ -45,9 +24,6 @@ def test_closed_form_coefficients(B):
             if nm == name:
                 ref[D.omega(n, l, m)] = v
         assert np.abs(fh - ref).max() < 1e-13 * 4, (B, name)
-
-
-_DEGREE = {"1": 0, "z": 1, "x+iy": 1, "x-iy": 1, "r2": 2}
 
 
 @pytest.mark.parametrize("B,s", [(3, 0.6), (5, 1.9), (8, 3.25)])
