@@ -150,6 +150,29 @@ sgl_status_t sgl_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples,
 sgl_status_t sgl_naive_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs, void* stream);
 sgl_status_t sgl_naive_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
 
+/* Cartesian midpoint-rule projection (Sect. 5: the field's practice, an
+ * accuracy foil for the sampling-theorem transforms) of every function of an
+ * SGL_F64 plan:
+ *     fhat_nlm ~ dV sum_c f(x_c) conj(H_nlm(x_c)) exp(-|x_c|^2)
+ * (weight of the SGL inner product; radially scaled plans use H^s and
+ * exp(-|x|^2/s^2)).  The grid has nx cells per axis on [-h, h]^3, h =
+ * half_width, cell side d = 2h/nx, dV = d^3, midpoints -h + (i + 1/2) d.
+ * d_values: device, const, nfunc * nx^3 complex128, function f at f * nx^3,
+ * cell (ix, iy, iz) at (ix nx + iy) nx + iz.  d_coeffs: the plan's coefficient
+ * layout, written.  Basis values come from the three-term recurrences per cell
+ * in FP64 (O(nx^3 B^3) work per function).  SGL_ERR_INVALID_ARG for nx outside
+ * [1, 1024] or a non-positive half width; SGL_ERR_UNSUPPORTED unless SGL_F64. */
+sgl_status_t sgl_midpoint_forward(sgl_plan_t plan, const void* d_values, int nx, double half_width, void* d_coeffs,
+                                  void* stream);
+
+/* Synthesis at arbitrary points: values[f * npts + p] = sum_nlm fhat_nlm H_nlm(x_p)
+ * for every function f of an SGL_F64 plan (H^s for radially scaled plans).
+ * d_coeffs: the plan's layout (const); d_xyz: device, const, npts x 3 doubles
+ * (x, y, z), shared by all functions; d_values: device, nfunc * npts complex128,
+ * written.  FP64 recurrences per point; SGL_ERR_UNSUPPORTED unless SGL_F64. */
+sgl_status_t sgl_synthesize_points(sgl_plan_t plan, const void* d_coeffs, int npts, const double* d_xyz,
+                                   void* d_values, void* stream);
+
 /* Free everything the plan owns (NULL is accepted). */
 sgl_status_t sgl_plan_destroy(sgl_plan_t plan);
 

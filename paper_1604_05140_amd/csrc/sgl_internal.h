@@ -88,10 +88,14 @@ struct ClassDesc {
   const double* R64;
   // naive forward transform: prefix over l of (2l+1) ceil((B-l)/naive_group()), B+1 entries
   const int* naive_loff;
-  // radially scaled basis: coefficient factors of the forward (s^(3/2)) and
-  // inverse (s^(-3/2)) naive transforms (the packed radial tables carry them)
-  double rs_fwd, rs_inv;
+  // radially scaled basis: its scale s and the coefficient factors s^(3/2)
+  // (forward) and s^(-3/2) (inverse) used by the naive and off-grid kernels
+  // (the packed radial tables carry them for the fast path)
+  double rscale, rs_fwd, rs_inv;
+  const int* fid;  // plan-wide function index of each function of the class
 };
+// naive / midpoint forward items group this many consecutive degrees n
+constexpr int kNaiveGroup = 8;
 
 // Work items (int4): stage a {class, j, col block, 0}; stage b {class, m, row tile, col tile};
 // stage c {class, l, row tile, col tile}.
@@ -148,6 +152,13 @@ hipError_t launch_naive_forward(const ClassDesc* d_cls, const int64_t* d_pre, in
                                 const void* samples, void* coeffs, bool raw, hipStream_t s);
 hipError_t launch_naive_inverse(const ClassDesc* d_cls, const int64_t* d_pre, int ncls, int64_t nitems,
                                 const void* coeffs, void* samples, bool raw, hipStream_t s);
+// Off-grid FP64 kernels of an SGL_F64 plan: Cartesian midpoint projection
+// (items as the naive forward, d_pre its per-class prefix) and synthesis at
+// arbitrary points (d_pre_nf: per-class prefix of function counts).
+hipError_t launch_midpoint_forward(const ClassDesc* d_cls, const int64_t* d_pre, int ncls, int64_t nitems,
+                                   const void* values, int nx, double h, void* coeffs, hipStream_t s);
+hipError_t launch_synthesize_points(const ClassDesc* d_cls, const int64_t* d_pre_nf, int ncls, int64_t nitems,
+                                    const void* coeffs, int npts, const double* xyz, void* values, hipStream_t s);
 hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, const double* X, double* C,
                              hipStream_t s);
 int gemm_tile_m();

@@ -16,7 +16,7 @@ namespace sgl {
 namespace {
 
 constexpr int NT = 256;  // threads per block
-constexpr int NG = 8;    // coefficients (consecutive n) per forward block
+constexpr int NG = kNaiveGroup;  // coefficients (consecutive n) per forward block
 constexpr int CH = 1024; // coefficients staged per inverse chunk
 
 __device__ inline double2 cmulc(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }

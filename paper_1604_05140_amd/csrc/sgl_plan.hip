@@ -32,6 +32,7 @@ struct ClassHost {
   void* g = nullptr;
   int64_t* soff = nullptr;
   int64_t* coff = nullptr;
+  int* fid = nullptr;
   int rpb = 1;
   std::vector<int> radices;
   int* naive_loff = nullptr;  // see ClassDesc
@@ -71,7 +72,7 @@ struct sgl_plan_s {
   std::vector<void*> allocs;
   ClassDesc* d_cls = nullptr;
   int4* d_work = nullptr;
-  int64_t* d_naive_pre = nullptr;  // [forward prefix (ncls + 1)][inverse prefix (ncls + 1)]
+  int64_t* d_naive_pre = nullptr;  // [forward prefix][inverse prefix][function-count prefix], ncls + 1 each
   int64_t n_naive_f = 0, n_naive_i = 0;
   int off_a = 0, n_a = 0, off_bf = 0, n_bf = 0, off_bi = 0, n_bi = 0, off_cf = 0, n_cf = 0, off_ci = 0, n_ci = 0;
   // stage (a) work by FFT mode (see fft_mode): offsets, counts, LDS bytes
@@ -176,7 +177,7 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
       tot += (int64_t)rows * ((K + KC - 1) / KC * KC);
     }
     SGL_TRY(p->alloc((void**)&c.Aoff[kind], B * sizeof(int64_t)));
-    SGL_HIP_TRY(hipMemcpyAsync(c.Aoff[kind], offs.data(), B * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    SGL_HIP_TRY(hipMemcpy(c.Aoff[kind], offs.data(), B * sizeof(int64_t), hipMemcpyHostToDevice));
     SGL_TRY(p->alloc(&c.A[kind], (size_t)tot * el * (prec == PREC_SPLIT ? 3 : 1)));
     c.Aplane[kind] = tot;
     // the radially scaled basis H^s = s^(-3/2) H(x/s) multiplies forward coefficients
@@ -203,7 +204,7 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
     for (int l = 0; l < B; ++l) lo[l + 1] = lo[l] + (2 * l + 1) * ((B - l + G - 1) / G);
     c.naive_per = lo[B];
     SGL_TRY(p->alloc((void**)&c.naive_loff, (B + 1) * sizeof(int)));
-    SGL_HIP_TRY(hipMemcpyAsync(c.naive_loff, lo.data(), (B + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    SGL_HIP_TRY(hipMemcpy(c.naive_loff, lo.data(), (B + 1) * sizeof(int), hipMemcpyHostToDevice));
   }
   c.radices = fft_radices(L);
   if ((int)c.radices.size() > kMaxRadices) {
@@ -226,8 +227,10 @@ sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
   }
   SGL_TRY(p->alloc((void**)&c.soff, nf * sizeof(int64_t)));
   SGL_TRY(p->alloc((void**)&c.coff, nf * sizeof(int64_t)));
-  SGL_HIP_TRY(hipMemcpyAsync(c.soff, so.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  SGL_HIP_TRY(hipMemcpyAsync(c.coff, co.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  SGL_HIP_TRY(hipMemcpy(c.soff, so.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice));
+  SGL_TRY(p->alloc((void**)&c.fid, nf * sizeof(int)));
+  SGL_HIP_TRY(hipMemcpy(c.fid, c.funcs.data(), nf * sizeof(int), hipMemcpyHostToDevice));
+  SGL_HIP_TRY(hipMemcpy(c.coff, co.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice));
   if (fft_pow2_path(L)) {
     c.rpb = fft_pow2_rpb(L, fft_threads(fft_mode(L), p->dtype == SGL_F64));
   } else if (c.M) {
@@ -334,7 +337,7 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
   p->off_cf = (int)all.size(); p->n_cf = (int)wcf.size(); all.insert(all.end(), wcf.begin(), wcf.end());
   p->off_ci = (int)all.size(); p->n_ci = (int)wci.size(); all.insert(all.end(), wci.begin(), wci.end());
   SGL_TRY(p->alloc((void**)&p->d_work, all.size() * sizeof(int4)));
-  SGL_HIP_TRY(hipMemcpyAsync(p->d_work, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  SGL_HIP_TRY(hipMemcpy(p->d_work, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice));
 
   return SGL_OK;
 }
@@ -388,27 +391,32 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
     d.P64 = c.P64;
     d.R64 = c.R64;
     d.naive_loff = c.naive_loff;
+    d.rscale = p->rscale;
+    d.fid = c.fid;
     d.rs_fwd = std::pow(p->rscale, 1.5);
     d.rs_inv = std::pow(p->rscale, -1.5);
     descs.push_back(d);
   }
   {
     // per-class prefix of naive work items (forward: (function, l, m, n group); inverse: (function, ring))
-    std::vector<int64_t> pf(1, 0), pi(1, 0);
+    std::vector<int64_t> pf(1, 0), pi(1, 0), pn(1, 0);
     for (auto& c : p->classes) {
       const int64_t nf = (int64_t)c.funcs.size(), L = 2 * c.B;
       pf.push_back(pf.back() + nf * c.naive_per);
       pi.push_back(pi.back() + nf * L * L);
+      pn.push_back(pn.back() + nf);
     }
     p->n_naive_f = pf.back();
     p->n_naive_i = pi.back();
-    SGL_TRY(p->alloc((void**)&p->d_naive_pre, 2 * pf.size() * sizeof(int64_t)));
-    SGL_HIP_TRY(hipMemcpyAsync(p->d_naive_pre, pf.data(), pf.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    SGL_HIP_TRY(hipMemcpyAsync(p->d_naive_pre + pf.size(), pi.data(), pi.size() * sizeof(int64_t),
-                               hipMemcpyHostToDevice, s));
+    // [forward prefix][inverse prefix][function-count prefix], ncls + 1 each
+    std::vector<int64_t> all(pf);
+    all.insert(all.end(), pi.begin(), pi.end());
+    all.insert(all.end(), pn.begin(), pn.end());
+    SGL_TRY(p->alloc((void**)&p->d_naive_pre, all.size() * sizeof(int64_t)));
+    SGL_HIP_TRY(hipMemcpy(p->d_naive_pre, all.data(), all.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   }
   SGL_TRY(p->alloc((void**)&p->d_cls, descs.size() * sizeof(ClassDesc)));
-  SGL_HIP_TRY(hipMemcpyAsync(p->d_cls, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice, s));
+  SGL_HIP_TRY(hipMemcpy(p->d_cls, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
   SGL_TRY(build_work(p, s));
   prepare_fft_kernels(p->lds_am);
   if (p->flags & SGL_GRAPHS) SGL_HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
@@ -736,6 +744,44 @@ sgl_status_t sgl_naive_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_sa
   const int ncls = (int)plan->classes.size();
   SGL_HIP_TRY(launch_naive_inverse(plan->d_cls, plan->d_naive_pre + ncls + 1, ncls, plan->n_naive_i, d_coeffs,
                                    d_samples, (plan->flags & SGL_SAMPLES_RAW) != 0, (hipStream_t)stream));
+  return SGL_OK;
+}
+
+sgl_status_t sgl_midpoint_forward(sgl_plan_t plan, const void* d_values, int nx, double half_width, void* d_coeffs,
+                                  void* stream) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  if (nx < 1 || nx > 1024) { set_error("nx must be in [1, 1024]"); return SGL_ERR_INVALID_ARG; }
+  if (!(half_width > 0.0) || !std::isfinite(half_width)) {
+    set_error("half_width must be positive and finite");
+    return SGL_ERR_INVALID_ARG;
+  }
+  const size_t nval = (size_t)plan->Bs.size() * nx * nx * nx;
+  SGL_TRY(check_call(plan, d_values, nval * plan->esz(), d_coeffs, plan->tot_c * plan->esz()));
+  if (plan->dtype != SGL_F64) { set_error("off-grid transforms run in SGL_F64 plans only"); return SGL_ERR_UNSUPPORTED; }
+  const int ncls = (int)plan->classes.size();
+  SGL_HIP_TRY(launch_midpoint_forward(plan->d_cls, plan->d_naive_pre, ncls, plan->n_naive_f, d_values, nx, half_width,
+                                      d_coeffs, (hipStream_t)stream));
+  return SGL_OK;
+}
+
+sgl_status_t sgl_synthesize_points(sgl_plan_t plan, const void* d_coeffs, int npts, const double* d_xyz,
+                                   void* d_values, void* stream) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  if (npts < 0) { set_error("npts must be >= 0"); return SGL_ERR_INVALID_ARG; }
+  if (npts == 0) return SGL_OK;
+  if (!d_xyz) { set_error("null point array"); return SGL_ERR_INVALID_ARG; }
+  const size_t nval = (size_t)plan->Bs.size() * npts;
+  SGL_TRY(check_call(plan, d_coeffs, plan->tot_c * plan->esz(), d_values, nval * plan->esz()));
+  if (overlap(d_xyz, (size_t)npts * 3 * sizeof(double), d_values, nval * plan->esz())) {
+    set_error("points and output overlap");
+    return SGL_ERR_INVALID_ARG;
+  }
+  if (plan->dtype != SGL_F64) { set_error("off-grid transforms run in SGL_F64 plans only"); return SGL_ERR_UNSUPPORTED; }
+  const int ncls = (int)plan->classes.size();
+  const int64_t chunks = (npts + 255) / 256;
+  SGL_HIP_TRY(launch_synthesize_points(plan->d_cls, plan->d_naive_pre + 2 * (ncls + 1), ncls,
+                                       chunks * (int64_t)plan->Bs.size(), d_coeffs, npts, d_xyz, d_values,
+                                       (hipStream_t)stream));
   return SGL_OK;
 }
 

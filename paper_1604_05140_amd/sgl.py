@@ -54,6 +54,8 @@ def _load():
         "sgl_inverse": ([P, P, P, P], ctypes.c_int),
         "sgl_naive_forward": ([P, P, P, P], ctypes.c_int),
         "sgl_naive_inverse": ([P, P, P, P], ctypes.c_int),
+        "sgl_midpoint_forward": ([P, P, ctypes.c_int, ctypes.c_double, P, P], ctypes.c_int),
+        "sgl_synthesize_points": ([P, P, ctypes.c_int, P, P, P], ctypes.c_int),
         "sgl_plan_destroy": ([P], ctypes.c_int),
         "sgl_num_samples": ([ctypes.c_int], ctypes.c_int64),
         "sgl_num_coeffs": ([ctypes.c_int], ctypes.c_int64),
@@ -88,6 +90,7 @@ _HEADER_NAMES = [
     "sgl_num_coeffs", "sgl_coeff_index", "sgl_plan_info", "sgl_offsets", "sgl_grid", "sgl_table",
     "sgl_set_timing", "sgl_stage_times", "sgl_debug_gemm", "sgl_status_string", "sgl_last_error",
     "sgl_launch_grids", "sgl_naive_forward", "sgl_naive_inverse", "sgl_plan_scaled",
+    "sgl_midpoint_forward", "sgl_synthesize_points",
 ]
 
 
@@ -258,6 +261,29 @@ def sgl_naive_inverse(plan: Plan, coeffs, samples, stream=None):
     plan._check_tensor(samples, plan.total_samples, "samples")
     _check(_load().sgl_naive_inverse(plan.handle, ctypes.c_void_p(coeffs.data_ptr()),
                                      ctypes.c_void_p(samples.data_ptr()), _stream_handle(stream)), "sgl_naive_inverse")
+
+
+def sgl_midpoint_forward(plan: Plan, values, nx: int, half_width: float, coeffs, stream=None):
+    """Cartesian midpoint-rule projection of nx^3 cell values per function (SGL_F64 plans)."""
+    plan._check_tensor(values, plan.nfunc * nx ** 3, "values")
+    plan._check_tensor(coeffs, plan.total_coeffs, "coeffs")
+    _check(_load().sgl_midpoint_forward(plan.handle, ctypes.c_void_p(values.data_ptr()), int(nx),
+                                        ctypes.c_double(half_width), ctypes.c_void_p(coeffs.data_ptr()),
+                                        _stream_handle(stream)), "sgl_midpoint_forward")
+
+
+def sgl_synthesize_points(plan: Plan, coeffs, xyz, values, stream=None):
+    """values[f, p] = sum fhat H(x_p) at arbitrary points xyz (npts x 3 float64 CUDA tensor)."""
+    import torch
+    if not isinstance(xyz, torch.Tensor) or not xyz.is_cuda or xyz.dtype != torch.float64 \
+            or not xyz.is_contiguous() or xyz.dim() != 2 or xyz.shape[1] != 3:
+        raise ValueError("xyz must be a contiguous float64 CUDA tensor of shape (npts, 3)")
+    npts = int(xyz.shape[0])
+    plan._check_tensor(coeffs, plan.total_coeffs, "coeffs")
+    plan._check_tensor(values, plan.nfunc * npts, "values")
+    _check(_load().sgl_synthesize_points(plan.handle, ctypes.c_void_p(coeffs.data_ptr()), npts,
+                                         ctypes.c_void_p(xyz.data_ptr()), ctypes.c_void_p(values.data_ptr()),
+                                         _stream_handle(stream)), "sgl_synthesize_points")
 
 
 def sgl_plan_destroy(plan: Plan):
