@@ -267,6 +267,56 @@ def bench_naive(args, torch, sgl, synth, dev):
         "rows": rows}), flush=True)
 
 
+def bench_midpoint(args, torch, sgl, synth, dev):
+    """Sect. 5's foil: the Cartesian midpoint-rule projection (the field's
+    practice) against the sampling-theorem transform, FP64 on the GPU.  A
+    bandlimited function with CN(0,1)/n coefficients is synthesized on the cells
+    of a regular grid on [-h, h]^3 (GPU), projected by the midpoint rule, and
+    compared with its true coefficients, for several cell sizes; the
+    sampling-theorem forward transform of its samples on the SGL grid is timed
+    and checked beside it."""
+    import numpy as np
+    rows = []
+    h = 10.0
+    for B in (8, 16):
+        c = synth.complex_normal_coeffs(B, 1, seed=synth.BASE_SEED + 80 + B, decay=1.0)[0]
+        c_in = torch.from_numpy(c).to(dev)
+        plan = sgl.sgl_plan(B, 1, "f64")
+        s = torch.empty(plan.total_samples, dtype=torch.complex128, device=dev)
+        out = torch.empty(plan.total_coeffs, dtype=torch.complex128, device=dev)
+        sgl.sgl_inverse(plan, c_in, s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sgl.sgl_forward(plan, s, out)
+        torch.cuda.synchronize()
+        t_sgl = time.perf_counter() - t0
+        e_sgl = float((out - c_in).abs().max() / c_in.abs().max())
+        for cell in (1.0, 0.75, 0.5, 0.35, 0.25):
+            nx = int(round(2 * h / cell))
+            ax = -h + (torch.arange(nx, dtype=torch.float64, device=dev) + 0.5) * (2 * h / nx)
+            gx, gy, gz = torch.meshgrid(ax, ax, ax, indexing="ij")
+            xyz = torch.stack([gx.reshape(-1), gy.reshape(-1), gz.reshape(-1)], dim=1).contiguous()
+            vals = torch.empty(nx ** 3, dtype=torch.complex128, device=dev)
+            sgl.sgl_synthesize_points(plan, c_in, xyz, vals)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sgl.sgl_midpoint_forward(plan, vals, nx, h, out)
+            torch.cuda.synchronize()
+            t_mid = time.perf_counter() - t0
+            e_mid = float((out - c_in).abs().max() / c_in.abs().max())
+            rows.append({"B": B, "cell": 2 * h / nx, "nx": nx, "cells": nx ** 3, "midpoint_e_inf": e_mid,
+                         "midpoint_ms": t_mid * 1e3, "sgl_grid_points": 8 * B ** 3, "sgl_e_inf": e_sgl,
+                         "sgl_forward_ms": t_sgl * 1e3})
+            print(f"[bench] midpoint B={B} cell={2 * h / nx:.3f}: e_inf {e_mid:.2e} ({t_mid * 1e3:.2f} ms); "
+                  f"SGL grid e_inf {e_sgl:.2e} ({t_sgl * 1e3:.3f} ms)", file=sys.stderr, flush=True)
+        plan.destroy()
+    print(json.dumps({
+        "metric": "midpoint-rule Cartesian projection vs SGL sampling-theorem transform, FP64 (Sect. 5 foil)",
+        "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"bandlimited functions, CN(0,1)/n coefficients, cells on [-{h}, {h}]^3"},
+        "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,9 +327,10 @@ def main():
     ap.add_argument("--dtype", default="split_bf16", choices=["split_bf16", "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and FP32 side runs")
-    ap.add_argument("--workload", default="b128", choices=["b128", "batched", "naive"],
+    ap.add_argument("--workload", default="b128", choices=["b128", "batched", "naive", "midpoint"],
                     help="b128: B=128 batch 4 (headline); batched: 256 functions, B uniform in {16..96}; "
-                         "naive: naive vs fast FP64 transforms at B = 2..32 (the paper's Sect. 4 protocol)")
+                         "naive: naive vs fast FP64 transforms at B = 2..32 (the paper's Sect. 4 protocol); "
+                         "midpoint: Cartesian midpoint-rule projection vs the sampling-theorem transform")
     ap.add_argument("--naive-max-b", type=int, default=32, help="largest bandlimit of the naive workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
@@ -316,6 +367,8 @@ def main():
         return bench_batched(args, torch, sgl, synth, dev)
     if args.workload == "naive":
         return bench_naive(args, torch, sgl, synth, dev)
+    if args.workload == "midpoint":
+        return bench_midpoint(args, torch, sgl, synth, dev)
     B, nf = args.B, args.batch
     ns, nc = 8 * B ** 3, num_coeffs(B)
     print(f"[bench] B={B} batch={nf} form={args.dtype}: building inputs", file=sys.stderr, flush=True)
