@@ -98,7 +98,7 @@ __device__ void stockham_stage(const T2* in, T2* out, const T2* tw, int L, int R
 }
 
 // ---------------------------------------------------------------------------
-// Power-of-two rings (L = 16 .. 512): register four-step FFT.
+// Power-of-two rings (L = 16 .. 256): register four-step FFT.
 //   x[R2 n1 + n2], X[k1 + R1 k2]:  X = DFT_R2 over n2 of ( w_L^{n2 k1} * DFT_R1 over n1 ),
 // pass 1 holds one n2 column (R1 values) per thread, pass 2 one k1 row (R2
 // values); the exchange goes through LDS laid out [k1][n2][ring] so that both
@@ -133,7 +133,9 @@ __host__ __device__ constexpr int bitrev(int i) {
 }
 
 // In-register DFT of size R (power of two <= 32): v[k] = sum_n v[n] exp(-+2 pi i n k / R).
-template <typename T2, int R, bool INV>
+// HALF_IN: the inputs n >= R/2 are zero (the first butterfly stage is a copy);
+// HALF_OUT: only the outputs k < R/2 are wanted (the others are left stale).
+template <typename T2, int R, bool INV, bool HALF_IN = false, bool HALF_OUT = false>
 __device__ inline void dft_reg(T2 (&v)[R]) {
   using Tr = decltype(v[0].x);
 #pragma unroll
@@ -156,9 +158,31 @@ __device__ inline void dft_reg(T2 (&v)[R]) {
         w.x = (Tr)kCos32[q];
         w.y = INV ? (Tr)kSin32[q] : -(Tr)kSin32[q];
         const T2 u = v[i + j];
-        const T2 t = j == 0 ? v[i + j + len / 2] : cmul(v[i + j + len / 2], w);
+        if (HALF_IN && len == 2) {  // the partner (bit-reversed odd slot) is zero
+          v[i + j + 1] = u;
+          continue;
+        }
+        const T2 x = v[i + j + len / 2];
+        T2 t = x;
+        if (q == 8) {  // times -i (forward) or +i (inverse): a swap, no arithmetic
+          t.x = INV ? -x.y : x.y;
+          t.y = INV ? x.x : -x.x;
+        } else if (q == 4 || q == 12) {  // times (+-1 -+ i) / sqrt 2: add first, one product each
+          const Tr c = (Tr)C32_4;
+          const Tr sx = INV ? x.x - x.y : x.x + x.y;  // q = 4: forward (1 - i), inverse (1 + i)
+          const Tr sy = INV ? x.x + x.y : x.y - x.x;
+          if (q == 4) {
+            t.x = c * sx;
+            t.y = c * sy;
+          } else {  // w^12 = w^4 (-+i)
+            t.x = INV ? -(c * sy) : c * sy;
+            t.y = INV ? c * sx : -(c * sx);
+          }
+        } else if (q != 0) {
+          t = cmul(x, w);
+        }
         v[i + j] = cadd(u, t);
-        v[i + j + len / 2] = csub(u, t);
+        if (!(HALF_OUT && len == R)) v[i + j + len / 2] = csub(u, t);
       }
     }
   }
@@ -283,8 +307,9 @@ __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int
 }
 
 // ---------------------------------------------------------------------------
-// Other ring lengths 6 <= L <= 256: Bluestein's chirp-z form on the register
-// four-step FFT of length M = 2^k >= 2L - 1:
+// Other ring lengths 6 <= L <= 254: Bluestein's chirp-z form on a
+// power-of-two FFT of length M = 2^k >= 2L - 1 (M <= 256 here, on the register
+// four-step FFT; M = 512 on the one-wavefront kernels further down):
 //   X_m = c_m sum_k (x_k c_k) conj(c_{m-k}),  c_p = exp(-i pi p^2 / L),
 // i.e. a cyclic convolution of length M computed as IFFT_M(FFT_M(a) * BH) with
 // the kernel spectrum BH precomputed (1/M folded in).  The inverse DFT uses
@@ -450,12 +475,281 @@ __device__ inline void inv_blue(const ClassDesc& C, int j, int col0, int nr, int
   __syncthreads();
 }
 
-// MODE 0: power-of-two rings up to 256 points and the generic path; MODE 1: the
-// 32 x 16 register FFT (512-point rings, Bluestein length 512); MODE 2:
+// ---------------------------------------------------------------------------
+// 512-point transforms with one wavefront per ring: rings of length 512, and
+// Bluestein rings whose convolution length is 512 (130 <= L <= 254).
+// Lane l holds x[64 a + l] in v[a]; three radix-8 passes:
+//   1: DFT_8 over a -> p, times w_512^(l p);
+//   2: lane 8p + c (c = l mod 8 in pass 1) holds b = 0..7: DFT_8 over b -> q,
+//      times w_64^(c q);
+//   3: lane 8q + p holds c = 0..7: DFT_8 over c -> s, giving
+//      X[p + 8q + 64s] = X[lane + 64s].
+// Input and output share the natural lane order, so the forward transform,
+// the kernel product and the inverse transform of a Bluestein convolution
+// follow one another in registers.  The two exchanges go through an LDS area
+// private to the wavefront, in XOR layouts that are free of bank conflicts
+// for 8- and 16-byte elements, so they need ordering at wavefront scope only.
+// A block is 16 wavefronts = 16 rings of consecutive columns; their areas
+// also stage the spectrum rows, which are read and written in runs of 16
+// columns.
+// ---------------------------------------------------------------------------
+constexpr int kRings512 = 16;  // rings (wavefronts) per block
+
+// Orders LDS accesses of one wavefront (its LDS operations complete in issue
+// order; this keeps the compiler from moving them across).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exchange layouts inside a ring area (elements): the first exchange puts
+// (p, b, c) at 72 p + 8 b + c, the second (p, q, c) at 72 q + 8 p + (c xor p).
+// Every write, and the first read, is a per-lane base plus an immediate
+// offset; the second read adds one xor per element.  Both layouts are free
+// of bank conflicts for single 8-byte accesses (32 lanes per cycle over 64
+// banks) and for the paired ones (ds_read2 / ds_write2: 16 lanes per cycle
+// and element, i.e. addresses distinct mod 16 within each quarter wave).
+// The largest offset is 567; the area pitch is 568 (ring reads at one bin in
+// the staging passes take a few 2- to 8-way conflicts; they are a small part).
+template <typename T2>
+__host__ __device__ constexpr int area_pitch() { return 568; }
+
+// LDS tables ahead of the ring areas (small offsets, so that table reads take
+// immediate offsets): w_512^(l p) at (p-1) 64 + l (p = 1..7), w_64^(c q) at
+// 448 + 8 (q-1) + c, the Bluestein kernel spectrum for k = 0..256 at 504 (it is
+// even in k: BH[512 - k] = BH[k]), the chirp at 761 (256 values, zero from L on).
+constexpr int kTabTw2 = 448, kTabKer = 504, kTabChirp = 761, kTab512 = 1017;
+
+template <typename T2, bool INV>
+__device__ inline T2 tw_sign(T2 w) { return INV ? conjc(w) : w; }
+
+// HALF_IN: x[64 a + l] = 0 for a >= 4; HALF_OUT: only X[l + 64 s], s < 4, wanted.
+template <typename T2, bool INV, bool HALF_IN = false, bool HALF_OUT = false>
+__device__ inline void fft512_wave(T2 (&v)[8], T2* ex, const T2* tab, int l) {
+  const int hi = l >> 3, lo = l & 7;
+  dft_reg<T2, 8, INV, HALF_IN>(v);
+#pragma unroll
+  for (int p = 1; p < 8; ++p) v[p] = cmul(v[p], tw_sign<T2, INV>(tab[(p - 1) * 64 + l]));
+  wave_lds_sync();
+  // first exchange: lane (b, c) = (hi, lo) writes p; lane (p, c) = (hi, lo) reads b
+  T2* w1 = ex + l;
+#pragma unroll
+  for (int p = 0; p < 8; ++p) w1[72 * p] = v[p];
+  wave_lds_sync();
+  const T2* r1 = ex + 72 * hi + lo;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) v[b] = r1[8 * b];
+  dft_reg<T2, 8, INV>(v);
+#pragma unroll
+  for (int q = 1; q < 8; ++q) v[q] = cmul(v[q], tw_sign<T2, INV>(tab[kTabTw2 + 8 * (q - 1) + lo]));
+  wave_lds_sync();
+  // second exchange: lane (p, c) = (hi, lo) writes q; lane (q, p) = (hi, lo) reads c
+  T2* w2 = ex + 8 * hi + (lo ^ hi);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) w2[72 * q] = v[q];
+  wave_lds_sync();
+  // the xor addresses are formed here (an opaque copy of the lane index keeps
+  // the compiler from holding eight of them live across the item loop)
+  int lo2 = lo;
+  asm volatile("" : "+v"(lo2));
+  const T2* r2 = ex + 72 * hi + 8 * lo;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = r2[c ^ lo2];
+  dft_reg<T2, 8, INV, false, HALF_OUT>(v);
+  wave_lds_sync();
+}
+
+// Fill the block's 512-point tables for class C (block-wide; ends synchronised).
+template <typename T2>
+__device__ inline void load_tab512(const ClassDesc& C, const void* kernel_spectrum, T2* tab) {
+  const T2* tw = reinterpret_cast<const T2*>(C.M ? C.twM : C.tw);  // exp(-2 pi i q / 512)
+  for (int q = threadIdx.x; q < 448; q += blockDim.x) {
+    const int p = q / 64 + 1, l = q % 64;
+    tab[q] = tw[(l * p) % 512];
+  }
+  for (int q = threadIdx.x; q < 56; q += blockDim.x) {
+    const int e = q / 8 + 1, c = q % 8;
+    tab[kTabTw2 + q] = tw[8 * ((c * e) % 64)];  // w_64^(c e)
+  }
+  if (C.M) {
+    const T2* bh = reinterpret_cast<const T2*>(kernel_spectrum);
+    for (int q = threadIdx.x; q <= 256; q += blockDim.x) tab[kTabKer + q] = bh[q];
+    const T2* ch = reinterpret_cast<const T2*>(C.chirp);
+    for (int q = threadIdx.x; q < 256; q += blockDim.x) {
+      const T2 c = ch[min(q, C.L - 1)];
+      const bool in = q < C.L;
+      T2 o;
+      o.x = in ? c.x : 0;
+      o.y = in ? c.y : 0;
+      tab[kTabChirp + q] = o;
+    }
+  }
+  __syncthreads();
+}
+
+// Bluestein kernel product in registers: v[s] holds bin l + 64 s.
+template <typename T2>
+__device__ inline void kernel_product(T2 (&v)[8], const T2* tab, int l) {
+  const T2* lo = tab + kTabKer + l;       // bins l + 64 s, s < 4
+  const T2* hi = tab + kTabKer + 64 - l;  // bins 512 - (l + 64 s) = 64 - l + 64 (7 - s), s >= 4
+#pragma unroll
+  for (int s = 0; s < 8; ++s) v[s] = cmul(v[s], s < 4 ? lo[64 * s] : hi[64 * (7 - s)]);
+}
+
+template <typename T, bool RAW>
+__device__ inline void fwd512(const ClassDesc& C, int j, int col0, int nr, const typename C2<T>::t* __restrict__ samples,
+                              const typename C2<T>::t* tab, typename C2<T>::t* smem) {
+  using T2 = typename C2<T>::t;
+  constexpr int P = area_pitch<T2>();
+  const int L = C.L, B = C.B;
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  T2* area = smem + wv * P;
+  const T wj = (T)C.btilde[j];
+  if (wv < nr) {
+    const int col = col0 + wv;
+    const int b = col / L, i = col - b * L;
+    const T2* src = samples + C.soff[b] + ((int64_t)i * L + j) * L;
+    const T sg = RAW ? (T)C.sigma[i] : (T)1;
+    T2 v[8];
+    if (!C.M) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        v[a] = src[64 * a + l];
+        if (RAW) {
+          v[a].x *= sg;
+          v[a].y *= sg;
+        }
+      }
+      fft512_wave<T2, false>(v, area, tab, l);
+    } else {
+      const T2* ch = tab + kTabChirp;
+      // bins k >= L are zero (L <= 254: only a < 4 can hold data): loads are
+      // clamped into the ring, and the chirp table is zero from L on
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int k = 64 * a + l;
+        v[a] = cmul(src[min(k, L - 1)], ch[k]);
+        if (RAW) {
+          v[a].x *= sg;
+          v[a].y *= sg;
+        }
+      }
+#pragma unroll
+      for (int a = 4; a < 8; ++a) v[a].x = v[a].y = 0;
+      fft512_wave<T2, false, true>(v, area, tab, l);
+      kernel_product(v, tab, l);
+      fft512_wave<T2, true, false, true>(v, area, tab, l);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[s] = cmul(v[s], ch[64 * s + l]);
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = 64 * s + l;
+      if (k < L) {
+        T2 o = v[s];
+        o.x *= wj;
+        o.y *= wj;
+        area[k] = o;
+      }
+    }
+  }
+  __syncthreads();
+  // spectrum rows out: thread (row, r) = (tid / 16, tid % 16) takes rows
+  // row, row + 64, ... of column r, so each row leaves as one 16-column run
+  const int r = threadIdx.x & (kRings512 - 1);
+  if (r < nr) {
+    const int ncol = C.nf * L;
+    const int nm = 2 * B - 1;
+    const int64_t step = (int64_t)(blockDim.x / kRings512) * L * ncol;
+    const T2* stage = smem + r * P;
+    int mi = threadIdx.x / kRings512;
+    T2* dst = reinterpret_cast<T2*>(C.F) + ((int64_t)mi * L + j) * ncol + col0 + r;
+    for (; mi < nm; mi += blockDim.x / kRings512, dst += step) {
+      const int m = mi - (B - 1);
+      *dst = stage[m >= 0 ? m : L + m];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, bool RAW>
+__device__ inline void inv512(const ClassDesc& C, int j, int col0, int nr, typename C2<T>::t* __restrict__ samples,
+                              const typename C2<T>::t* tab, typename C2<T>::t* smem) {
+  using T2 = typename C2<T>::t;
+  constexpr int P = area_pitch<T2>();
+  const int L = C.L, B = C.B;
+  const T2* F = reinterpret_cast<const T2*>(C.F);
+  const int ncol = C.nf * L;
+  const T2* ch = tab + kTabChirp;
+  // spectrum rows -> ring areas; bin B (which no coefficient produces) and,
+  // for Bluestein rings, the padding bins L..255 are zero
+  const int nb = C.M ? 256 : L;
+  {
+    const int r = threadIdx.x & (kRings512 - 1);
+    if (r < nr) {
+      T2* stage = smem + r * P;
+      const T2* src = F + (int64_t)j * ncol + col0 + r;
+      const int64_t row = (int64_t)L * ncol;
+      for (int p = threadIdx.x / kRings512; p < nb; p += blockDim.x / kRings512) {
+        T2 v;
+        v.x = 0;
+        v.y = 0;
+        if (p != B && p < L) {
+          const int mi = (p < B ? p : p - L) + B - 1;
+          v = src[mi * row];
+          if (C.M) v = cmul(v, conjc(ch[p]));
+        }
+        stage[p] = v;
+      }
+    }
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  T2* area = smem + wv * P;
+  if (wv < nr) {
+    const int col = col0 + wv;
+    const int b = col / L, i = col - b * L;
+    T2* dst = samples + C.soff[b] + ((int64_t)i * L + j) * L;
+    const T sg = RAW ? (T)(1.0 / C.sigma[i]) : (T)1;
+    T2 v[8];
+    if (!C.M) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) v[a] = area[64 * a + l];
+      fft512_wave<T2, true>(v, area, tab, l);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) v[a] = area[64 * a + l];
+#pragma unroll
+      for (int a = 4; a < 8; ++a) v[a].x = v[a].y = 0;
+      fft512_wave<T2, false, true>(v, area, tab, l);
+      kernel_product(v, tab, l);
+      fft512_wave<T2, true, false, true>(v, area, tab, l);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[s] = cmul(v[s], conjc(ch[64 * s + l]));
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int k = 64 * s + l;
+      if (k < L) {
+        T2 o = v[s];
+        if (RAW) {
+          o.x *= sg;
+          o.y *= sg;
+        }
+        dst[k] = o;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// MODE 0: power-of-two rings up to 256 points and the generic path; MODE 1:
+// 512-point rings and Bluestein length 512, one wavefront per ring; MODE 2:
 // Bluestein rings with M <= 256.  Each mode is its own kernel so that it gets
 // only the registers its FFT size needs.
 template <typename T, bool RAW, int MODE>
-__global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_forward(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
+__global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_waves(MODE, sizeof(T) == 8)) k_fft_forward(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                                      int nwork, const void* __restrict__ samples_v) {
   using T2 = typename C2<T>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -470,7 +764,15 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_forwa
     const int rpb = it.w;
     const int col0 = it.z * rpb;
     const int nr = min(rpb, ncol - col0);
-    if (MODE != 2 && fft_pow2_path(L)) {
+    if constexpr (MODE == 1) {
+      if (it.x != tw_cls) {
+        load_tab512<T2>(C, C.bhf, smem);
+        tw_cls = it.x;
+      }
+      fwd512<T, RAW>(C, j, col0, nr, samples, smem, smem + kTab512);
+      continue;
+    }
+    if (MODE == 0 && fft_pow2_path(L)) {
       T2* twl = smem + L * (rpb + 1);
       if (it.x != tw_cls) {
         const T2* tw = reinterpret_cast<const T2*>(C.tw);
@@ -478,9 +780,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_forwa
         __syncthreads();
         tw_cls = it.x;
       }
-      if constexpr (MODE == 1) {
-        fwd_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, twl);
-      } else {
+      {
         if constexpr (MODE == 0) switch (L) {
           case 16: fwd_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
           case 32: fwd_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
@@ -508,9 +808,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_forwa
         __syncthreads();
         tw_cls = it.x;
       }
-      if constexpr (MODE == 1) {
-        fwd_blue<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs);
-      } else {
+      {
         if constexpr (MODE == 2) switch (M) {
           case 16: fwd_blue<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
           case 32: fwd_blue<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
@@ -567,7 +865,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_forwa
 }
 
 template <typename T, bool RAW, int MODE>
-__global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_inverse(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
+__global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_waves(MODE, sizeof(T) == 8)) k_fft_inverse(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
                                                      int nwork, void* __restrict__ samples_v) {
   using T2 = typename C2<T>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -582,7 +880,15 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_inver
     const int rpb = it.w;
     const int col0 = it.z * rpb;
     const int nr = min(rpb, ncol - col0);
-    if (MODE != 2 && fft_pow2_path(L)) {
+    if constexpr (MODE == 1) {
+      if (it.x != tw_cls) {
+        load_tab512<T2>(C, C.bhi, smem);
+        tw_cls = it.x;
+      }
+      inv512<T, RAW>(C, j, col0, nr, samples, smem, smem + kTab512);
+      continue;
+    }
+    if (MODE == 0 && fft_pow2_path(L)) {
       T2* twl = smem + L * (rpb + 1);
       if (it.x != tw_cls) {
         const T2* tw = reinterpret_cast<const T2*>(C.tw);
@@ -590,9 +896,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_inver
         __syncthreads();
         tw_cls = it.x;
       }
-      if constexpr (MODE == 1) {
-        inv_pow2<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, twl);
-      } else {
+      {
         if constexpr (MODE == 0) switch (L) {
           case 16: inv_pow2<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
           case 32: inv_pow2<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, twl); break;
@@ -620,9 +924,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8)) k_fft_inver
         __syncthreads();
         tw_cls = it.x;
       }
-      if constexpr (MODE == 1) {
-        inv_blue<T, 32, 16, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs);
-      } else {
+      {
         if constexpr (MODE == 2) switch (M) {
           case 16: inv_blue<T, 4, 4, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
           case 32: inv_blue<T, 8, 4, RAW>(C, j, col0, nr, rpb, samples, smem, tws, chs, bhs); break;
@@ -691,6 +993,8 @@ inline int grid_for(int nwork, int max_grid) {
 // LDS bytes for rings_per_block rings of length L in the given precision
 static size_t fft_lds_bytes(int prec, int rpb, int L) {
   const size_t es = prec == PREC_F64 ? sizeof(double2) : sizeof(float2);
+  if (fft_mode(L) == 1)  // ring areas + tables
+    return ((size_t)kRings512 * (prec == PREC_F64 ? area_pitch<double2>() : area_pitch<float2>()) + kTab512) * es;
   if (fft_pow2_path(L)) return (size_t)L * (rpb + 2) * es;  // exchange buffer + twiddle table
   if (const int M = fft_bluestein_m(L)) return ((size_t)M * (rpb + 3) + L) * es;  // buffer + tw, kernel, chirp
   return (size_t)2 * rpb * L * es;

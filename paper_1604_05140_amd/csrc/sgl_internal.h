@@ -133,8 +133,15 @@ inline int fft_mode(int L) {
 }
 // Threads per stage-(a) block: 512 for the single-precision power-of-two
 // family (32 rings per block at L = 256, so spectrum rows are read and written
-// in 256-byte runs), 256 for FP64 (LDS) and the 32 x 16 and Bluestein kernels.
-__host__ __device__ constexpr int fft_threads(int mode, bool f64) { return mode == 0 && !f64 ? 512 : 256; }
+// in 256-byte runs), 1024 for the 512-point kernels (one wavefront per ring,
+// 16 rings), 256 otherwise (FP64 power-of-two, shorter Bluestein lengths).
+__host__ __device__ constexpr int fft_threads(int mode, bool f64) {
+  return mode == 1 ? 1024 : (mode == 0 && !f64 ? 512 : 256);
+}
+// Waves per SIMD the stage-(a) kernels are compiled for: two 1024-thread
+// blocks of the single-precision 512-point kernel per compute unit (LDS holds
+// two), i.e. at most 64 VGPRs; the others as the compiler chooses.
+__host__ __device__ constexpr int fft_min_waves(int mode, bool f64) { return mode == 1 && !f64 ? 8 : 1; }
 // Rings per block of the register four-step FFT of length L = R1 R2.
 inline int fft_pow2_rpb(int L, int threads) {
   int r1 = 1;

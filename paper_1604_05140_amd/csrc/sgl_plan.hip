@@ -231,7 +231,9 @@ sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
   SGL_TRY(p->alloc((void**)&c.fid, nf * sizeof(int)));
   SGL_HIP_TRY(hipMemcpy(c.fid, c.funcs.data(), nf * sizeof(int), hipMemcpyHostToDevice));
   SGL_HIP_TRY(hipMemcpy(c.coff, co.data(), nf * sizeof(int64_t), hipMemcpyHostToDevice));
-  if (fft_pow2_path(L)) {
+  if (fft_mode(L) == 1) {
+    c.rpb = fft_threads(1, p->dtype == SGL_F64) / 64;  // one wavefront per ring
+  } else if (fft_pow2_path(L)) {
     c.rpb = fft_pow2_rpb(L, fft_threads(fft_mode(L), p->dtype == SGL_F64));
   } else if (c.M) {
     c.rpb = fft_pow2_rpb(c.M, fft_threads(fft_mode(L), p->dtype == SGL_F64));

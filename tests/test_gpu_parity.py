@@ -181,6 +181,47 @@ def test_fp64_raw_samples():
     assert einf(f, fg) <= 1e-12
 
 
+@pytest.mark.parametrize("B", [65, 67, 127])
+def test_fp64_512_point_rings(B):
+    """Ring lengths 130..254 run Bluestein's convolution of length 512 on the
+    one-wavefront 512-point kernels (the ragged column tail included: 2 x 2B
+    columns are not a multiple of the 16 rings of a block): forward against the
+    quadrature sum at seeded coefficients, inverse against the synthesis sum at
+    seeded grid points, for arbitrary samples and coefficients."""
+    batch = 2
+    s = synth.complex_normal_samples(B, batch, seed=SEED + 110 + B)
+    c = synth.complex_normal_coeffs(B, batch, seed=SEED + 120 + B)
+    plan = sgl.sgl_plan(B, batch, "f64")
+    assert plan.launch_grids()[1] > 0 and plan.launch_grids()[8] > 0
+    cg = gpu_forward(plan, s).cpu().numpy().reshape(batch, -1)
+    sg = gpu_inverse(plan, c).cpu().numpy().reshape(batch, -1)
+    for b in range(batch):
+        oms = synth.subset(6, D.num_coeffs(B), seed=SEED + 130 + b)
+        f_or = D.forward(s[b], B, omegas=oms)
+        assert np.abs(cg[b][oms] - f_or).max() <= 1e-12 * np.abs(cg[b]).max(), b
+        pts = synth.grid_points(64, B, seed=SEED + 140 + b)
+        s_or = D.inverse(c[b], B, points=pts)
+        s_at = sg[b].reshape(2 * B, 2 * B, 2 * B)[pts[:, 0], pts[:, 1], pts[:, 2]]
+        assert np.abs(s_at - s_or).max() <= 1e-12 * np.abs(sg[b]).max(), b
+    plan.destroy()
+
+
+def test_fp64_raw_samples_512_point_rings():
+    """Raw samples through the 512-point kernels: synthesis of raw values and
+    analysis back to the coefficients (B = 70, rings of 140 points)."""
+    B = 70
+    c = synth.complex_normal_coeffs(B, 1, seed=SEED + 150, decay=1.0)[0]
+    plan = sgl.sgl_plan_ex([B], "f64", sgl.SGL_SAMPLES_RAW)
+    f = gpu_inverse(plan, c)
+    cg = gpu_forward(plan, f).cpu().numpy()
+    assert einf(c, cg) <= 1e-12
+    pts = synth.grid_points(32, B, seed=SEED + 151)
+    f_or = D.inverse(c, B, points=pts, raw=True)
+    f_at = f.cpu().numpy().reshape(2 * B, 2 * B, 2 * B)[pts[:, 0], pts[:, 1], pts[:, 2]]
+    assert np.abs(f_at - f_or).max() <= 1e-12 * np.abs(f_or).max()
+    plan.destroy()
+
+
 def test_fp64_config2_b64_subsets_and_round_trip():
     """B = 64, batch 1, CN(0,1)/n: GPU inverse at 200 seeded grid points against
     the oracle's synthesis sum; GPU forward at 200 seeded coefficients against the
