@@ -88,6 +88,17 @@ typedef enum { SGL_F64 = 0, SGL_F32 = 1, SGL_SPLIT_BF16 = 2 } sgl_dtype_t;
 #define SGL_AUTOTUNE 4u    /* at plan time, time each stage launch with several
                               persistent grid sizes on scratch buffers and keep the
                               fastest (plan creation takes longer) */
+#define SGL_SEMINAIVE 8u   /* seminaive Legendre step (Sect. 3.3.1, Eq. DCT, Eq.
+                              dct_trick): per order m the weighted polar data go
+                              through the orthonormal DCT of length 2B (an FFT of
+                              length 4B per spectrum column; odd orders first take
+                              a sin(theta_j) factor), then the contraction runs
+                              over the cosine indices k < B with the precomputed
+                              cosine-domain Legendre table (zero beyond the degree
+                              l - (m mod 2)); the inverse is the transpose (the
+                              contraction, then the inverse DCT).  Same results as
+                              the direct sums up to rounding.  Power-of-two
+                              bandlimits 8..256 only (SGL_ERR_UNSUPPORTED otherwise). */
 
 #define SGL_MAX_B 256 /* largest supported bandlimit */
 
@@ -102,7 +113,8 @@ sgl_status_t sgl_plan(sgl_plan_t* out, int B, int batch, int dtype);
  * (host array).  Functions are packed back to back in the caller's buffers
  * at the offsets reported by sgl_offsets.  Functions of equal bandlimit share
  * tables; every stage runs as one persistent launch over a work list keyed by
- * (order, bandlimit).  flags: any of SGL_SAMPLES_RAW, SGL_GRAPHS, SGL_AUTOTUNE. */
+ * (order, bandlimit).  flags: any of SGL_SAMPLES_RAW, SGL_GRAPHS, SGL_AUTOTUNE,
+ * SGL_SEMINAIVE. */
 sgl_status_t sgl_plan_ex(sgl_plan_t* out, const int* B_list, int nfunc, int dtype, unsigned flags);
 
 /* Like sgl_plan_ex for the radially scaled basis of scale s = radial_scale > 0
@@ -199,7 +211,11 @@ sgl_status_t sgl_grid(sgl_plan_t plan, int B, double* r, double* log_a, double* 
  * doubles.  which = 0: Legendre table, for m = 0..B-1 the (B-m) x 2B block
  * Pbar_lm(cos th_j), rows l = m..B-1, block offset 2B (m B - m(m-1)/2).
  * which = 1: radial table, for l = 0..B-1 the (B-l) x 2B block
- * rho_nl(r_i) = sigma_i N_nl R_nl(r_i), rows n = l+1..B, same offsets. */
+ * rho_nl(r_i) = sigma_i N_nl R_nl(r_i), rows n = l+1..B, same offsets.
+ * which = 2 (SGL_SEMINAIVE plans): cosine-domain Legendre table, B^2 (B+1) / 2
+ * doubles, for m = 0..B-1 the (B-m) x B block [C_2B q_lm]_k, k < B, with
+ * q_lm = Pbar_lm / sin^(m mod 2) theta (Eq. DCT), rows l = m..B-1, block
+ * offset B (m B - m(m-1)/2); entries beyond k = l - (m mod 2) are zero. */
 sgl_status_t sgl_table(sgl_plan_t plan, int B, int which, double* host_out);
 
 /* Per-stage kernel timing with HIP events recorded on the caller's stream.

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgl.so")
-SOURCES = ["sgl_plan.hip", "sgl_tables.hip", "sgl_fft.hip", "sgl_gemm.hip", "sgl_naive.hip", "sgl_points.hip"]
+SOURCES = ["sgl_plan.hip", "sgl_tables.hip", "sgl_fft.hip", "sgl_gemm.hip", "sgl_naive.hip", "sgl_points.hip",
+           "sgl_dct.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

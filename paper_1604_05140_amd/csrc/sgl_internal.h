@@ -93,6 +93,10 @@ struct ClassDesc {
   // (the packed radial tables carry them for the fast path)
   double rscale, rs_fwd, rs_inv;
   const int* fid;  // plan-wide function index of each function of the class
+  // Legendre contraction length on the polar side: 2B (direct sums over j) or B
+  // (seminaive step: cosine-domain sums over k < B, Sect. 3.3.1)
+  int kb;
+  const void* dct;  // DCT constants of the seminaive step (dct_const_count(B) complex), else null
 };
 // naive / midpoint forward items group this many consecutive degrees n
 constexpr int kNaiveGroup = 8;
@@ -106,8 +110,8 @@ enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_SPLIT = 2 };
 // stage (a) work items carry the rings per block in .w; lds_bytes is the largest
 // fft_lds_bytes_for over the rings of the launch
 // Stage (a) runs as up to three kernels by ring-length family (mode 0: power-of-two
-// rings up to 256 points and the generic path; mode 1: 32 x 16 register FFTs,
-// i.e. 512-point rings and Bluestein length 512; mode 2: Bluestein with M <= 256)
+// rings up to 256 points and the generic path; mode 1: one-wavefront 512-point
+// FFTs, i.e. 512-point rings and Bluestein length 512; mode 2: Bluestein with M <= 256)
 // so that each gets only the registers its FFT size needs.  max_grid bounds the
 // persistent grid (0 = the default bound).
 hipError_t launch_fft_forward(int prec, bool raw, const ClassDesc* d_cls, const int4* d_work, int nwork,
@@ -116,8 +120,8 @@ hipError_t launch_fft_inverse(int prec, bool raw, const ClassDesc* d_cls, const 
                               int lds_bytes, int mode, void* samples, int max_grid, hipStream_t s);
 void prepare_fft_kernels(const int* lds_per_mode);
 size_t fft_lds_bytes_for(int prec, int rpb, int L);
-// power-of-two ring lengths 16..512 take the register four-step path; its rings
-// per block are 256 / R1 with L = R1 * R2, R1 = R2 or 2 R2.
+// power-of-two ring lengths 16..512 take the register FFT paths (the four-step
+// FFT up to 256 points, the one-wavefront kernel at 512).
 __host__ __device__ inline bool fft_pow2_path(int L) { return L >= 16 && L <= 512 && (L & (L - 1)) == 0; }
 // Bluestein convolution length for ring length L (0 if L takes another path)
 __host__ __device__ inline int fft_bluestein_m(int L) {
@@ -194,7 +198,20 @@ hipError_t convert_table_split(const double* src, uint16_t* dst, int64_t n, hipS
 // Pack an FP64 natural table (Legendre for kind 0/1, radial for kind 2/3) into the
 // GEMM operand layout of `kind` in precision `prec` (see ClassDesc::A), every
 // value multiplied by `scale` before rounding.
+// W: grid-side row length of the source table (0: 2B; B for the cosine-domain Legendre table)
 hipError_t pack_table(int B, int kind, int prec, const double* T64, const int64_t* d_offs, void* dst,
-                      int64_t plane, double scale, hipStream_t s);
+                      int64_t plane, double scale, hipStream_t s, int W = 0);
+// Seminaive Legendre step: the FP64 cosine-domain Legendre table (blocks m of
+// (B-m) x B) and the per-class DCT constants (see k_dct_consts; the DCT kernels
+// take them in FP64 for every plan precision).
+hipError_t build_cos_legendre(int B, const double* P64, double* D64, hipStream_t s);
+hipError_t build_dct_consts(int B, void* out, bool f32, hipStream_t s);
+__host__ __device__ inline int dct_const_count(int B) { return 2 * B + B + 2 * B; }
+// DCT launches of the seminaive Legendre step (sgl_dct.hip): items {class, m + B - 1,
+// column tile, columns per tile}; lds_bytes from dct_lds_bytes.
+hipError_t launch_dct(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork, int lds_bytes,
+                      int cols, hipStream_t s);
+size_t dct_lds_bytes(int prec, int B, int cols);
+void prepare_dct_kernels(int lds_bytes);
 
 }  // namespace sgl

@@ -42,6 +42,8 @@ struct ClassHost {
   void* chirp = nullptr;
   void* bhf = nullptr;
   void* bhi = nullptr;
+  double* D64 = nullptr;  // seminaive: FP64 cosine-domain Legendre table (blocks m of (B-m) x B)
+  void* dct = nullptr;    // seminaive: DCT constants (see k_dct_consts)
 };
 
 std::vector<int> fft_radices(int L) {
@@ -75,6 +77,9 @@ struct sgl_plan_s {
   int64_t* d_naive_pre = nullptr;  // [forward prefix][inverse prefix][function-count prefix], ncls + 1 each
   int64_t n_naive_f = 0, n_naive_i = 0;
   int off_a = 0, n_a = 0, off_bf = 0, n_bf = 0, off_bi = 0, n_bi = 0, off_cf = 0, n_cf = 0, off_ci = 0, n_ci = 0;
+  // seminaive Legendre step: DCT work items {class, m + B - 1, column tile, columns per tile}
+  int off_dct = 0, n_dct = 0, dct_cols = 16, dct_lds = 0;
+  bool seminaive() const { return (flags & SGL_SEMINAIVE) != 0; }
   // stage (a) work by FFT mode (see fft_mode): offsets, counts, LDS bytes
   int off_am[3] = {0, 0, 0}, n_am[3] = {0, 0, 0}, lds_am[3] = {0, 0, 0};
   // persistent grid bound per launch slot (0 = kernel default; set by the autotuner)
@@ -154,6 +159,8 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
     c.radices = share->radices;
     c.naive_loff = share->naive_loff;
     c.naive_per = share->naive_per;
+    c.D64 = share->D64;
+    c.dct = share->dct;
     return build_class_data(p, c, s);
   }
   SGL_TRY(p->alloc((void**)&c.grid, 6 * (size_t)L * sizeof(double)));
@@ -162,17 +169,27 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
   SGL_TRY(p->alloc((void**)&c.P64, ts * sizeof(double)));
   SGL_TRY(p->alloc((void**)&c.R64, ts * sizeof(double)));
   SGL_HIP_TRY(build_tables(B, gb.r, gb.log_sig, gb.theta, c.P64, c.R64, s));
+  const bool semi = p->seminaive();
+  if (semi) {
+    // seminaive step: cosine-domain Legendre table and the DCT constants
+    SGL_TRY(p->alloc((void**)&c.D64, ts / 2 * sizeof(double)));
+    SGL_HIP_TRY(build_cos_legendre(B, c.P64, c.D64, s));
+    SGL_TRY(p->alloc(&c.dct, (size_t)dct_const_count(B) * sizeof(double2)));  // FP64 for every precision
+    SGL_HIP_TRY(build_dct_consts(B, c.dct, false, s));
+  }
   // packed GEMM operands, one per contraction direction
   const int prec = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
   const size_t el = prec == PREC_F64 ? 8 : (prec == PREC_F32 ? 4 : 2);
   const int KC = gemm_k_chunk(prec);
   for (int kind = 0; kind < 4; ++kind) {
     const bool fwd = kind == 0 || kind == 2;
+    // grid-side length: 2B, or B for the seminaive cosine-domain Legendre operands
+    const int W = (semi && kind < 2) ? B : L;
     std::vector<int64_t> offs(B);
     int64_t tot = 0;
     for (int q = 0; q < B; ++q) {
-      const int rows = fwd ? B - q : L;
-      const int K = fwd ? L : B - q;
+      const int rows = fwd ? B - q : W;
+      const int K = fwd ? W : B - q;
       offs[q] = tot;
       tot += (int64_t)rows * ((K + KC - 1) / KC * KC);
     }
@@ -183,7 +200,8 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
     // the radially scaled basis H^s = s^(-3/2) H(x/s) multiplies forward coefficients
     // by s^(3/2) and divides inverse inputs by it: folded into the radial operands
     const double sc = kind == 2 ? std::pow(p->rscale, 1.5) : (kind == 3 ? std::pow(p->rscale, -1.5) : 1.0);
-    SGL_HIP_TRY(pack_table(B, kind, prec, kind < 2 ? c.P64 : c.R64, c.Aoff[kind], c.A[kind], tot, sc, s));
+    const double* src = kind < 2 ? (semi ? c.D64 : c.P64) : c.R64;
+    SGL_HIP_TRY(pack_table(B, kind, prec, src, c.Aoff[kind], c.A[kind], tot, sc, s, W));
   }
   const bool f32 = p->dtype != SGL_F64;
   const size_t ces = f32 ? sizeof(float2) : sizeof(double2);
@@ -247,7 +265,14 @@ sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
 
 sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
   const int BM = gemm_tile_m(), BNC = gemm_tile_n_complex();
-  std::vector<int4> wam[3], wbf, wbi, wcf, wci;
+  std::vector<int4> wam[3], wbf, wbi, wcf, wci, wdct;
+  if (p->seminaive()) {
+    // columns per DCT block: 16 unless the 4B-point FP64 column buffers of
+    // B = 256 need the room of 8
+    p->dct_cols = 16;
+    for (auto& c : p->classes)
+      if (dct_lds_bytes(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.B, 16) > 160 * 1024) p->dct_cols = 8;
+  }
   struct Item { int cost; int4 w; };
   std::vector<Item> bf, bi, cf, ci;
   int ldsm[3] = {0, 0, 0};
@@ -260,14 +285,21 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
     for (int j = 0; j < L; ++j)
       for (int cb = 0; cb < ncb; ++cb) wam[mode].push_back(make_int4(ci_, j, cb, c.rpb));
     ldsm[mode] = std::max(ldsm[mode], (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
+    const int kb = p->seminaive() ? B : L;  // polar-side contraction length
     for (int m = 0; m < B; ++m) {
       const int rows = B - m;
       const int ncc = (m ? 2 : 1) * nf * L;
       const int nt = (ncc + BNC - 1) / BNC;
       for (int mt = 0; mt < (rows + BM - 1) / BM; ++mt)
-        for (int t = 0; t < nt; ++t) bf.push_back({L, make_int4(ci_, m, mt, t)});
-      for (int mt = 0; mt < (L + BM - 1) / BM; ++mt)
+        for (int t = 0; t < nt; ++t) bf.push_back({kb, make_int4(ci_, m, mt, t)});
+      for (int mt = 0; mt < (kb + BM - 1) / BM; ++mt)
         for (int t = 0; t < nt; ++t) bi.push_back({rows, make_int4(ci_, m, mt, t)});
+    }
+    if (p->seminaive()) {
+      const int nct = (ncol + p->dct_cols - 1) / p->dct_cols;
+      for (int mi = 0; mi < 2 * B - 1; ++mi)
+        for (int t = 0; t < nct; ++t) wdct.push_back(make_int4(ci_, mi, t, p->dct_cols));
+      p->dct_lds = std::max(p->dct_lds, (int)dct_lds_bytes(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, B, p->dct_cols));
     }
     for (int l = 0; l < B; ++l) {
       const int rows = B - l;
@@ -338,6 +370,7 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
   p->off_bi = (int)all.size(); p->n_bi = (int)wbi.size(); all.insert(all.end(), wbi.begin(), wbi.end());
   p->off_cf = (int)all.size(); p->n_cf = (int)wcf.size(); all.insert(all.end(), wcf.begin(), wcf.end());
   p->off_ci = (int)all.size(); p->n_ci = (int)wci.size(); all.insert(all.end(), wci.begin(), wci.end());
+  p->off_dct = (int)all.size(); p->n_dct = (int)wdct.size(); all.insert(all.end(), wdct.begin(), wdct.end());
   SGL_TRY(p->alloc((void**)&p->d_work, all.size() * sizeof(int4)));
   SGL_HIP_TRY(hipMemcpy(p->d_work, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice));
 
@@ -397,6 +430,8 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
     d.fid = c.fid;
     d.rs_fwd = std::pow(p->rscale, 1.5);
     d.rs_inv = std::pow(p->rscale, -1.5);
+    d.kb = p->seminaive() ? c.B : 2 * c.B;
+    d.dct = c.dct;
     descs.push_back(d);
   }
   {
@@ -421,6 +456,7 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
   SGL_HIP_TRY(hipMemcpy(p->d_cls, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
   SGL_TRY(build_work(p, s));
   prepare_fft_kernels(p->lds_am);
+  if (p->seminaive()) prepare_dct_kernels(p->dct_lds);
   if (p->flags & SGL_GRAPHS) SGL_HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
   SGL_HIP_TRY(hipStreamSynchronize(s));
   return SGL_OK;
@@ -501,13 +537,23 @@ hipError_t launch_slot(sgl_plan_s* p, int slot, const void* in, void* out, hipSt
                                 g, s);
     }
     case S_LEG_F:
+      if (p->seminaive()) {
+        // seminaive step: DCT over the polar index, then the cosine-domain contraction
+        hipError_t e = launch_dct(prec == PREC_F64 ? PREC_F64 : PREC_F32, false, p->d_cls, p->d_work + p->off_dct,
+                                  p->n_dct, p->dct_lds, p->dct_cols, s);
+        if (e != hipSuccess) return e;
+      }
       return launch_legendre(prec, false, p->d_cls, p->d_work + p->off_bf, p->n_bf, g, s);
     case S_RAD_F:
       return launch_radial(prec, false, p->d_cls, p->d_work + p->off_cf, p->n_cf, nullptr, out, g, s);
     case S_RAD_I:
       return launch_radial(prec, true, p->d_cls, p->d_work + p->off_ci, p->n_ci, in, nullptr, g, s);
-    default:
-      return launch_legendre(prec, true, p->d_cls, p->d_work + p->off_bi, p->n_bi, g, s);
+    default: {
+      hipError_t e = launch_legendre(prec, true, p->d_cls, p->d_work + p->off_bi, p->n_bi, g, s);
+      if (e != hipSuccess || !p->seminaive()) return e;
+      return launch_dct(prec == PREC_F64 ? PREC_F64 : PREC_F32, true, p->d_cls, p->d_work + p->off_dct, p->n_dct,
+                        p->dct_lds, p->dct_cols, s);
+    }
   }
 }
 
@@ -675,7 +721,10 @@ sgl_status_t sgl_plan_scaled(sgl_plan_t* out, const int* B_list, int nfunc, int 
     set_error("unknown dtype");
     return SGL_ERR_INVALID_ARG;
   }
-  if (flags & ~(SGL_SAMPLES_RAW | SGL_GRAPHS | SGL_AUTOTUNE)) { set_error("unknown flag"); return SGL_ERR_INVALID_ARG; }
+  if (flags & ~(SGL_SAMPLES_RAW | SGL_GRAPHS | SGL_AUTOTUNE | SGL_SEMINAIVE)) {
+    set_error("unknown flag");
+    return SGL_ERR_INVALID_ARG;
+  }
   if ((flags & SGL_SAMPLES_RAW) && dtype != SGL_F64) {
     set_error("raw samples need SGL_F64 (they leave the FP32 range for B > ~40)");
     return SGL_ERR_UNSUPPORTED;
@@ -684,6 +733,11 @@ sgl_status_t sgl_plan_scaled(sgl_plan_t* out, const int* B_list, int nfunc, int 
     if (B_list[f] < 1 || B_list[f] > SGL_MAX_B) {
       set_error("bandlimit out of range [1, " + std::to_string(SGL_MAX_B) + "]");
       return SGL_ERR_INVALID_ARG;
+    }
+    const int B = B_list[f];
+    if ((flags & SGL_SEMINAIVE) && (B < 8 || (B & (B - 1)) != 0)) {
+      set_error("the seminaive Legendre step needs power-of-two bandlimits >= 8");
+      return SGL_ERR_UNSUPPORTED;
     }
   }
   std::unique_ptr<sgl_plan_s> p(new (std::nothrow) sgl_plan_s());
@@ -829,10 +883,12 @@ sgl_status_t sgl_grid(sgl_plan_t plan, int B, double* r, double* log_a, double* 
 }
 
 sgl_status_t sgl_table(sgl_plan_t plan, int B, int which, double* host_out) {
-  if (!plan || !host_out || (which != 0 && which != 1)) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
+  if (!plan || !host_out || which < 0 || which > 2) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
   const ClassHost* c = find_class(plan, B);
   if (!c) { set_error("bandlimit not in plan"); return SGL_ERR_INVALID_ARG; }
-  SGL_HIP_TRY(hipMemcpy(host_out, which == 0 ? c->P64 : c->R64, table_size(B) * sizeof(double),
+  if (which == 2 && !c->D64) { set_error("not a seminaive plan"); return SGL_ERR_INVALID_ARG; }
+  const double* src = which == 0 ? c->P64 : (which == 1 ? c->R64 : c->D64);
+  SGL_HIP_TRY(hipMemcpy(host_out, src, (which == 2 ? table_size(B) / 2 : table_size(B)) * sizeof(double),
                         hipMemcpyDeviceToHost));
   return SGL_OK;
 }

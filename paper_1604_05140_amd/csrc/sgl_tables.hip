@@ -402,15 +402,17 @@ __global__ void k_to_split(const double* src, uint16_t* dst, int64_t n) {
 }
 
 // Packed GEMM operand from a natural FP64 table (see ClassDesc::A).
+// W: the grid-side length of the table rows (2B; B for the cosine-domain
+// Legendre table, whose block q starts at table_block(B, q) / 2).
 __global__ void k_pack(int B, int kind, int prec, const double* T64, const int64_t* offs, void* dst,
-                       int64_t plane, int kchunk, double scale) {
+                       int64_t plane, int kchunk, double scale, int W) {
   const int q = blockIdx.y;
   const bool fwd = kind == 0 || kind == 2;
-  const int L = 2 * B;
+  const int L = W;
   const int rows = fwd ? B - q : L;
   const int K = fwd ? L : B - q;
   const int pitch = (K + kchunk - 1) / kchunk * kchunk;
-  const double* src = T64 + table_block(B, q);
+  const double* src = T64 + table_block(B, q) / (2 * B) * W;
   const int64_t base = offs[q];
   const int64_t n = (int64_t)rows * pitch;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -539,9 +541,83 @@ hipError_t convert_table_f32(const double* src, float* dst, int64_t n, hipStream
 }
 
 hipError_t pack_table(int B, int kind, int prec, const double* T64, const int64_t* d_offs, void* dst,
-                      int64_t plane, double scale, hipStream_t s) {
+                      int64_t plane, double scale, hipStream_t s, int W) {
   hipLaunchKernelGGL(k_pack, dim3(64, B), dim3(256), 0, s, B, kind, prec, T64, d_offs, dst, plane, gemm_k_chunk(prec),
-                     scale);
+                     scale, W > 0 ? W : 2 * B);
+  return hipGetLastError();
+}
+
+// Cosine-domain Legendre table of the seminaive step (Sect. 3.3.1, Eq. DCT and
+// Eq. dct_trick): block m (m = 0..B-1) holds rows l = m..B-1 of B values
+//   D[l][k] = s_k sum_j cos(k th_j) Pbar_lm(cos th_j) / sin^par th_j,
+// par = m mod 2, th_j = (2j+1) pi / 4B, s_0 = sqrt(1/2B), s_k = sqrt(2/2B),
+// set to zero beyond the degree (k > l - par).  Pbar from the FP64 master table.
+__global__ void k_cos_legendre(int B, const double* P64, double* D64) {
+  const int m = blockIdx.y;
+  const int L = 2 * B;
+  const int par = m & 1;
+  const double* P = P64 + table_block(B, m);
+  double* D = D64 + table_block(B, m) / 2;
+  const int n = (B - m) * B;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int r = e / B, k = e - r * B;
+    const int l = m + r;
+    double v = 0.0;
+    if (k <= l - par) {
+      for (int j = 0; j < L; ++j) {
+        // cos(k (2j+1) pi / 2L): exact argument reduction of the rational multiple of pi
+        const int q = (k * (2 * j + 1)) % (4 * L);
+        double w = cospi((double)q / (double)(2 * L)) * P[(int64_t)r * L + j];
+        if (par) w /= sinpi((double)(2 * j + 1) / (double)(2 * L));
+        v += w;
+      }
+      v *= k == 0 ? sqrt(1.0 / L) : sqrt(2.0 / L);
+    }
+    D[e] = v;
+  }
+}
+
+// Constants of the DCT kernels of a class, P2 = 4B (complex, plan precision):
+// [0, P2/2) the FFT twiddles exp(-2 pi i t / P2); [P2/2, P2/2 + B) the DCT
+// post-factors s_k / 2 exp(-i pi k / 4B); [P2/2 + B, P2/2 + 3B) sin th_j (real part).
+template <typename T2>
+__global__ void k_dct_consts(int B, T2* out) {
+  const int P2 = 4 * B, L = 2 * B;
+  const int n = P2 / 2 + B + L;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    double re, im;
+    if (e < P2 / 2) {
+      sincospi(-2.0 * e / P2, &im, &re);
+    } else if (e < P2 / 2 + B) {
+      const int k = e - P2 / 2;
+      const double sk = (k == 0 ? sqrt(1.0 / L) : sqrt(2.0 / L)) * 0.5;
+      sincospi(-(double)k / (2.0 * L), &im, &re);
+      re *= sk;
+      im *= sk;
+    } else {
+      const int j = e - P2 / 2 - B;
+      re = sinpi((double)(2 * j + 1) / (double)(2 * L));
+      im = 0.0;
+    }
+    T2 v;
+    v.x = re;
+    v.y = im;
+    out[e] = v;
+  }
+}
+
+hipError_t build_cos_legendre(int B, const double* P64, double* D64, hipStream_t s) {
+  hipLaunchKernelGGL(k_cos_legendre, dim3(nblk((int64_t)B * B, 128) < 64 ? nblk((int64_t)B * B, 128) : 64, B),
+                     dim3(128), 0, s, B, P64, D64);
+  return hipGetLastError();
+}
+
+hipError_t build_dct_consts(int B, void* out, bool f32, hipStream_t s) {
+  const int n = 2 * B + B + 2 * B;
+  if (f32)
+    hipLaunchKernelGGL(k_dct_consts<float2>, dim3(nblk(n, 128)), dim3(128), 0, s, B, (float2*)out);
+  else
+    hipLaunchKernelGGL(k_dct_consts<double2>, dim3(nblk(n, 128)), dim3(128), 0, s, B, (double2*)out);
   return hipGetLastError();
 }
 

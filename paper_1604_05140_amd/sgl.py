@@ -21,6 +21,7 @@ SGL_F64, SGL_F32, SGL_SPLIT_BF16 = 0, 1, 2
 SGL_SAMPLES_RAW = 1
 SGL_GRAPHS = 2
 SGL_AUTOTUNE = 4
+SGL_SEMINAIVE = 8
 SGL_MAX_B = 256
 SGL_NUM_SLOTS = 10
 DTYPES = {"f64": SGL_F64, "f32": SGL_F32, "split_bf16": SGL_SPLIT_BF16}
@@ -161,7 +162,7 @@ class Plan:
         return dict(zip(["r", "log_a", "log_sigma", "theta", "btilde"], arrs))
 
     def table(self, B: int, which: int) -> np.ndarray:
-        out = np.zeros(B * B * (B + 1))
+        out = np.zeros(B * B * (B + 1) // (2 if which == 2 else 1))
         _check(_load().sgl_table(self._h, B, which, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "sgl_table")
         return out

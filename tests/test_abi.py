@@ -67,7 +67,7 @@ def test_invalid_plan_ex_arguments():
     assert lib.sgl_plan_ex(ctypes.byref(h), arr, 3, 0, 0) == 1
     arr = (ctypes.c_int * 1)(8)
     assert lib.sgl_plan_ex(ctypes.byref(h), arr, 0, 0, 0) == 1
-    assert lib.sgl_plan_ex(ctypes.byref(h), arr, 1, 0, 8) == 1          # unknown flag
+    assert lib.sgl_plan_ex(ctypes.byref(h), arr, 1, 0, 16) == 1         # unknown flag
     assert lib.sgl_plan_ex(ctypes.byref(h), arr, 1, 1, 1) == 2          # raw samples need FP64
     assert lib.sgl_plan_ex(None, arr, 1, 0, 0) == 1
 
@@ -86,3 +86,14 @@ def test_scaled_plan_rejects_bad_scale(scale):
     with pytest.raises(sgl.SglError) as e:
         sgl.sgl_plan_scaled([4], "f64", 0, scale)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("B", [1, 4, 12, 96, 100])
+def test_seminaive_needs_power_of_two_bandlimits(B):
+    """The seminaive Legendre step takes power-of-two bandlimits >= 8; the check
+    runs before any device work."""
+    lib = _lib()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int * 2)(16, B)
+    assert lib.sgl_plan_ex(ctypes.byref(h), arr, 2, 0, sgl.SGL_SEMINAIVE) == 2
+    assert b"power-of-two" in lib.sgl_last_error()
