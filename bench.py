@@ -222,6 +222,87 @@ def bench_batched(args, torch, sgl, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+def seminaive_stage_work(B, nf, dtype):
+    """Algorithmic flops and HBM bytes of the seminaive Legendre stage (Sect. 3.3.1)
+    per direction: the DCT pass over the spectrum (read F, write the B cosine rows;
+    inverse: read them, write F) plus the contraction over k < B (read the cosine
+    rows and the table, write g; inverse the reverse).  Flops: the 4B-point FFT of
+    every spectrum column and 8 B^4 per function for the contraction (half of the
+    direct 16 B^4; times six issued bf16 products in the split form)."""
+    es = 16 if dtype == "f64" else 8
+    cols = (2 * B - 1) * 2 * B * nf
+    F = cols * 2 * B * es
+    T = cols * B * es
+    g = 2 * B ** 3 * nf * es
+    tab = B * B * (B + 1) // 2 * {"f64": 8, "f32": 4, "split_bf16": 6}[dtype]
+    mult = 6 if dtype == "split_bf16" else 1
+    dct_flops = 5 * 4 * B * math.log2(4 * B) * cols
+    return dct_flops + 8 * B ** 4 * nf * mult, (F + T) + (T + g + tab)
+
+
+def bench_seminaive(args, torch, sgl, synth, dev):
+    """The seminaive Legendre step (SGL_SEMINAIVE) beside the direct sums, B = 128
+    batch 4, in the headline split-bf16 form and in plain FP64: ms per step, the
+    per-stage kernel times, the errors against the FP64 direct path, and the
+    Legendre stages against HBM and the matrix-core peak."""
+    B, nf = args.B, args.batch
+    ns, nc = 8 * B ** 3, num_coeffs(B)
+    c = synth.complex_normal_coeffs(B, nf, seed=synth.BASE_SEED + 3, decay=1.0).reshape(-1)
+    c128 = torch.from_numpy(c).to(dev)
+    p64 = sgl.sgl_plan(B, nf, "f64")
+    s128 = torch.empty(p64.total_samples, dtype=torch.complex128, device=dev)
+    sgl.sgl_inverse(p64, c128, s128)
+    c_ref = torch.empty_like(c128)
+    sgl.sgl_forward(p64, s128, c_ref)
+    torch.cuda.synchronize()
+
+    def einf(ref, got, n):
+        ref = ref.reshape(-1, n).to(torch.complex128)
+        got = got.reshape(-1, n).to(torch.complex128)
+        return float(((got - ref).abs().amax(dim=1) / ref.abs().amax(dim=1)).max())
+
+    forms = {}
+    for dtype in ([args.dtype] + [d for d in ("f64",) if d != args.dtype]):
+        for semi in (True, False):
+            flags = sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS | (sgl.SGL_SEMINAIVE if semi else 0)
+            plan = sgl.sgl_plan_ex([B] * nf, dtype, flags)
+            s_in = s128 if dtype == "f64" else s128.to(torch.complex64)
+            c_in = c128 if dtype == "f64" else c128.to(torch.complex64)
+            print(f"[bench] seminaive={semi} {dtype}: timing", file=sys.stderr, flush=True)
+            ms, ms_inst, per_stage, cout, sout = run_form(sgl, torch, plan, c_in, s_in, args.steps, args.warmup)
+            key = f"{dtype}_{'seminaive' if semi else 'direct'}"
+            forms[key] = {"ms_per_step": ms, "transforms_per_s": nf * 1000.0 / ms, "stage_ms": per_stage,
+                          "e_inf_forward_vs_f64": einf(c_ref, cout, nc),
+                          "e_inf_inverse_vs_f64": einf(s128, sout, ns)}
+            if semi:
+                fl, nb = seminaive_stage_work(B, nf, dtype)
+                pk = {"f64": PEAK["f64"], "f32": PEAK["f32"], "split_bf16": PEAK["bf16"]}[dtype]
+                forms[key]["legendre_roofline"] = {
+                    st: {"ms": per_stage[st], "hbm_GBps": nb / per_stage[st] / 1e6,
+                         "hbm_frac": nb / per_stage[st] / 1e6 / PEAK["hbm_GBs"],
+                         "issued_TFLOPs": fl / per_stage[st] / 1e9, "mfma_frac": fl / per_stage[st] / 1e9 / pk}
+                    for st in ("fwd_b_legendre", "inv_b_legendre")}
+                forms[key]["algorithmic_bytes_per_legendre_launch"] = nb
+            print(f"[bench] {key}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+            del cout, sout
+            plan.destroy()
+    head = forms[f"{args.dtype}_seminaive"]
+    out = {
+        "metric": f"SGL fwd+inv transforms/s at B={B} batch {nf}, seminaive Legendre step (Sect. 3.3.1)",
+        "value": head["transforms_per_s"], "unit": "transforms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"split_bf16": "bf16x3 (fp32 accumulate)", "f32": "f32", "f64": "f64"}[args.dtype],
+        "data": "synthetic",
+        "config": {"workload": f"SGL forward+inverse, B={B}, batch {nf}, complex-normal/n coefficients, "
+                               "seminaive vs direct Legendre step", "form": args.dtype},
+        "forms": forms,
+        "seminaive_over_direct_time": {d: forms[f"{d}_seminaive"]["ms_per_step"] / forms[f"{d}_direct"]["ms_per_step"]
+                                       for d in {args.dtype, "f64"}},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_naive(args, torch, sgl, synth, dev):
     """The paper's Sect. 4 protocol on the GPU, naive (Alg. 1/2) beside fast
     (Alg. 3/4), both plain FP64: coefficients with real and imaginary parts
@@ -327,10 +408,11 @@ def main():
     ap.add_argument("--dtype", default="split_bf16", choices=["split_bf16", "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and FP32 side runs")
-    ap.add_argument("--workload", default="b128", choices=["b128", "batched", "naive", "midpoint"],
+    ap.add_argument("--workload", default="b128", choices=["b128", "batched", "naive", "midpoint", "seminaive"],
                     help="b128: B=128 batch 4 (headline); batched: 256 functions, B uniform in {16..96}; "
                          "naive: naive vs fast FP64 transforms at B = 2..32 (the paper's Sect. 4 protocol); "
-                         "midpoint: Cartesian midpoint-rule projection vs the sampling-theorem transform")
+                         "midpoint: Cartesian midpoint-rule projection vs the sampling-theorem transform; "
+                         "seminaive: the seminaive (cosine-domain) Legendre step beside the direct sums")
     ap.add_argument("--naive-max-b", type=int, default=32, help="largest bandlimit of the naive workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
@@ -369,6 +451,8 @@ def main():
         return bench_naive(args, torch, sgl, synth, dev)
     if args.workload == "midpoint":
         return bench_midpoint(args, torch, sgl, synth, dev)
+    if args.workload == "seminaive":
+        return bench_seminaive(args, torch, sgl, synth, dev)
     B, nf = args.B, args.batch
     ns, nc = 8 * B ** 3, num_coeffs(B)
     print(f"[bench] B={B} batch={nf} form={args.dtype}: building inputs", file=sys.stderr, flush=True)

@@ -15,12 +15,13 @@
 // One block per (order, tile of up to 16 columns), one wavefront per column:
 // the block moves the tile's rows through LDS (each row leaves and arrives as a
 // run of the tile width), and each wavefront runs an in-place radix-2 FFT
-// (bit-reversed input, natural-order output) of its column in LDS.  The
-// transform computes in FP64 for every plan precision (single-precision
-// spectra are widened on load and rounded once on store): a 4B-point FFT in
-// FP32 alone would add ~log2(4B) roundings to the split-bf16 form's 1e-6
-// budget.
-#include "sgl_internal.h"
+// (bit-reversed input, natural-order output) of its column in LDS; at B = 128
+// (4B = 512) the column runs through the three-pass radix-8 one-wavefront FFT
+// instead (natural order in and out, two LDS exchanges).  The transform
+// computes in FP64 for every plan precision (single-precision spectra are
+// widened on load and rounded once on store): a 4B-point FFT in FP32 alone
+// would add ~log2(4B) roundings to the split-bf16 form's 1e-6 budget.
+#include "sgl_wave.h"
 
 namespace sgl {
 namespace {
@@ -30,25 +31,14 @@ template <> struct CT<float> { using t = float2; };
 template <> struct CT<double> { using t = double2; };
 
 template <typename T2>
-__device__ inline T2 cm(T2 a, T2 b) {
-  T2 r;
-  r.x = a.x * b.x - a.y * b.y;
-  r.y = a.x * b.y + a.y * b.x;
-  return r;
-}
+__device__ inline T2 cm(T2 a, T2 b) { return cmul(a, b); }
 template <typename T2>
-__device__ inline T2 cconj(T2 a) {
-  a.y = -a.y;
-  return a;
-}
+__device__ inline T2 cconj(T2 a) { return conjc(a); }
+__device__ inline void wave_sync() { wave_lds_sync(); }
 
-// Orders the LDS accesses of one wavefront (completed in issue order) against
-// compiler motion.
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+// LDS of the 512-point path: the class constants, the 512-point FFT table
+// (w_512^(l p), w_64^(c q)), then 16 column areas of area_pitch elements.
+constexpr int kFftTab = kTabTw2 + 56;
 
 // column pitch (elements): 16 columns read at one row fall on distinct banks
 template <typename T2>
@@ -85,6 +75,86 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
     const T2* sn = post + B;        // sin th_j (real part), j < 2B
     T2* bufs = tab + nconst;
     S2* Fb = reinterpret_cast<S2*>(C.F) + (int64_t)mi * L * ncol + col0;
+    if (P2 == 512) {
+      // --- 512-point path (B = 128): columns in areas of area_pitch elements ---
+      T2* ftab = bufs;                  // w_512^(l p), w_64^(c q)
+      T2* areas = ftab + kFftTab;
+      constexpr int AP = area_pitch<double2>();
+      for (int q = threadIdx.x; q < kFftTab; q += blockDim.x) {
+        // exponent e of w_512^e from the half-circle table (w^(e+256) = -w^e)
+        const int e = q < kTabTw2 ? ((q % 64) * (q / 64 + 1)) % 512 : 8 * ((((q - kTabTw2) / 8 + 1) * (q % 8)) % 64);
+        T2 v = tw[e & 255];
+        if (e >= 256) {
+          v.x = -v.x;
+          v.y = -v.y;
+        }
+        ftab[q] = v;
+      }
+      if (!INV) {
+        for (int e = threadIdx.x; e < L * nc; e += blockDim.x) {
+          const int j = e / nc, r = e - j * nc;
+          const S2 f = Fb[(int64_t)j * ncol + r];
+          const double sg = par ? sn[j].x : 1.0;
+          areas[r * AP + j] = make_double2(f.x * sg, f.y * sg);
+        }
+      } else {
+        for (int e = threadIdx.x; e < nc * AP; e += blockDim.x) areas[e] = make_double2(0.0, 0.0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < B * nc; e += blockDim.x) {
+          const int k = e / nc, r = e - k * nc;
+          const S2 f = Fb[(int64_t)k * ncol + r];
+          const T2 u = make_double2(f.x, f.y);
+          const T2 p = post[k];
+          T2 a = cm(u, cconj(p));
+          a.x += a.x;
+          a.y += a.y;
+          areas[r * AP + k] = a;
+          if (k > 0) {
+            T2 c = cm(u, p);
+            c.x += c.x;
+            c.y += c.y;
+            areas[r * AP + P2 - k] = c;
+          }
+        }
+      }
+      __syncthreads();
+      const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+      if (wv < nc) {
+        T2* area = areas + wv * AP;
+        T2 v[8];
+        const T2 a0 = area[0];
+        if (!INV) {
+          // even extension: y[n] = x[n] (n < 256), y[511 - n] = x[n]
+#pragma unroll
+          for (int a = 0; a < 8; ++a) v[a] = a < 4 ? area[64 * a + l] : area[64 * (7 - a) + 63 - l];
+          fft512_wave<T2, false>(v, area, ftab, l);
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2) area[64 * s2 + l] = cm(v[s2], post[64 * s2 + l]);
+        } else {
+#pragma unroll
+          for (int a = 0; a < 8; ++a) v[a] = area[64 * a + l];
+          fft512_wave<T2, true>(v, area, ftab, l);
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int j = 64 * s4 + l;
+            const double f = par ? 0.5 * sn[j].x : 0.5;
+            area[j] = make_double2((v[s4].x + a0.x) * f, (v[s4].y + a0.y) * f);
+          }
+        }
+      }
+      __syncthreads();
+      const int nrow = INV ? L : B;
+      for (int e = threadIdx.x; e < nrow * nc; e += blockDim.x) {
+        const int j = e / nc, r = e - j * nc;
+        const T2 v = areas[r * AP + j];
+        S2 o;
+        o.x = v.x;
+        o.y = v.y;
+        Fb[(int64_t)j * ncol + r] = o;
+      }
+      __syncthreads();
+      continue;
+    }
     if (!INV) {
       // rows j of the tile -> bit-reversed slots j and 4B-1-j of the even extension
       for (int e = threadIdx.x; e < L * nc; e += blockDim.x) {
@@ -183,6 +253,8 @@ void allow(K kernel, int bytes) {
 }  // namespace
 
 size_t dct_lds_bytes(int, int B, int cols) {
+  if (4 * B == 512)
+    return ((size_t)dct_const_count(B) + kFftTab + (size_t)cols * area_pitch<double2>()) * sizeof(double2);
   return ((size_t)dct_const_count(B) + (size_t)cols * (4 * B + col_pad<double2>())) * sizeof(double2);
 }
 
