@@ -150,6 +150,9 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
         S2 o;
         o.x = v.x;
         o.y = v.y;
+        if (INV)
+        store_stream(&Fb[(int64_t)j * ncol + r], o);  // read once by the inverse FFT
+      else
         Fb[(int64_t)j * ncol + r] = o;
       }
       __syncthreads();
@@ -237,7 +240,10 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
       S2 o;
       o.x = v.x;
       o.y = v.y;
-      Fb[(int64_t)j * ncol + r] = o;
+      if (INV)
+        store_stream(&Fb[(int64_t)j * ncol + r], o);  // read once by the inverse FFT
+      else
+        Fb[(int64_t)j * ncol + r] = o;
     }
     __syncthreads();
   }

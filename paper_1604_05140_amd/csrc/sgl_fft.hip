@@ -134,7 +134,7 @@ __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int
         T2 o = y[k2];
         o.x *= wj;
         o.y *= wj;
-        F[((int64_t)mi * L + j) * ncol + col0 + r] = o;
+        store_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r], o);
       }
     }
   }
@@ -194,7 +194,7 @@ __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int
         }
       }
 #pragma unroll
-      for (int n1 = 0; n1 < R1; ++n1) dst[R2 * n1 + n2] = v[n1];
+      for (int n1 = 0; n1 < R1; ++n1) store_stream(&dst[R2 * n1 + n2], v[n1]);
     }
   }
   __syncthreads();
@@ -309,7 +309,7 @@ __device__ inline void fwd_blue(const ClassDesc& C, int j, int col0, int nr, int
       T2 o = cmul(z[n1], chirp[idx]);
       o.x *= wj;
       o.y *= wj;
-      F[((int64_t)mi * L + j) * ncol + col0 + r] = o;
+      store_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r], o);
     }
   }
   __syncthreads();
@@ -363,7 +363,7 @@ __device__ inline void inv_blue(const ClassDesc& C, int j, int col0, int nr, int
         o.x *= sg;
         o.y *= sg;
       }
-      dst[idx] = o;
+      store_stream(&dst[idx], o);
     }
   }
   __syncthreads();
@@ -502,7 +502,7 @@ __device__ inline void fwd512(const ClassDesc& C, int j, int col0, int nr, const
     T2* dst = reinterpret_cast<T2*>(C.F) + ((int64_t)mi * L + j) * ncol + col0 + r;
     for (; mi < nm; mi += blockDim.x / kRings512, dst += step) {
       const int m = mi - (B - 1);
-      *dst = stage[m >= 0 ? m : L + m];
+      store_stream(dst, stage[m >= 0 ? m : L + m]);
     }
   }
   __syncthreads();
@@ -572,7 +572,7 @@ __device__ inline void inv512(const ClassDesc& C, int j, int col0, int nr, typen
           o.x *= sg;
           o.y *= sg;
         }
-        dst[k] = o;
+        store_stream(&dst[k], o);
       }
     }
   }
@@ -693,7 +693,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       T2 v = cur[r * L + bin];
       v.x *= wj;
       v.y *= wj;
-      F[((int64_t)mi * L + j) * ncol + col0 + r] = v;
+      store_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r], v);
     }
     __syncthreads();
   }
@@ -812,7 +812,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
         v.x *= sg;
         v.y *= sg;
       }
-      samples[C.soff[b] + ((int64_t)i * L + j) * L + k] = v;
+      store_stream(&samples[C.soff[b] + ((int64_t)i * L + j) * L + k], v);
     }
     __syncthreads();
   }

@@ -704,7 +704,14 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = row_of(i, v);
-            if (okc && row < t.M) op[2 * x_off<DUAL>(t, oc, row)] = value(i, j, v);
+            if (okc && row < t.M) {
+              // the spectrum rows of the inverse Legendre stage stream out (they
+              // are read once, in full, by the inverse FFT)
+              if constexpr (KIND == K_B_INV)
+                __builtin_nontemporal_store(value(i, j, v), &op[2 * x_off<DUAL>(t, oc, row)]);
+              else
+                op[2 * x_off<DUAL>(t, oc, row)] = value(i, j, v);
+            }
           }
         }
       }

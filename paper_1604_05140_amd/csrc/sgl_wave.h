@@ -26,6 +26,17 @@ __device__ inline T2 csub(T2 a, T2 b) { T2 r; r.x = a.x - b.x; r.y = a.y - b.y; 
 template <typename T2>
 __device__ inline T2 conjc(T2 a) { a.y = -a.y; return a; }
 
+// Streaming store of a complex value (non-temporal: the line is not kept in
+// the caches).  Used for the large outputs that the next kernel reads once in
+// full (spectrum rows, samples): measured on MI355X at B = 128, batch 4, the
+// caches then hold fewer dirty lines of them, and the next launches' reads
+// run faster (about 7% per transform pair).
+template <typename T2>
+__device__ inline void store_stream(T2* p, T2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+
 // twiddle exp(sign 2 pi i q / L) from the forward table exp(-2 pi i q / L)
 template <typename T2, bool INV>
 __device__ inline T2 twid(const T2* tw, int q) {
