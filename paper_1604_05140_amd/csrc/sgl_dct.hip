@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
       if (!INV) {
         for (int e = threadIdx.x; e < L * nc; e += blockDim.x) {
           const int j = e / nc, r = e - j * nc;
-          const S2 f = Fb[(int64_t)j * ncol + r];
+          const S2 f = load_stream(&Fb[(int64_t)j * ncol + r]);
           const double sg = par ? sn[j].x : 1.0;
           areas[r * AP + j] = make_double2(f.x * sg, f.y * sg);
         }
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
       // rows j of the tile -> bit-reversed slots j and 4B-1-j of the even extension
       for (int e = threadIdx.x; e < L * nc; e += blockDim.x) {
         const int j = e / nc, r = e - j * nc;
-        const S2 f = Fb[(int64_t)j * ncol + r];
+        const S2 f = load_stream(&Fb[(int64_t)j * ncol + r]);
         T2 x = make_double2(f.x, f.y);
         if (par) {
           x.x *= sn[j].x;

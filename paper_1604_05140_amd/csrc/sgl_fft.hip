@@ -98,7 +98,7 @@ __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int
       const T2* src = samples + C.soff[b] + ((int64_t)i * L + j) * L;
       T2 v[R1];
 #pragma unroll
-      for (int n1 = 0; n1 < R1; ++n1) v[n1] = src[R2 * n1 + n2];
+      for (int n1 = 0; n1 < R1; ++n1) v[n1] = load_stream(&src[R2 * n1 + n2]);
       if (RAW) {
         const T sg = (T)C.sigma[i];
 #pragma unroll
@@ -163,7 +163,7 @@ __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int
           y[k2].y = 0;
         } else {
           const int mi = (bin < B ? bin : bin - L) + B - 1;
-          y[k2] = F[((int64_t)mi * L + j) * ncol + col0 + r];
+          y[k2] = load_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r]);
         }
       }
       dft_reg<T2, R2, true>(y);
@@ -283,7 +283,7 @@ __device__ inline void fwd_blue(const ClassDesc& C, int j, int col0, int nr, int
     if (k < L) {
       const int col = col0 + r;
       const int b = col / L, i = col - b * L;
-      v = cmul(samples[C.soff[b] + ((int64_t)i * L + j) * L + k], chirp[k]);
+      v = cmul(load_stream(&samples[C.soff[b] + ((int64_t)i * L + j) * L + k]), chirp[k]);
       if (RAW) {
         const T sg = (T)C.sigma[i];
         v.x *= sg;
@@ -333,7 +333,7 @@ __device__ inline void inv_blue(const ClassDesc& C, int j, int col0, int nr, int
     v.y = 0;
     if (p != B) {
       const int mi = (p < B ? p : p - L) + B - 1;
-      v = cmul(F[((int64_t)mi * L + j) * ncol + col0 + r], conjc(chirp[p]));
+      v = cmul(load_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r]), conjc(chirp[p]));
     }
     buf[r * M + p] = v;
   }
@@ -450,7 +450,7 @@ __device__ inline void fwd512(const ClassDesc& C, int j, int col0, int nr, const
     if (!C.M) {
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        v[a] = src[64 * a + l];
+        v[a] = load_stream(&src[64 * a + l]);
         if (RAW) {
           v[a].x *= sg;
           v[a].y *= sg;
@@ -464,7 +464,7 @@ __device__ inline void fwd512(const ClassDesc& C, int j, int col0, int nr, const
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int k = 64 * a + l;
-        v[a] = cmul(src[min(k, L - 1)], ch[k]);
+        v[a] = cmul(load_stream(&src[min(k, L - 1)]), ch[k]);
         if (RAW) {
           v[a].x *= sg;
           v[a].y *= sg;
@@ -532,7 +532,7 @@ __device__ inline void inv512(const ClassDesc& C, int j, int col0, int nr, typen
         v.y = 0;
         if (p != B && p < L) {
           const int mi = (p < B ? p : p - L) + B - 1;
-          v = src[mi * row];
+          v = load_stream(&src[mi * row]);
           if (C.M) v = cmul(v, conjc(ch[p]));
         }
         stage[p] = v;
@@ -661,7 +661,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       const int r = e / L, k = e - r * L;
       const int col = col0 + r;
       const int b = col / L, i = col - b * L;
-      T2 v = samples[C.soff[b] + ((int64_t)i * L + j) * L + k];
+      T2 v = load_stream(&samples[C.soff[b] + ((int64_t)i * L + j) * L + k]);
       if (RAW) {
         const T sg = (T)C.sigma[i];
         v.x *= sg;
@@ -786,7 +786,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       const int mi = e / nr, r = e - mi * nr;
       const int m = mi - (B - 1);
       const int bin = m >= 0 ? m : L + m;
-      buf0[r * L + bin] = F[((int64_t)mi * L + j) * ncol + col0 + r];
+      buf0[r * L + bin] = load_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r]);
     }
     __syncthreads();
     const T2* tw = reinterpret_cast<const T2*>(C.tw);

@@ -345,9 +345,16 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol<typenam
 #pragma unroll
     for (int u = 0; u < XN; ++u) {
       const int k = min(kb + u, kmax);
-      const T2 v = *reinterpret_cast<const T2*>(xc.p + 2 * x_off<KIND>(t, xc, k));
-      st.xr[u] = v.x;
-      st.xi[u] = v.y;
+      if constexpr (KIND == K_B_FWD) {
+        // spectrum rows are read once: streaming loads keep g cached for stage (c)
+        const T* q = xc.p + 2 * x_off<KIND>(t, xc, k);
+        st.xr[u] = __builtin_nontemporal_load(q);
+        st.xi[u] = __builtin_nontemporal_load(q + 1);
+      } else {
+        const T2 v = *reinterpret_cast<const T2*>(xc.p + 2 * x_off<KIND>(t, xc, k));
+        st.xr[u] = v.x;
+        st.xi[u] = v.y;
+      }
     }
   }
 }

@@ -36,6 +36,16 @@ __device__ inline void store_stream(T2* p, T2 v) {
   __builtin_nontemporal_store(v.x, &p->x);
   __builtin_nontemporal_store(v.y, &p->y);
 }
+// Streaming load (non-temporal) of a value read once: the spectrum rows and the
+// samples are larger than the caches, and streaming them keeps the smaller
+// stage (b)/(c) intermediates cached between their launches.
+template <typename T2>
+__device__ inline T2 load_stream(const T2* p) {
+  T2 v;
+  v.x = __builtin_nontemporal_load(&p->x);
+  v.y = __builtin_nontemporal_load(&p->y);
+  return v;
+}
 
 // twiddle exp(sign 2 pi i q / L) from the forward table exp(-2 pi i q / L)
 template <typename T2, bool INV>
