@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
     const int cols = it.w, col0 = it.z * cols;
     const int nc = min(cols, ncol - col0);
     if (it.x != tab_cls) {
-      const T2* src = reinterpret_cast<const T2*>(C.dct);  // FP64 constants
+      const SGL_G T2* src = gmem(reinterpret_cast<const T2*>(C.dct));  // FP64 constants
       for (int q = threadIdx.x; q < nconst; q += blockDim.x) tab[q] = src[q];
       __syncthreads();
       tab_cls = it.x;
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
     const T2* post = tab + P2 / 2;  // s_k / 2 exp(-i pi k / 4B), k < B
     const T2* sn = post + B;        // sin th_j (real part), j < 2B
     T2* bufs = tab + nconst;
-    S2* Fb = reinterpret_cast<S2*>(C.F) + (int64_t)mi * L * ncol + col0;
+    SGL_G S2* Fb = gmem(reinterpret_cast<S2*>(C.F)) + (int64_t)mi * L * ncol + col0;
     if (P2 == 512) {
       // --- 512-point path (B = 128): columns in areas of area_pitch elements ---
       T2* ftab = bufs;                  // w_512^(l p), w_64^(c q)

@@ -20,7 +20,7 @@ namespace {
 
 // One Stockham stage of radix R over `nring` rings of length L held in LDS.
 template <typename T2, bool INV>
-__device__ void stockham_stage(const T2* in, T2* out, const T2* tw, int L, int R, int Ns, int nring) {
+__device__ void stockham_stage(const T2* in, T2* out, const SGL_G T2* tw, int L, int R, int Ns, int nring) {
   const int nbf = L / R;
   const int total = nring * nbf;
   const int LR = L / R;
@@ -84,7 +84,7 @@ __device__ void stockham_stage(const T2* in, T2* out, const T2* tw, int L, int R
 
 template <typename T, int R1, int R2, bool RAW>
 __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int rpb,
-                                const typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds,
+                                const SGL_G typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds,
                                 const typename C2<T>::t* tw) {
   using T2 = typename C2<T>::t;
   constexpr int L = R1 * R2, B = L / 2;
@@ -95,12 +95,12 @@ __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int
     if (r < nr) {
       const int col = col0 + r;
       const int b = col / L, i = col % L;
-      const T2* src = samples + C.soff[b] + ((int64_t)i * L + j) * L;
+      const SGL_G T2* src = samples + gmem(C.soff)[b] + ((int64_t)i * L + j) * L;
       T2 v[R1];
 #pragma unroll
       for (int n1 = 0; n1 < R1; ++n1) v[n1] = load_stream(&src[R2 * n1 + n2]);
       if (RAW) {
-        const T sg = (T)C.sigma[i];
+        const T sg = (T)gmem(C.sigma)[i];
 #pragma unroll
         for (int n1 = 0; n1 < R1; ++n1) {
           v[n1].x *= sg;
@@ -123,9 +123,9 @@ __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int
 #pragma unroll
       for (int n2 = 0; n2 < R2; ++n2) y[n2] = lds[(k1 * R2 + n2) * P + r];
       dft_reg<T2, R2, false>(y);
-      const T wj = (T)C.btilde[j];
+      const T wj = (T)gmem(C.btilde)[j];
       const int ncol = C.nf * L;
-      T2* F = reinterpret_cast<T2*>(C.F);
+      SGL_G T2* F = gmem(reinterpret_cast<T2*>(C.F));
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
         const int bin = k1 + R1 * k2;
@@ -143,7 +143,7 @@ __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int
 
 template <typename T, int R1, int R2, bool RAW>
 __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int rpb,
-                                typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds,
+                                SGL_G typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds,
                                 const typename C2<T>::t* tw) {
   using T2 = typename C2<T>::t;
   constexpr int L = R1 * R2, B = L / 2;
@@ -153,7 +153,7 @@ __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int
     const int r = t % rpb, k1 = t / rpb;
     if (r < nr) {
       const int ncol = C.nf * L;
-      const T2* F = reinterpret_cast<const T2*>(C.F);
+      const SGL_G T2* F = gmem(reinterpret_cast<const T2*>(C.F));
       T2 y[R2];
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
@@ -184,9 +184,9 @@ __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int
       dft_reg<T2, R1, true>(v);
       const int col = col0 + r;
       const int b = col / L, i = col % L;
-      T2* dst = samples + C.soff[b] + ((int64_t)i * L + j) * L;
+      SGL_G T2* dst = samples + gmem(C.soff)[b] + ((int64_t)i * L + j) * L;
       if (RAW) {
-        const T sg = (T)(1.0 / C.sigma[i]);
+        const T sg = (T)(1.0 / gmem(C.sigma)[i]);
 #pragma unroll
         for (int n1 = 0; n1 < R1; ++n1) {
           v[n1].x *= sg;
@@ -269,7 +269,7 @@ __device__ inline void blue_core(int rpb, int nr, typename C2<T>::t* buf, const 
 
 template <typename T, int R1, int R2, bool RAW>
 __device__ inline void fwd_blue(const ClassDesc& C, int j, int col0, int nr, int rpb,
-                                const typename C2<T>::t* __restrict__ samples, typename C2<T>::t* buf,
+                                const SGL_G typename C2<T>::t* __restrict__ samples, typename C2<T>::t* buf,
                                 const typename C2<T>::t* twM, const typename C2<T>::t* chirp,
                                 const typename C2<T>::t* bh) {
   using T2 = typename C2<T>::t;
@@ -283,9 +283,9 @@ __device__ inline void fwd_blue(const ClassDesc& C, int j, int col0, int nr, int
     if (k < L) {
       const int col = col0 + r;
       const int b = col / L, i = col - b * L;
-      v = cmul(load_stream(&samples[C.soff[b] + ((int64_t)i * L + j) * L + k]), chirp[k]);
+      v = cmul(load_stream(&samples[gmem(C.soff)[b] + ((int64_t)i * L + j) * L + k]), chirp[k]);
       if (RAW) {
-        const T sg = (T)C.sigma[i];
+        const T sg = (T)gmem(C.sigma)[i];
         v.x *= sg;
         v.y *= sg;
       }
@@ -298,9 +298,9 @@ __device__ inline void fwd_blue(const ClassDesc& C, int j, int col0, int nr, int
   const int t = threadIdx.x;
   const int r = t % rpb, n2 = t / rpb;
   if (t < rpb * R2 && r < nr) {
-    const T wj = (T)C.btilde[j];
+    const T wj = (T)gmem(C.btilde)[j];
     const int ncol = C.nf * L;
-    T2* F = reinterpret_cast<T2*>(C.F);
+    SGL_G T2* F = gmem(reinterpret_cast<T2*>(C.F));
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) {
       const int idx = R2 * n1 + n2;
@@ -317,14 +317,14 @@ __device__ inline void fwd_blue(const ClassDesc& C, int j, int col0, int nr, int
 
 template <typename T, int R1, int R2, bool RAW>
 __device__ inline void inv_blue(const ClassDesc& C, int j, int col0, int nr, int rpb,
-                                typename C2<T>::t* __restrict__ samples, typename C2<T>::t* buf,
+                                SGL_G typename C2<T>::t* __restrict__ samples, typename C2<T>::t* buf,
                                 const typename C2<T>::t* twM, const typename C2<T>::t* chirp,
                                 const typename C2<T>::t* bh) {
   using T2 = typename C2<T>::t;
   constexpr int M = R1 * R2;
   const int L = C.L, B = C.B;
   const int ncol = C.nf * L;
-  const T2* F = reinterpret_cast<const T2*>(C.F);
+  const SGL_G T2* F = gmem(reinterpret_cast<const T2*>(C.F));
   // bins p < L in the ring-fastest order of F rows, twisted by conj(c_p)
   for (int e = threadIdx.x; e < nr * L; e += blockDim.x) {
     const int p = e / nr, r = e - p * nr;
@@ -352,8 +352,8 @@ __device__ inline void inv_blue(const ClassDesc& C, int j, int col0, int nr, int
   if (t < rpb * R2 && r < nr) {
     const int col = col0 + r;
     const int b = col / L, i = col - b * L;
-    T2* dst = samples + C.soff[b] + ((int64_t)i * L + j) * L;
-    const T sg = RAW ? (T)(1.0 / C.sigma[i]) : (T)1;
+    SGL_G T2* dst = samples + gmem(C.soff)[b] + ((int64_t)i * L + j) * L;
+    const T sg = RAW ? (T)(1.0 / gmem(C.sigma)[i]) : (T)1;
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) {
       const int idx = R2 * n1 + n2;
@@ -398,7 +398,7 @@ constexpr int kTabKer = 504, kTabChirp = 761, kTab512 = 1017;  // kTabTw2 = 448 
 // Fill the block's 512-point tables for class C (block-wide; ends synchronised).
 template <typename T2>
 __device__ inline void load_tab512(const ClassDesc& C, const void* kernel_spectrum, T2* tab) {
-  const T2* tw = reinterpret_cast<const T2*>(C.M ? C.twM : C.tw);  // exp(-2 pi i q / 512)
+  const SGL_G T2* tw = gmem(reinterpret_cast<const T2*>(C.M ? C.twM : C.tw));  // exp(-2 pi i q / 512)
   for (int q = threadIdx.x; q < 448; q += blockDim.x) {
     const int p = q / 64 + 1, l = q % 64;
     tab[q] = tw[(l * p) % 512];
@@ -408,9 +408,9 @@ __device__ inline void load_tab512(const ClassDesc& C, const void* kernel_spectr
     tab[kTabTw2 + q] = tw[8 * ((c * e) % 64)];  // w_64^(c e)
   }
   if (C.M) {
-    const T2* bh = reinterpret_cast<const T2*>(kernel_spectrum);
+    const SGL_G T2* bh = gmem(reinterpret_cast<const T2*>(kernel_spectrum));
     for (int q = threadIdx.x; q <= 256; q += blockDim.x) tab[kTabKer + q] = bh[q];
-    const T2* ch = reinterpret_cast<const T2*>(C.chirp);
+    const SGL_G T2* ch = gmem(reinterpret_cast<const T2*>(C.chirp));
     for (int q = threadIdx.x; q < 256; q += blockDim.x) {
       const T2 c = ch[min(q, C.L - 1)];
       const bool in = q < C.L;
@@ -433,19 +433,19 @@ __device__ inline void kernel_product(T2 (&v)[8], const T2* tab, int l) {
 }
 
 template <typename T, bool RAW>
-__device__ inline void fwd512(const ClassDesc& C, int j, int col0, int nr, const typename C2<T>::t* __restrict__ samples,
+__device__ inline void fwd512(const ClassDesc& C, int j, int col0, int nr, const SGL_G typename C2<T>::t* __restrict__ samples,
                               const typename C2<T>::t* tab, typename C2<T>::t* smem) {
   using T2 = typename C2<T>::t;
   constexpr int P = area_pitch<T2>();
   const int L = C.L, B = C.B;
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
   T2* area = smem + wv * P;
-  const T wj = (T)C.btilde[j];
+  const T wj = (T)gmem(C.btilde)[j];
   if (wv < nr) {
     const int col = col0 + wv;
     const int b = col / L, i = col - b * L;
-    const T2* src = samples + C.soff[b] + ((int64_t)i * L + j) * L;
-    const T sg = RAW ? (T)C.sigma[i] : (T)1;
+    const SGL_G T2* src = samples + gmem(C.soff)[b] + ((int64_t)i * L + j) * L;
+    const T sg = RAW ? (T)gmem(C.sigma)[i] : (T)1;
     T2 v[8];
     if (!C.M) {
 #pragma unroll
@@ -499,7 +499,7 @@ __device__ inline void fwd512(const ClassDesc& C, int j, int col0, int nr, const
     const int64_t step = (int64_t)(blockDim.x / kRings512) * L * ncol;
     const T2* stage = smem + r * P;
     int mi = threadIdx.x / kRings512;
-    T2* dst = reinterpret_cast<T2*>(C.F) + ((int64_t)mi * L + j) * ncol + col0 + r;
+    SGL_G T2* dst = gmem(reinterpret_cast<T2*>(C.F)) + ((int64_t)mi * L + j) * ncol + col0 + r;
     for (; mi < nm; mi += blockDim.x / kRings512, dst += step) {
       const int m = mi - (B - 1);
       store_stream(dst, stage[m >= 0 ? m : L + m]);
@@ -509,12 +509,12 @@ __device__ inline void fwd512(const ClassDesc& C, int j, int col0, int nr, const
 }
 
 template <typename T, bool RAW>
-__device__ inline void inv512(const ClassDesc& C, int j, int col0, int nr, typename C2<T>::t* __restrict__ samples,
+__device__ inline void inv512(const ClassDesc& C, int j, int col0, int nr, SGL_G typename C2<T>::t* __restrict__ samples,
                               const typename C2<T>::t* tab, typename C2<T>::t* smem) {
   using T2 = typename C2<T>::t;
   constexpr int P = area_pitch<T2>();
   const int L = C.L, B = C.B;
-  const T2* F = reinterpret_cast<const T2*>(C.F);
+  const SGL_G T2* F = gmem(reinterpret_cast<const T2*>(C.F));
   const int ncol = C.nf * L;
   const T2* ch = tab + kTabChirp;
   // spectrum rows -> ring areas; bin B (which no coefficient produces) and,
@@ -524,7 +524,7 @@ __device__ inline void inv512(const ClassDesc& C, int j, int col0, int nr, typen
     const int r = threadIdx.x & (kRings512 - 1);
     if (r < nr) {
       T2* stage = smem + r * P;
-      const T2* src = F + (int64_t)j * ncol + col0 + r;
+      const SGL_G T2* src = F + (int64_t)j * ncol + col0 + r;
       const int64_t row = (int64_t)L * ncol;
       for (int p = threadIdx.x / kRings512; p < nb; p += blockDim.x / kRings512) {
         T2 v;
@@ -545,8 +545,8 @@ __device__ inline void inv512(const ClassDesc& C, int j, int col0, int nr, typen
   if (wv < nr) {
     const int col = col0 + wv;
     const int b = col / L, i = col - b * L;
-    T2* dst = samples + C.soff[b] + ((int64_t)i * L + j) * L;
-    const T sg = RAW ? (T)(1.0 / C.sigma[i]) : (T)1;
+    SGL_G T2* dst = samples + gmem(C.soff)[b] + ((int64_t)i * L + j) * L;
+    const T sg = RAW ? (T)(1.0 / gmem(C.sigma)[i]) : (T)1;
     T2 v[8];
     if (!C.M) {
 #pragma unroll
@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
   using T2 = typename C2<T>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* smem = reinterpret_cast<T2*>(smem_raw);
-  const T2* samples = reinterpret_cast<const T2*>(samples_v);
+  const SGL_G T2* samples = gmem(reinterpret_cast<const T2*>(samples_v));
   int tw_cls = -1;  // class whose twiddles sit in LDS (block-uniform)
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int4 it = work[w];
@@ -610,7 +610,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
     if (MODE == 0 && fft_pow2_path(L)) {
       T2* twl = smem + L * (rpb + 1);
       if (it.x != tw_cls) {
-        const T2* tw = reinterpret_cast<const T2*>(C.tw);
+        const SGL_G T2* tw = gmem(reinterpret_cast<const T2*>(C.tw));
         for (int q = threadIdx.x; q < L; q += blockDim.x) twl[q] = tw[q];
         __syncthreads();
         tw_cls = it.x;
@@ -632,9 +632,9 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       T2* chs = tws + M;
       T2* bhs = chs + L;
       if (it.x != tw_cls) {
-        const T2* tw = reinterpret_cast<const T2*>(C.twM);
-        const T2* ch = reinterpret_cast<const T2*>(C.chirp);
-        const T2* bh = reinterpret_cast<const T2*>(C.bhf);
+        const SGL_G T2* tw = gmem(reinterpret_cast<const T2*>(C.twM));
+        const SGL_G T2* ch = gmem(reinterpret_cast<const T2*>(C.chirp));
+        const SGL_G T2* bh = gmem(reinterpret_cast<const T2*>(C.bhf));
         for (int q = threadIdx.x; q < M; q += blockDim.x) {
           tws[q] = tw[q];
           bhs[q] = bh[q];
@@ -661,16 +661,16 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       const int r = e / L, k = e - r * L;
       const int col = col0 + r;
       const int b = col / L, i = col - b * L;
-      T2 v = load_stream(&samples[C.soff[b] + ((int64_t)i * L + j) * L + k]);
+      T2 v = load_stream(&samples[gmem(C.soff)[b] + ((int64_t)i * L + j) * L + k]);
       if (RAW) {
-        const T sg = (T)C.sigma[i];
+        const T sg = (T)gmem(C.sigma)[i];
         v.x *= sg;
         v.y *= sg;
       }
       buf0[r * L + k] = v;
     }
     __syncthreads();
-    const T2* tw = reinterpret_cast<const T2*>(C.tw);
+    const SGL_G T2* tw = gmem(reinterpret_cast<const T2*>(C.tw));
     T2* cur = buf0;
     T2* nxt = buf1;
     int Ns = 1;
@@ -683,8 +683,8 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       nxt = tmp;
       Ns *= R;
     }
-    const T wj = (T)C.btilde[j];
-    T2* F = reinterpret_cast<T2*>(C.F);
+    const T wj = (T)gmem(C.btilde)[j];
+    SGL_G T2* F = gmem(reinterpret_cast<T2*>(C.F));
     const int nm = 2 * B - 1;
     for (int e = threadIdx.x; e < nm * nr; e += blockDim.x) {
       const int mi = e / nr, r = e - mi * nr;
@@ -705,7 +705,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
   using T2 = typename C2<T>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T2* smem = reinterpret_cast<T2*>(smem_raw);
-  T2* samples = reinterpret_cast<T2*>(samples_v);
+  SGL_G T2* samples = gmem(reinterpret_cast<T2*>(samples_v));
   int tw_cls = -1;
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int4 it = work[w];
@@ -726,7 +726,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
     if (MODE == 0 && fft_pow2_path(L)) {
       T2* twl = smem + L * (rpb + 1);
       if (it.x != tw_cls) {
-        const T2* tw = reinterpret_cast<const T2*>(C.tw);
+        const SGL_G T2* tw = gmem(reinterpret_cast<const T2*>(C.tw));
         for (int q = threadIdx.x; q < L; q += blockDim.x) twl[q] = tw[q];
         __syncthreads();
         tw_cls = it.x;
@@ -748,9 +748,9 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       T2* chs = tws + M;
       T2* bhs = chs + L;
       if (it.x != tw_cls) {
-        const T2* tw = reinterpret_cast<const T2*>(C.twM);
-        const T2* ch = reinterpret_cast<const T2*>(C.chirp);
-        const T2* bh = reinterpret_cast<const T2*>(C.bhi);
+        const SGL_G T2* tw = gmem(reinterpret_cast<const T2*>(C.twM));
+        const SGL_G T2* ch = gmem(reinterpret_cast<const T2*>(C.chirp));
+        const SGL_G T2* bh = gmem(reinterpret_cast<const T2*>(C.bhi));
         for (int q = threadIdx.x; q < M; q += blockDim.x) {
           tws[q] = tw[q];
           bhs[q] = bh[q];
@@ -773,7 +773,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
     if constexpr (MODE != 0) continue;
     T2* buf0 = smem;
     T2* buf1 = smem + rpb * L;
-    const T2* F = reinterpret_cast<const T2*>(C.F);
+    const SGL_G T2* F = gmem(reinterpret_cast<const T2*>(C.F));
     // bins B (not produced by any coefficient) start at zero
     for (int r = threadIdx.x; r < nr; r += blockDim.x) {
       T2 z;
@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       buf0[r * L + bin] = load_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r]);
     }
     __syncthreads();
-    const T2* tw = reinterpret_cast<const T2*>(C.tw);
+    const SGL_G T2* tw = gmem(reinterpret_cast<const T2*>(C.tw));
     T2* cur = buf0;
     T2* nxt = buf1;
     int Ns = 1;
@@ -808,11 +808,11 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       const int b = col / L, i = col - b * L;
       T2 v = cur[r * L + k];
       if (RAW) {
-        const T sg = (T)(1.0 / C.sigma[i]);
+        const T sg = (T)(1.0 / gmem(C.sigma)[i]);
         v.x *= sg;
         v.y *= sg;
       }
-      store_stream(&samples[C.soff[b] + ((int64_t)i * L + j) * L + k], v);
+      store_stream(&samples[gmem(C.soff)[b] + ((int64_t)i * L + j) * L + k], v);
     }
     __syncthreads();
   }

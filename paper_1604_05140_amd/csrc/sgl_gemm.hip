@@ -19,9 +19,10 @@
 // columns = 2N real columns).  One kernel template covers the four cases:
 //   * tile 128 x 128 real outputs, 8 waves of 64 x 32 (4 x 2 MFMA blocks of
 //     16 x 16); 128 rows cover a whole Legendre block at B <= 128, so the
-//     spectrum F is read from HBM once; K in chunks of 64 through LDS, with
-//     two register stages: the loads of chunk c+2 are issued before the MFMAs
-//     of chunk c, so each load has two MFMA phases to arrive;
+//     spectrum F is read from HBM once; K in chunks through LDS (32 for the
+//     split and FP32 forms, 64 for FP64), with register stages that issue the
+//     loads of the next chunk (FP32: the next two) before the MFMAs of the
+//     current one;
 //   * the table operand comes pre-packed per direction (row-major, K padded to
 //     a multiple of 64 with zeros), so every table load is a 16-byte vector;
 //   * data-operand loads follow the layout the previous stage wrote: each
@@ -209,7 +210,7 @@ __device__ inline void load_a(Stage<PREC>& st, const Tile& t, int k0, int tid) {
   const int rmax = t.M - 1;
   constexpr int EV = PREC == PREC_SPLIT ? 8 : (PREC == PREC_F32 ? 4 : 2);  // elements per vector
   constexpr int ES = PREC == PREC_SPLIT ? 2 : (PREC == PREC_F32 ? 4 : 8);  // element bytes
-  const unsigned char* tab = reinterpret_cast<const unsigned char*>(t.tab);
+  const SGL_G unsigned char* tab = gmem(reinterpret_cast<const unsigned char*>(t.tab));
 #pragma unroll
   for (int v = 0; v < C::NA; ++v) {
     const int e = tid + v * NT;  // plane, row, vector (a row's vectors in consecutive lanes)
@@ -218,7 +219,7 @@ __device__ inline void load_a(Stage<PREC>& st, const Tile& t, int k0, int tid) {
     const int r = rem / C::VR, kg = rem - r * C::VR;
     const int gr = min(t.row0 + r, rmax);
     const int64_t off = (int64_t)gr * t.pitch + k0 + kg * EV;
-    st.a[v] = *reinterpret_cast<const u4*>(tab + ES * (PREC == PREC_SPLIT ? p * t.plane + off : off));
+    st.a[v] = *reinterpret_cast<const SGL_G u4*>(tab + ES * (PREC == PREC_SPLIT ? p * t.plane + off : off));
   }
 }
 
@@ -249,14 +250,14 @@ __device__ inline void store_a(const Stage<PREC>& st, unsigned char* sm, int tid
 //   K_C_INV  fhat[b][omega(n = l+1+k, l, m)]: off = n (n-1) (2n-1) / 6
 template <typename T>
 struct XCol {
-  T* p;
+  SGL_G T* p;
   int a, b;
   T sgn;  // (-1)^m on the -m segment of stage b, else 1
 };
 
 template <int KIND, typename T>
 __device__ inline XCol<T> x_col(const Tile& t, int c, T* base) {
-  XCol<T> x{base, 0, 0, (T)1};
+  XCol<T> x{gmem(base), 0, 0, (T)1};
   const ClassDesc& C = *t.C;
   const int B = C.B, L = C.L, nf = C.nf;
   if constexpr (KIND == K_B_FWD || KIND == K_B_INV) {
@@ -266,21 +267,21 @@ __device__ inline XCol<T> x_col(const Tile& t, int c, T* base) {
     const int mp = seg ? -t.q : t.q;
     if (seg && (t.q & 1)) x.sgn = (T)-1;
     if constexpr (KIND == K_B_FWD) {
-      x.p = base + 2 * ((int64_t)(mp + B - 1) * L * ncf + cp);
+      x.p = gmem(base) + 2 * ((int64_t)(mp + B - 1) * L * ncf + cp);
       x.a = ncf;
     } else {
       const int b = cp / L, i = cp - b * L;
-      x.p = base + 2 * ((int64_t)(b + mp) * L + i);
+      x.p = gmem(base) + 2 * ((int64_t)(b + mp) * L + i);
       x.a = nf * L;
       x.b = (2 * b + 1) * L;
     }
   } else if constexpr (KIND == K_C_FWD) {
-    x.p = base + 2 * ((int64_t)t.q * t.q * nf * L + (int64_t)c * L);
+    x.p = gmem(base) + 2 * ((int64_t)t.q * t.q * nf * L + (int64_t)c * L);
   } else {  // K_C_INV
     const int l = t.q;
     const int b = c / (2 * l + 1);
     const int m = c - b * (2 * l + 1) - l;
-    x.p = base + 2 * (C.coff[b] + (int64_t)l * (l + 1) + m);
+    x.p = gmem(base) + 2 * (C.coff[b] + (int64_t)l * (l + 1) + m);
   }
   return x;
 }
@@ -322,15 +323,15 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol<typenam
       const int k = kb + u;
       const int n0 = 2 * c, n1 = 2 * c + 1;
       const bool ok = k < t.K;
-      st.xr[u] = (ok && n0 < dbg.N) ? (T)dbg.X[(int64_t)k * dbg.N + n0] : (T)0;
-      st.xi[u] = (ok && n1 < dbg.N) ? (T)dbg.X[(int64_t)k * dbg.N + n1] : (T)0;
+      st.xr[u] = (ok && n0 < dbg.N) ? (T)gmem(dbg.X)[(int64_t)k * dbg.N + n0] : (T)0;
+      st.xi[u] = (ok && n1 < dbg.N) ? (T)gmem(dbg.X)[(int64_t)k * dbg.N + n1] : (T)0;
     }
   } else {
     const int kmax = t.K - 1;
     if constexpr (KIND == K_C_FWD && PREC != PREC_F64) {
       if (kb + XN <= t.K) {
         // XN consecutive k of one column are contiguous (g rows run along i)
-        const float4* src = reinterpret_cast<const float4*>(xc.p + 2 * kb);
+        const SGL_G float4* src = reinterpret_cast<const SGL_G float4*>(xc.p + 2 * kb);
 #pragma unroll
         for (int u = 0; u < XN / 2; ++u) {
           const float4 v = src[u];
@@ -347,11 +348,11 @@ __device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol<typenam
       const int k = min(kb + u, kmax);
       if constexpr (KIND == K_B_FWD) {
         // spectrum rows are read once: streaming loads keep g cached for stage (c)
-        const T* q = xc.p + 2 * x_off<KIND>(t, xc, k);
+        const SGL_G T* q = xc.p + 2 * x_off<KIND>(t, xc, k);
         st.xr[u] = __builtin_nontemporal_load(q);
         st.xi[u] = __builtin_nontemporal_load(q + 1);
       } else {
-        const T2 v = *reinterpret_cast<const T2*>(xc.p + 2 * x_off<KIND>(t, xc, k));
+        const T2 v = *reinterpret_cast<const SGL_G T2*>(xc.p + 2 * x_off<KIND>(t, xc, k));
         st.xr[u] = v.x;
         st.xi[u] = v.y;
       }
@@ -426,9 +427,9 @@ __device__ inline typename DT<PREC>::t* x_base(const Tile& t, const void* cin) {
 
 // ---- the kernel ------------------------------------------------------------
 // Persistent blocks walk the work list.  Per item: K in chunks of BK through
-// LDS with two register stages; before an item's outputs are written, the
-// first two chunks of the block's next item are already being loaded, so the
-// load latency of short contractions overlaps the stores.  Outputs go straight
+// LDS with NS register stages; before an item's outputs are written, the
+// first chunks of the block's next item are already being loaded (split and
+// FP32 forms), so the load latency of short contractions overlaps the stores.  Outputs go straight
 // from the accumulators to the next stage's layout.
 template <int PREC, int KIND>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PREC>::WAVES))) k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
@@ -509,7 +510,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
         for (int e = tid; e < BM * BK; e += NT) {
           const int r = e / BK, k = e - r * BK;
           const int gr = t.row0 + r, gk = k0 + k;
-          const double v = (gr < t.M && gk < t.K) ? dbg.A[(int64_t)gr * t.K + gk] : 0.0;
+          const double v = (gr < t.M && gk < t.K) ? gmem(dbg.A)[(int64_t)gr * t.K + gk] : 0.0;
           if constexpr (PREC == PREC_SPLIT) {
             uint16_t* As = reinterpret_cast<uint16_t*>(sm);
             const uint16_t h0 = f2bf((float)v);
@@ -652,7 +653,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = row_of(i, v);
-            if (i < nbi && row < t.M) dbg.C[(int64_t)row * dbg.N + nr] = (double)value(i, j, v);
+            if (i < nbi && row < t.M) gmem(dbg.C)[(int64_t)row * dbg.N + nr] = (double)value(i, j, v);
           }
       }
     } else if constexpr (KIND == K_C_INV) {
@@ -685,9 +686,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
             const float4 o = even ? make_float4(v0, got0, v1, got1) : make_float4(got0, v2, got1, v3);
             if (okc) {
               if (rs + 1 < t.M) {
-                *reinterpret_cast<float4*>(oc.p + 2 * rs) = o;
+                *reinterpret_cast<SGL_G float4*>(oc.p + 2 * rs) = o;
               } else if (rs < t.M) {
-                *reinterpret_cast<float2*>(oc.p + 2 * rs) = make_float2(o.x, o.y);
+                *reinterpret_cast<SGL_G float2*>(oc.p + 2 * rs) = make_float2(o.x, o.y);
               }
             }
           }
@@ -703,7 +704,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
         const int c = t.col0 + (rc >> 1);
         if (j >= nbj) continue;
         const XCol<T> oc = x_col<DUAL>(t, min(c, t.Ncc - 1), obase);
-        T* op = oc.p + (rc & 1);
+        SGL_G T* op = oc.p + (rc & 1);
         const bool okc = c < t.Ncc;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {

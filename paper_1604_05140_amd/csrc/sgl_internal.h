@@ -26,6 +26,26 @@ void set_error(const std::string& msg);
   } while (0)
 
 // ---------------------------------------------------------------------------
+// Global-memory views of device pointers.  A pointer read from a descriptor
+// is generic to the compiler, which then emits flat memory instructions; those
+// also count in the LDS wait counter, so every wait for an LDS access (each
+// MFMA operand read, each barrier) would wait for all HBM loads and stores in
+// flight as well, and no prefetch could overlap compute.  Accesses through
+// these views compile to global instructions (vector-memory counter only).
+// The cast changes no bits: global and generic addresses coincide.  The host
+// pass, which only type-checks device code, sees plain pointers.
+// ---------------------------------------------------------------------------
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SGL_G __attribute__((address_space(1)))
+#else
+#define SGL_G
+#endif
+template <typename T>
+__device__ inline SGL_G T* gmem(T* p) {
+  return (SGL_G T*)p;
+}
+
+// ---------------------------------------------------------------------------
 // Sizes and table offsets
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int64_t num_coeffs(int B) { return (int64_t)B * (B + 1) * (2 * B + 1) / 6; }

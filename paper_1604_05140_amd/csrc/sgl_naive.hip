@@ -56,23 +56,23 @@ __global__ void __launch_bounds__(NT) k_naive_forward(const ClassDesc* __restric
     const int c = class_of(pre, ncls, w);
     const ClassDesc& C = cls[c];
     const int B = C.B, L = C.L;
-    const int per = C.naive_loff[B];
+    const int per = gmem(C.naive_loff)[B];
     const int64_t r = w - pre[c];
     const int b = (int)(r / per);
     int q = (int)(r - (int64_t)b * per);
     int l = 0;
-    while (C.naive_loff[l + 1] <= q) ++l;
-    q -= C.naive_loff[l];
+    while (gmem(C.naive_loff)[l + 1] <= q) ++l;
+    q -= gmem(C.naive_loff)[l];
     const int ng = (B - l + NG - 1) / NG;
     const int m = q / ng - l;
     const int n0 = l + 1 + (q - (m + l) * ng) * NG;
     const int nn = min(NG, B + 1 - n0);
     const int am = m < 0 ? -m : m;
     const double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;  // Pbar_{l,-m} = (-1)^m Pbar_lm
-    const double* P = C.P64 + table_block(B, am) + (int64_t)(l - am) * L;
-    const double* R = C.R64 + table_block(B, l) + (int64_t)(n0 - l - 1) * L;
-    const double2* tw = reinterpret_cast<const double2*>(C.tw);  // exp(-2 pi i q / L)
-    const double2* s = samples + C.soff[b];
+    const double* P = gmem(C.P64) + table_block(B, am) + (int64_t)(l - am) * L;
+    const double* R = gmem(C.R64) + table_block(B, l) + (int64_t)(n0 - l - 1) * L;
+    const double2* tw = gmem(reinterpret_cast<const double2*>(C.tw));  // exp(-2 pi i q / L)
+    const double2* s = samples + gmem(C.soff)[b];
     double ar[NG], ai[NG];
     for (int g = 0; g < NG; ++g) ar[g] = ai[g] = 0.0;
     const int L2 = L * L;
@@ -81,10 +81,10 @@ __global__ void __launch_bounds__(NT) k_naive_forward(const ClassDesc* __restric
       const int i = p / L2, jk = p - i * L2, j = jk / L, k = jk - j * L;
       double2 v = s[p];
       if (raw) {
-        v.x *= C.sigma[i];
-        v.y *= C.sigma[i];
+        v.x *= gmem(C.sigma)[i];
+        v.y *= gmem(C.sigma)[i];
       }
-      const double wj = C.btilde[j] * P[j] * sg;
+      const double wj = gmem(C.btilde)[j] * P[j] * sg;
       const double2 t = cmulc(v, tw[phase_index(m, k, L)]);
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(NT) k_naive_forward(const ClassDesc* __restric
     for (int g = 0; g < nn; ++g) {
       const double sr = block_sum(ar[g], red);
       const double si = block_sum(ai[g], red);
-      if (threadIdx.x == 0) coeffs[C.coff[b] + omega(n0 + g, l, m)] = make_double2(sr * C.rs_fwd, si * C.rs_fwd);
+      if (threadIdx.x == 0) coeffs[gmem(C.coff)[b] + omega(n0 + g, l, m)] = make_double2(sr * C.rs_fwd, si * C.rs_fwd);
     }
     __syncthreads();
   }
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(NT) k_naive_inverse(const ClassDesc* __restric
     const int nco = (int)num_coeffs(B);
     if (c != tw_cls) {
       __syncthreads();
-      const double2* tw = reinterpret_cast<const double2*>(C.tw);
+      const double2* tw = gmem(reinterpret_cast<const double2*>(C.tw));
       for (int q = threadIdx.x; q < L; q += NT) tws[q] = tw[q];
       tw_cls = c;
     }
@@ -151,9 +151,9 @@ __global__ void __launch_bounds__(NT) k_naive_inverse(const ClassDesc* __restric
         decode_omega(w0 + e, n, l, m);
         const int am = m < 0 ? -m : m;
         const double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
-        const double f = sg * C.rs_inv * C.R64[table_block(B, l) + (int64_t)(n - l - 1) * L + i] *
-                         C.P64[table_block(B, am) + (int64_t)(l - am) * L + j];
-        const double2 x = coeffs[C.coff[b] + w0 + e];
+        const double f = sg * C.rs_inv * gmem(C.R64)[table_block(B, l) + (int64_t)(n - l - 1) * L + i] *
+                         gmem(C.P64)[table_block(B, am) + (int64_t)(l - am) * L + j];
+        const double2 x = coeffs[gmem(C.coff)[b] + w0 + e];
         Q[e] = make_double2(f * x.x, f * x.y);
         Mq[e] = m;
       }
@@ -173,8 +173,8 @@ __global__ void __launch_bounds__(NT) k_naive_inverse(const ClassDesc* __restric
         }
       }
     }
-    double2* dst = samples + C.soff[b] + ((int64_t)i * L + j) * L;
-    const double inv = raw ? 1.0 / C.sigma[i] : 1.0;
+    double2* dst = samples + gmem(C.soff)[b] + ((int64_t)i * L + j) * L;
+    const double inv = raw ? 1.0 / gmem(C.sigma)[i] : 1.0;
     if (k0 < L) dst[k0] = make_double2(acc0.x * inv, acc0.y * inv);
     if (k1 < L) dst[k1] = make_double2(acc1.x * inv, acc1.y * inv);
   }

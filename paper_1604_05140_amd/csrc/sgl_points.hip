@@ -104,13 +104,13 @@ __global__ void __launch_bounds__(NT) k_midpoint_forward(const ClassDesc* __rest
     const int c = class_of(pre, ncls, w);
     const ClassDesc& C = cls[c];
     const int B = C.B;
-    const int per = C.naive_loff[B];
+    const int per = gmem(C.naive_loff)[B];
     const int64_t rr = w - pre[c];
     const int b = (int)(rr / per);
     int q = (int)(rr - (int64_t)b * per);
     int l = 0;
-    while (C.naive_loff[l + 1] <= q) ++l;
-    q -= C.naive_loff[l];
+    while (gmem(C.naive_loff)[l + 1] <= q) ++l;
+    q -= gmem(C.naive_loff)[l];
     const int ng = (B - l + NG - 1) / NG;
     const int m = q / ng - l;
     const int n0 = l + 1 + (q - (m + l) * ng) * NG;
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(NT) k_midpoint_forward(const ClassDesc* __rest
     const double sg = (m < 0 && (am & 1)) ? -1.0 : 1.0;
     const double inv_s = 1.0 / C.rscale;
     const double al = l + 0.5;
-    const double2* f = values + (int64_t)C.fid[b] * ncell;
+    const double2* f = values + (int64_t)gmem(C.fid)[b] * ncell;
     double ar[NG], ai[NG];
     for (int g = 0; g < NG; ++g) ar[g] = ai[g] = 0.0;
     for (int cell = threadIdx.x; cell < ncell; cell += NT) {
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(NT) k_midpoint_forward(const ClassDesc* __rest
     for (int g = 0; g < nn; ++g) {
       const double sr = block_sum(ar[g], red);
       const double si = block_sum(ai[g], red);
-      if (threadIdx.x == 0) coeffs[C.coff[b] + omega(n0 + g, l, m)] = make_double2(sr * scale, si * scale);
+      if (threadIdx.x == 0) coeffs[gmem(C.coff)[b] + omega(n0 + g, l, m)] = make_double2(sr * scale, si * scale);
     }
     __syncthreads();
   }
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(NT) k_synthesize_points(const ClassDesc* __res
     const double inv_s = 1.0 / C.rscale;
     const Sph p = spherical(xyz[3 * (int64_t)pt] * inv_s, xyz[3 * (int64_t)pt + 1] * inv_s,
                             xyz[3 * (int64_t)pt + 2] * inv_s);
-    const double2* f = coeffs + C.coff[b];
+    const double2* f = coeffs + gmem(C.coff)[b];
     double accr = 0.0, acci = 0.0;
     for (int m = 1 - B; m < B; ++m) {
       const int am = m < 0 ? -m : m;
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(NT) k_synthesize_points(const ClassDesc* __res
       }
     }
     const double e = exp(0.5 * p.r2) * C.rs_inv;  // undo exp(-|y|^2/2) of u_k; s^(-3/2)
-    out[(int64_t)C.fid[b] * npts + pt] = make_double2(accr * e, acci * e);
+    out[(int64_t)gmem(C.fid)[b] * npts + pt] = make_double2(accr * e, acci * e);
   }
 }
 

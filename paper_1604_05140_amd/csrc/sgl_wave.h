@@ -32,7 +32,7 @@ __device__ inline T2 conjc(T2 a) { a.y = -a.y; return a; }
 // caches then hold fewer dirty lines of them, and the next launches' reads
 // run faster (about 7% per transform pair).
 template <typename T2>
-__device__ inline void store_stream(T2* p, T2 v) {
+__device__ inline void store_stream(SGL_G T2* p, T2 v) {
   __builtin_nontemporal_store(v.x, &p->x);
   __builtin_nontemporal_store(v.y, &p->y);
 }
@@ -40,7 +40,7 @@ __device__ inline void store_stream(T2* p, T2 v) {
 // samples are larger than the caches, and streaming them keeps the smaller
 // stage (b)/(c) intermediates cached between their launches.
 template <typename T2>
-__device__ inline T2 load_stream(const T2* p) {
+__device__ inline T2 load_stream(const SGL_G T2* p) {
   T2 v;
   v.x = __builtin_nontemporal_load(&p->x);
   v.y = __builtin_nontemporal_load(&p->y);
