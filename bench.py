@@ -145,6 +145,26 @@ def roofline(form, dtype, B, nf):
     return roof
 
 
+def copy_reference(torch, dev, nbytes=1 << 30, reps=5):
+    """Measured streaming rate of a plain device-to-device copy (torch's copy
+    kernel, read + write bytes over time): a practical ceiling for kernels that
+    read and write HBM once, for context beside the published 8 TB/s."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / ms / 1e6
+
+
 def stage_rooflines(form, dtype, B, nf):
     """Every stage of a form against HBM (algorithmic bytes) and against its
     dtype's dense MFMA peak (issued flops; stage (a) runs on the vector ALUs)."""
@@ -503,6 +523,9 @@ def main():
 
     head = forms[args.dtype]
     roof = roofline(head, args.dtype, B, nf)
+    if roof["bound"] == "hbm":
+        roof["copy_GBps"] = copy_reference(torch, dev)
+        roof["frac_of_copy"] = roof["achieved"] / roof["copy_GBps"]
 
     out = {
         "metric": "SGL fwd+inv transforms/s at B=128 (MFMA split vs FP64), rel err <=1e-6",

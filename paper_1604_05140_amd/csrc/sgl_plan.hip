@@ -620,7 +620,9 @@ sgl_status_t run_direction(sgl_plan_s* p, int dir, const void* in, void* out, hi
 
 // Plan-time autotuner: for every launch slot, time the persistent grid bounds
 // {1, 2, 4, 8, 16} x CUs and "one block per work item" on scratch buffers and
-// keep the fastest.
+// keep the fastest.  The candidates are timed in three interleaved rounds (a
+// warm-up launch and three timed launches each) and each keeps its best round,
+// so that clock drift during tuning does not favour the candidates timed first.
 sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
   int dev = 0, ncu = 256;
   SGL_HIP_TRY(hipGetDevice(&dev));
@@ -645,28 +647,29 @@ sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
     for (int mult : {1, 2, 4, 8, 16})
       if (mult * ncu < n) cand.push_back(mult * ncu);
     cand.push_back(n);
-    float best = 1e30f;
-    int best_g = 0;
-    for (int g : cand) {
-      p->grid[slot] = g;
-      hipError_t e = launch_slot(p, slot, in, out, s);  // warm-up
-      if (e == hipSuccess) e = hipEventRecord(e0, s);
-      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_slot(p, slot, in, out, s);
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        set_error(std::string("autotune: ") + hipGetErrorString(e));
-        st = SGL_ERR_HIP;
-        break;
-      }
-      if (ms < best) {
-        best = ms;
-        best_g = g;
+    std::vector<float> tbest(cand.size(), 1e30f);
+    for (int round = 0; round < 3 && st == SGL_OK; ++round) {
+      for (size_t ci = 0; ci < cand.size(); ++ci) {
+        p->grid[slot] = cand[ci];
+        hipError_t e = launch_slot(p, slot, in, out, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_slot(p, slot, in, out, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          set_error(std::string("autotune: ") + hipGetErrorString(e));
+          st = SGL_ERR_HIP;
+          break;
+        }
+        tbest[ci] = std::min(tbest[ci], ms);
       }
     }
-    p->grid[slot] = best_g;
+    size_t bi = 0;
+    for (size_t ci = 1; ci < cand.size(); ++ci)
+      if (tbest[ci] < tbest[bi]) bi = ci;
+    p->grid[slot] = cand[bi];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
