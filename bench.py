@@ -476,7 +476,9 @@ def main():
     B, nf = args.B, args.batch
     ns, nc = 8 * B ** 3, num_coeffs(B)
     print(f"[bench] B={B} batch={nf} form={args.dtype}: building inputs", file=sys.stderr, flush=True)
-    c = synth.complex_normal_coeffs(B, nf, seed=synth.BASE_SEED + 3, decay=1.0).reshape(-1)
+    # coefficient decay n^-p: p = 1 up to B = 128, 1.5 for the B = 256 configuration
+    decay = 1.5 if B >= 256 else 1.0
+    c = synth.complex_normal_coeffs(B, nf, seed=synth.BASE_SEED + 3, decay=decay).reshape(-1)
     c128 = torch.from_numpy(c).to(dev)
     p64 = sgl.sgl_plan(B, nf, "f64")
     s128 = torch.empty(p64.total_samples, dtype=torch.complex128, device=dev)
@@ -541,7 +543,7 @@ def main():
         "dtype": {"split_bf16": "bf16x3 (fp32 accumulate)", "f32": "f32", "f64": "f64"}[args.dtype],
         "data": "synthetic",
         "config": {
-            "workload": f"SGL forward+inverse, B={B}, batch {nf}, complex-normal/n coefficients, "
+            "workload": f"SGL forward+inverse, B={B}, batch {nf}, complex-normal/n^{decay:g} coefficients, "
                         f"{'complex128' if args.dtype == 'f64' else 'complex64'} scaled samples on the "
                         f"sampling-theorem grid",
             "B": B, "batch": nf, "form": args.dtype,
