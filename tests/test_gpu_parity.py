@@ -224,8 +224,8 @@ def test_fp64_raw_samples_512_point_rings():
 
 def test_fp64_config2_b64_subsets_and_round_trip():
     """B = 64, batch 1, CN(0,1)/n: GPU inverse at 200 seeded grid points against
-    the oracle's synthesis sum; GPU forward at 200 seeded coefficients against the
-    oracle's quadrature sum on the same samples; round trip."""
+    the oracle's synthesis sum; round trip; GPU forward of seeded CN(0,1) samples
+    at 200 seeded coefficients against the oracle's quadrature sum."""
     B = 64
     c = synth.complex_normal_coeffs(B, 1, seed=SEED + 2, decay=1.0)[0]
     plan = sgl.sgl_plan(B, 1, "f64")
@@ -234,12 +234,14 @@ def test_fp64_config2_b64_subsets_and_round_trip():
     pts = synth.grid_points(200, B, seed=SEED + 1002)
     s_or = D.inverse(c, B, points=pts)
     s_at = s.reshape(2 * B, 2 * B, 2 * B)[pts[:, 0], pts[:, 1], pts[:, 2]]
-    assert np.abs(s_at - s_or).max() <= 1e-12 * np.abs(s).max()
+    assert np.abs(s_at - s_or).max() <= 1e-12 * np.abs(s_or).max()
     c2 = gpu_forward(plan, s_gpu).cpu().numpy()
     assert einf(c, c2) <= 1e-12
+    s_arb = synth.complex_normal_samples(B, 1, seed=SEED + 1006)[0]
+    c_arb = gpu_forward(plan, s_arb).cpu().numpy()
     oms = synth.subset(200, D.num_coeffs(B), seed=SEED + 1003)
-    f_or = D.forward(s, B, omegas=oms)
-    assert np.abs(c2[oms] - f_or).max() <= 1e-12 * np.abs(c).max()
+    f_or = D.forward(s_arb, B, omegas=oms)
+    assert np.abs(c_arb[oms] - f_or).max() <= 1e-12 * np.abs(f_or).max()
 
 
 def test_batched_uneven_bandlimits_fp64():
@@ -295,27 +297,66 @@ def _precision_case(B, batch, decay, seed, dtypes=(("f32", 1e-5), ("split_bf16",
     return c, s_host, res
 
 
+def psi_of(pts, B):
+    """psi index of (i, j, k) grid triples (Sect. 3.4 ordering)."""
+    return (pts[:, 0] * 2 * B + pts[:, 1]) * 2 * B + pts[:, 2]
+
+
 def test_precision_forms_small_b():
     _precision_case(12, 3, 1.0, SEED + 60)
 
 
 def test_precision_forms_config3_b128():
     """B = 128, batch 4, CN(0,1)/n: FP32 MFMA (1e-5) and split-bf16 (1e-6) against
-    FP64; the FP64 samples checked against the oracle at 24 seeded coefficients."""
+    FP64; the FP64 synthesis of function 1 checked against the oracle's synthesis
+    of the same seeded coefficients at 24 seeded grid points."""
     B, batch = 128, 4
     c, s1, _ = _precision_case(B, batch, 1.0, SEED + 3, host_fn=1)
-    oms = synth.subset(24, D.num_coeffs(B), seed=SEED + 1004)
-    f_or = D.forward(s1, B, omegas=oms)
-    assert np.abs(c[1][oms] - f_or).max() <= 1e-12 * np.abs(c[1]).max()
+    pts = synth.grid_points(24, B, seed=SEED + 1004)
+    ref = D.inverse(c[1], B, points=pts)
+    assert np.abs(s1[psi_of(pts, B)] - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 def test_precision_config5_b256_split():
     """B = 256, batch 8, CN(0,1) n^-1.5: split-bf16 against FP64 (1e-6)."""
     B, batch = 256, 8
     c, s0, _ = _precision_case(B, batch, 1.5, SEED + 5, dtypes=(("split_bf16", 1e-6),), host_fn=0)
-    oms = synth.subset(6, D.num_coeffs(B), seed=SEED + 1005)
-    f_or = D.forward(s0, B, omegas=oms)
-    assert np.abs(c[0][oms] - f_or).max() <= 1e-12 * np.abs(c[0]).max()
+    pts = synth.grid_points(6, B, seed=SEED + 1005)
+    ref = D.inverse(c[0], B, points=pts)
+    assert np.abs(s0[psi_of(pts, B)] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_bench_launch_configuration_split_vs_oracle():
+    """The timed configuration of the benchmark: B = 128, batch 4, split-bf16 plan
+    built with SGL_AUTOTUNE | SGL_GRAPHS, eager capture and a graph replay.
+    Forward: seeded CN(0,1) samples (rounded to complex64, the same values fed
+    to the oracle) at 24 seeded coefficients of function 2 against the oracle's
+    quadrature sums, 1e-6 of the largest of those 24.  Inverse: seeded
+    CN(0,1)/n coefficients (complex64) at 24 seeded grid points of function 3
+    against the oracle's synthesis, 1e-6 of the largest sample magnitude (the
+    e_inf denominator, taken from the FP64 GPU synthesis of the same
+    coefficients, itself pinned to the oracle above)."""
+    B, batch = 128, 4
+    ns, nc = D.num_samples(B), D.num_coeffs(B)
+    s = synth.complex_normal_samples(B, batch, seed=SEED + 2001).astype(np.complex64)
+    c = synth.complex_normal_coeffs(B, batch, seed=SEED + 2002, decay=1.0).astype(np.complex64)
+    plan = sgl.sgl_plan_ex([B] * batch, "split_bf16", sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS)
+    s_dev, c_dev = dev(s, torch.complex64), dev(c, torch.complex64)
+    oms = synth.subset(24, nc, seed=SEED + 2003)
+    f_ref = D.forward(s[2].astype(np.complex128), B, omegas=oms)
+    pts = synth.grid_points(24, B, seed=SEED + 2004)
+    s_ref = D.inverse(c[3].astype(np.complex128), B, points=pts)
+    p64 = sgl.sgl_plan(B, 1, "f64")
+    smax = float(gpu_inverse(p64, dev(c[3], torch.complex128)).abs().max())
+    p64.destroy()
+    for call in range(2):  # capture, then replay
+        cf = gpu_forward(plan, s_dev)[2 * nc:3 * nc].cpu().numpy()
+        sf = gpu_inverse(plan, c_dev)[3 * ns:4 * ns].cpu().numpy()
+        ef = np.abs(cf[oms] - f_ref).max() / np.abs(f_ref).max()
+        ei = np.abs(sf[psi_of(pts, B)] - s_ref).max() / smax
+        print(f"bench configuration, call {call}: forward {ef:.2e}, inverse {ei:.2e}", flush=True)
+        assert ef <= 1e-6 and ei <= 1e-6, (call, ef, ei)
+    plan.destroy()
 
 
 # ---------------------------------------------------------------------------
@@ -395,11 +436,11 @@ def test_batched_config4_256_functions_f32():
     print(f"config4: FP64 round trip {worst_rt:.2e}; FP32 forward {worst_f:.2e}, inverse {worst_i:.2e}", flush=True)
     assert worst_rt <= 1e-12
     assert worst_f <= 1e-5 and worst_i <= 1e-5
-    # oracle spot check on the two smallest functions
+    # oracle spot check on the two smallest functions: FP64 synthesis at seeded
+    # grid points against the oracle's synthesis of the same coefficients
     for q in np.argsort(Bs)[:2]:
         B = int(Bs[q])
-        s_host = s64[so[q]:so[q] + D.num_samples(B)].cpu().numpy()
-        oms = synth.subset(8, D.num_coeffs(B), seed=SEED + 4100 + int(q))
-        f_or = D.forward(s_host, B, omegas=oms)
-        got = c64[co[q]:co[q] + D.num_coeffs(B)].cpu().numpy()[oms]
-        assert np.abs(got - f_or).max() <= 1e-12 * np.abs(cs[q]).max()
+        pts = synth.grid_points(8, B, seed=SEED + 4100 + int(q))
+        s_or = D.inverse(cs[q], B, points=pts)
+        got = s64[so[q]:so[q] + D.num_samples(B)].cpu().numpy()[psi_of(pts, B)]
+        assert np.abs(got - s_or).max() <= 1e-12 * np.abs(s_or).max()
