@@ -139,7 +139,7 @@ sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t s);
 // Build one class.  `share` (may be null) is an earlier class of the same
 // bandlimit whose grid, tables and FFT constants are reused.
 sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hipStream_t s) {
-  const int B = c.B, L = 2 * B, nf = (int)c.funcs.size();
+  const int B = c.B, L = 2 * B;
   const int64_t ts = table_size(B);
   if (share) {
     c.grid = share->grid;
@@ -233,7 +233,7 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
 }
 
 // Per-class workspace, function offsets and FFT blocking (not shared).
-sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
+sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t /*s*/) {
   const int B = c.B, L = 2 * B, nf = (int)c.funcs.size();
   const size_t es = p->esz();
   SGL_TRY(p->alloc(&c.F, (size_t)(2 * B - 1) * L * nf * L * es));
@@ -263,7 +263,7 @@ sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t s) {
   return SGL_OK;
 }
 
-sgl_status_t build_work(sgl_plan_s* p, hipStream_t s) {
+sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
   const int BM = gemm_tile_m(), BNC = gemm_tile_n_complex();
   std::vector<int4> wam[3], wbf, wbi, wcf, wci, wdct;
   if (p->seminaive()) {
