@@ -559,7 +559,7 @@ def main():
         out["speedup_vs_f64"] = head["transforms_per_s"] / forms["f64"]["transforms_per_s"]
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(B, 16, 200, synth.BASE_SEED + 7)
+        out["cpu_baseline"] = cpu_baseline(B, 48, 600, synth.BASE_SEED + 7)
     print(json.dumps(out), flush=True)
 
 
