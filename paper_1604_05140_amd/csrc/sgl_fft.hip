@@ -275,22 +275,37 @@ __device__ inline void fwd_blue(const ClassDesc& C, int j, int col0, int nr, int
   using T2 = typename C2<T>::t;
   constexpr int M = R1 * R2;
   const int L = C.L, B = C.B;
-  for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
-    const int r = e / M, k = e - r * M;
-    T2 v;
-    v.x = 0;
-    v.y = 0;
-    if (k < L) {
+  // four loads per thread in flight before any is used (indices past the ring set or the ring
+  // length load a valid sample and are replaced by zero or skipped)
+  const int ne = nr * M;
+  for (int e0 = threadIdx.x; e0 < ne; e0 += 4 * blockDim.x) {
+    T2 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = min(e0 + q * (int)blockDim.x, ne - 1);
+      const int r = e / M, k = e - r * M;
       const int col = col0 + r;
       const int b = col / L, i = col - b * L;
-      v = cmul(load_stream(&samples[gmem(C.soff)[b] + ((int64_t)i * L + j) * L + k]), chirp[k]);
-      if (RAW) {
-        const T sg = (T)gmem(C.sigma)[i];
-        v.x *= sg;
-        v.y *= sg;
-      }
+      v[q] = load_stream(&samples[gmem(C.soff)[b] + ((int64_t)i * L + j) * L + min(k, L - 1)]);
     }
-    buf[r * M + k] = v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = e0 + q * (int)blockDim.x;
+      if (e >= ne) break;
+      const int r = e / M, k = e - r * M;
+      T2 w;
+      w.x = 0;
+      w.y = 0;
+      if (k < L) {
+        w = cmul(v[q], chirp[k]);
+        if (RAW) {
+          const T sg = (T)gmem(C.sigma)[(col0 + r) % L];
+          w.x *= sg;
+          w.y *= sg;
+        }
+      }
+      buf[r * M + k] = w;
+    }
   }
   __syncthreads();
   T2 z[R1];
@@ -326,16 +341,27 @@ __device__ inline void inv_blue(const ClassDesc& C, int j, int col0, int nr, int
   const int ncol = C.nf * L;
   const SGL_G T2* F = gmem(reinterpret_cast<const T2*>(C.F));
   // bins p < L in the ring-fastest order of F rows, twisted by conj(c_p)
-  for (int e = threadIdx.x; e < nr * L; e += blockDim.x) {
-    const int p = e / nr, r = e - p * nr;
-    T2 v;
-    v.x = 0;
-    v.y = 0;
-    if (p != B) {
-      const int mi = (p < B ? p : p - L) + B - 1;
-      v = cmul(load_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r]), conjc(chirp[p]));
+  // four loads per thread in flight before any is used (bin B loads a valid row and is zeroed)
+  const int ne = nr * L;
+  for (int e0 = threadIdx.x; e0 < ne; e0 += 4 * blockDim.x) {
+    T2 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = min(e0 + q * (int)blockDim.x, ne - 1);
+      const int p = e / nr, r = e - p * nr;
+      const int pc = p == B ? 0 : p;
+      const int mi = (pc < B ? pc : pc - L) + B - 1;
+      v[q] = load_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r]);
     }
-    buf[r * M + p] = v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = e0 + q * (int)blockDim.x;
+      if (e >= ne) break;
+      const int p = e / nr, r = e - p * nr;
+      T2 w = cmul(v[q], conjc(chirp[p]));
+      if (p == B) w.x = w.y = 0;
+      buf[r * M + p] = w;
+    }
   }
   for (int e = threadIdx.x; e < nr * (M - L); e += blockDim.x) {
     const int r = e / (M - L), p = L + e - r * (M - L);
@@ -526,16 +552,28 @@ __device__ inline void inv512(const ClassDesc& C, int j, int col0, int nr, SGL_G
       T2* stage = smem + r * P;
       const SGL_G T2* src = F + (int64_t)j * ncol + col0 + r;
       const int64_t row = (int64_t)L * ncol;
-      for (int p = threadIdx.x / kRings512; p < nb; p += blockDim.x / kRings512) {
-        T2 v;
-        v.x = 0;
-        v.y = 0;
-        if (p != B && p < L) {
-          const int mi = (p < B ? p : p - L) + B - 1;
-          v = load_stream(&src[mi * row]);
-          if (C.M) v = cmul(v, conjc(ch[p]));
+      // thread rows p0 + 64 s; all loads of a thread are issued before any is used (bin B and the
+      // Bluestein padding bins p >= L load a valid row and are set to zero)
+      // (groups of four rows: the single-precision kernel keeps to 64 registers)
+      constexpr int kStep = fft_threads(1, false) / kRings512, kGroup = 4;
+      const int p0 = threadIdx.x / kRings512;
+      for (int g0 = 0; g0 < nb; g0 += kGroup * kStep) {
+        T2 v[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+          const int p = g0 + p0 + kStep * q;
+          const int pc = (p != B && p < L) ? p : 0;
+          const int mi = (pc < B ? pc : pc - L) + B - 1;
+          v[q] = load_stream(&src[mi * row]);
         }
-        stage[p] = v;
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+          const int p = g0 + p0 + kStep * q;
+          T2 w = v[q];
+          if (C.M) w = cmul(w, conjc(ch[p]));
+          if (p == B || p >= L) w.x = w.y = 0;
+          stage[p] = w;
+        }
       }
     }
   }
