@@ -91,29 +91,54 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
         ftab[q] = v;
       }
       if (!INV) {
-        for (int e = threadIdx.x; e < L * nc; e += blockDim.x) {
-          const int j = e / nc, r = e - j * nc;
-          const S2 f = load_stream(&Fb[(int64_t)j * ncol + r]);
-          const double sg = par ? sn[j].x : 1.0;
-          areas[r * AP + j] = make_double2(f.x * sg, f.y * sg);
+        // four loads per thread in flight before any is used
+        const int ne = L * nc;
+        for (int e0 = threadIdx.x; e0 < ne; e0 += 4 * blockDim.x) {
+          S2 f[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = min(e0 + q * (int)blockDim.x, ne - 1);
+            const int j = e / nc, r = e - j * nc;
+            f[q] = load_stream(&Fb[(int64_t)j * ncol + r]);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * (int)blockDim.x;
+            if (e >= ne) break;
+            const int j = e / nc, r = e - j * nc;
+            const double sg = par ? sn[j].x : 1.0;
+            areas[r * AP + j] = make_double2(f[q].x * sg, f[q].y * sg);
+          }
         }
       } else {
         for (int e = threadIdx.x; e < nc * AP; e += blockDim.x) areas[e] = make_double2(0.0, 0.0);
         __syncthreads();
-        for (int e = threadIdx.x; e < B * nc; e += blockDim.x) {
-          const int k = e / nc, r = e - k * nc;
-          const S2 f = Fb[(int64_t)k * ncol + r];
-          const T2 u = make_double2(f.x, f.y);
-          const T2 p = post[k];
-          T2 a = cm(u, cconj(p));
-          a.x += a.x;
-          a.y += a.y;
-          areas[r * AP + k] = a;
-          if (k > 0) {
-            T2 c = cm(u, p);
-            c.x += c.x;
-            c.y += c.y;
-            areas[r * AP + P2 - k] = c;
+        const int ne = B * nc;
+        for (int e0 = threadIdx.x; e0 < ne; e0 += 4 * blockDim.x) {
+          S2 f[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = min(e0 + q * (int)blockDim.x, ne - 1);
+            const int k = e / nc, r = e - k * nc;
+            f[q] = Fb[(int64_t)k * ncol + r];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * (int)blockDim.x;
+            if (e >= ne) break;
+            const int k = e / nc, r = e - k * nc;
+            const T2 u = make_double2(f[q].x, f[q].y);
+            const T2 p = post[k];
+            T2 a = cm(u, cconj(p));
+            a.x += a.x;
+            a.y += a.y;
+            areas[r * AP + k] = a;
+            if (k > 0) {
+              T2 c = cm(u, p);
+              c.x += c.x;
+              c.y += c.y;
+              areas[r * AP + P2 - k] = c;
+            }
           }
         }
       }
@@ -160,17 +185,29 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
     }
     if (!INV) {
       // rows j of the tile -> bit-reversed slots j and 4B-1-j of the even extension
-      for (int e = threadIdx.x; e < L * nc; e += blockDim.x) {
-        const int j = e / nc, r = e - j * nc;
-        const S2 f = load_stream(&Fb[(int64_t)j * ncol + r]);
-        T2 x = make_double2(f.x, f.y);
-        if (par) {
-          x.x *= sn[j].x;
-          x.y *= sn[j].x;
+      const int ne = L * nc;
+      for (int e0 = threadIdx.x; e0 < ne; e0 += 4 * blockDim.x) {
+        S2 f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = min(e0 + q * (int)blockDim.x, ne - 1);
+          const int j = e / nc, r = e - j * nc;
+          f[q] = load_stream(&Fb[(int64_t)j * ncol + r]);
         }
-        T2* b = bufs + r * CP;
-        b[__brev((unsigned)j) >> (32 - lg)] = x;
-        b[__brev((unsigned)(P2 - 1 - j)) >> (32 - lg)] = x;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = e0 + q * (int)blockDim.x;
+          if (e >= ne) break;
+          const int j = e / nc, r = e - j * nc;
+          T2 x = make_double2(f[q].x, f[q].y);
+          if (par) {
+            x.x *= sn[j].x;
+            x.y *= sn[j].x;
+          }
+          T2* b = bufs + r * CP;
+          b[__brev((unsigned)j) >> (32 - lg)] = x;
+          b[__brev((unsigned)(P2 - 1 - j)) >> (32 - lg)] = x;
+        }
       }
     } else {
       for (int e = threadIdx.x; e < nc * CP; e += blockDim.x) {
@@ -180,21 +217,33 @@ __global__ void __launch_bounds__(1024) k_dct(const ClassDesc* __restrict__ cls,
         bufs[e] = z;
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < B * nc; e += blockDim.x) {
-        const int k = e / nc, r = e - k * nc;
-        const S2 f = Fb[(int64_t)k * ncol + r];
-        const T2 u = make_double2(f.x, f.y);
-        const T2 p = post[k];
-        T2* b = bufs + r * CP;
-        T2 a = cm(u, cconj(p));  // a_k exp(+i pi k / 4B) / 2
-        a.x += a.x;
-        a.y += a.y;
-        b[__brev((unsigned)k) >> (32 - lg)] = a;
-        if (k > 0) {
-          T2 c = cm(u, p);
-          c.x += c.x;
-          c.y += c.y;
-          b[__brev((unsigned)(P2 - k)) >> (32 - lg)] = c;
+      const int ne = B * nc;
+      for (int e0 = threadIdx.x; e0 < ne; e0 += 4 * blockDim.x) {
+        S2 f[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = min(e0 + q * (int)blockDim.x, ne - 1);
+          const int k = e / nc, r = e - k * nc;
+          f[q] = Fb[(int64_t)k * ncol + r];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = e0 + q * (int)blockDim.x;
+          if (e >= ne) break;
+          const int k = e / nc, r = e - k * nc;
+          const T2 u = make_double2(f[q].x, f[q].y);
+          const T2 p = post[k];
+          T2* b = bufs + r * CP;
+          T2 a = cm(u, cconj(p));  // a_k exp(+i pi k / 4B) / 2
+          a.x += a.x;
+          a.y += a.y;
+          b[__brev((unsigned)k) >> (32 - lg)] = a;
+          if (k > 0) {
+            T2 c = cm(u, p);
+            c.x += c.x;
+            c.y += c.y;
+            b[__brev((unsigned)(P2 - k)) >> (32 - lg)] = c;
+          }
         }
       }
     }
