@@ -393,6 +393,39 @@ def test_graph_replays_match_eager(dtype):
     assert torch.equal(c_out2, c_out)
 
 
+def test_graph_cache_eviction_and_caller_streams():
+    """SGL_GRAPHS keeps at most eight instantiated graphs: ten output buffers used in
+    turn (each call a capture or a replay after eviction) all equal the eager result,
+    on the default stream and on a caller-created stream."""
+    B, batch = 16, 1
+    eager = sgl.sgl_plan(B, batch, "split_bf16")
+    graph = sgl.sgl_plan_ex([B] * batch, "split_bf16", sgl.SGL_GRAPHS)
+    ct = eager.complex_dtype
+    s_in = dev(synth.complex_normal_samples(B, batch, seed=SEED + 95), ct)
+    c_in = dev(synth.complex_normal_coeffs(B, batch, seed=SEED + 96), ct)
+    ref_c = gpu_forward(eager, s_in)
+    ref_s = gpu_inverse(eager, c_in)
+    outs_c = [torch.empty(graph.total_coeffs, dtype=ct, device=DEV) for _ in range(10)]
+    outs_s = [torch.empty(graph.total_samples, dtype=ct, device=DEV) for _ in range(10)]
+    side = torch.cuda.Stream()
+    for rnd in range(2):
+        for q in range(10):
+            for o in (outs_c[q], outs_s[q]):
+                o.fill_(float("nan"))
+            st = side if (q + rnd) % 2 else None
+            if st is not None:
+                st.wait_stream(torch.cuda.current_stream())
+            sgl.sgl_forward(graph, s_in, outs_c[q], st)
+            sgl.sgl_inverse(graph, c_in, outs_s[q], st)
+            if st is not None:
+                torch.cuda.current_stream().wait_stream(st)
+            torch.cuda.synchronize()
+            assert torch.equal(outs_c[q], ref_c), (rnd, q)
+            assert torch.equal(outs_s[q], ref_s), (rnd, q)
+    graph.destroy()
+    eager.destroy()
+
+
 def test_autotuned_plan_matches_default():
     B, batch = 16, 3
     s = synth.complex_normal_samples(B, batch, seed=SEED + 90)
