@@ -6,6 +6,7 @@ oracle; FP32 1e-5 and split-bf16 1e-6 against the plain FP64 GPU path on the
 same inputs (which is itself held to 1e-12 against the oracle).
 """
 
+import ctypes
 import math
 
 import numpy as np
@@ -424,6 +425,33 @@ def test_graph_cache_eviction_and_caller_streams():
             assert torch.equal(outs_s[q], ref_s), (rnd, q)
     graph.destroy()
     eager.destroy()
+
+
+def test_call_argument_errors_leave_outputs_untouched():
+    """Through the C ABI on a live plan: null data pointers and overlapping input and
+    output are rejected with SGL_ERR_INVALID_ARG, the naive transforms of a non-FP64
+    plan with SGL_ERR_UNSUPPORTED, and no output element is written."""
+    lib = sgl._load()
+    B = 8
+    plan = sgl.sgl_plan(B, 1, "split_bf16")
+    ct = plan.complex_dtype
+    s = dev(synth.complex_normal_samples(B, 1, seed=SEED + 97), ct)
+    c = torch.full((plan.total_coeffs,), 7.0, dtype=ct, device=DEV)
+    buf = torch.zeros(plan.total_samples + plan.total_coeffs, dtype=ct, device=DEV)
+    torch.cuda.synchronize()
+    P = ctypes.c_void_p
+    h, st = plan.handle, P(torch.cuda.current_stream().cuda_stream)
+    assert lib.sgl_forward(h, None, P(c.data_ptr()), st) == 1
+    assert b"null" in lib.sgl_last_error()
+    assert lib.sgl_inverse(h, P(c.data_ptr()), None, st) == 1
+    # output overlapping the input: coefficients written over the samples' tail
+    over = buf.data_ptr() + (plan.total_samples - 1) * buf.element_size()
+    assert lib.sgl_forward(h, P(buf.data_ptr()), P(over), st) == 1
+    assert b"overlap" in lib.sgl_last_error()
+    assert lib.sgl_naive_forward(h, P(s.data_ptr()), P(c.data_ptr()), st) == 2
+    torch.cuda.synchronize()
+    assert bool((c == 7.0).all()) and bool((buf == 0).all())
+    plan.destroy()
 
 
 def test_autotuned_plan_matches_default():
