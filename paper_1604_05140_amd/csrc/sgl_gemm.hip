@@ -151,6 +151,18 @@ struct Tile {
   int64_t plane;    // split-plane stride of the packed table (elements)
 };
 
+// A plan constant at a wave-uniform address, read through the scalar cache (a
+// generic-pointer load would be a flat load, which the compiler makes wait
+// for every outstanding vector-memory operation when its result is used).
+template <typename T>
+__device__ inline T load_uniform(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(4))) T*)p;
+#else
+  return *p;
+#endif
+}
+
 template <int PREC, int KIND>
 __device__ inline Tile make_tile(const ClassDesc* cls, const int4* work, int w, const DebugArgs& dbg) {
   using T = typename DT<PREC>::t;
@@ -187,7 +199,7 @@ __device__ inline Tile make_tile(const ClassDesc* cls, const int4* work, int w, 
     t.pitch = (t.K + BK - 1) / BK * BK;
     t.plane = C.Aplane[KIND];
     t.tab = reinterpret_cast<const unsigned char*>(C.A[KIND]) +
-            C.Aoff[KIND][t.q] * (int64_t)(PREC == PREC_SPLIT ? 2 : sizeof(T));
+            load_uniform(C.Aoff[KIND] + t.q) * (int64_t)(PREC == PREC_SPLIT ? 2 : sizeof(T));
     t.row0 = it.z * BM;
     t.col0 = it.w * BNC;
   }
@@ -731,6 +743,301 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
   }
 }
 
+// ---- split-form forward Legendre stage: operands by global -> LDS copies -----
+// The forward Legendre contraction reads the spectrum F from HBM once (K = 2B
+// contraction rows per item) and runs at the rate at which the CUs keep bytes
+// in flight.  The register-staged kernel above holds one chunk ahead within
+// its register budget.  This kernel moves both operands with 16-byte global ->
+// LDS copies (no registers, no LDS stores): the table through two LDS stages,
+// the data through three, so that the data of the next two chunks are in
+// flight while a chunk is used.  All its vector-memory loads are such copies,
+// so the waits are its own (the compiler makes any use of a loaded register
+// wait for every outstanding copy).  The inverse contraction keeps the kernel
+// above: its items are short (K = B - m) and write 128 KB each, and with one
+// block per CU nothing hides the drain of those stores at the next item's
+// first wait (measured 0.213 ms against 0.150 at B = 128, batch 4).
+//   block: 1024 threads, 16 waves in a 2 x 8 layout; tile 128 rows x 128
+//   complex columns; wave (wr, wc) computes rows wr..wr+63 of complex columns
+//   wc..wc+15 as two 16-column MFMA blocks, real and imaginary parts;
+//   table chunk (3 planes x 128 rows x 32 k, 64 bytes a row and plane, in the
+//   swizzled slot order of swz): 24 copies of 1 KB (16 rows of one plane),
+//   copy q by wave q % 16 (waves 0..7 also take q = 16..23);
+//   data chunk (32 rows x 128 complex columns, 1 KB a row as in memory): wave
+//   w copies rows 2w and 2w + 1, lane l the complex column pair 2l, 2l + 1;
+//   rows sit kLRow = 1040 bytes apart, so that rows 8 apart (the k groups of
+//   an MFMA operand read) fall in opposite halves of the LDS banks.
+// LDS: 2 x 24 KB + 3 x 32.5 KB + one spare row = 147 KB, one block per CU
+// (16 waves, as two 512-thread blocks of the kernel above).
+constexpr int LT = 1024;
+constexpr int LBNC = 128;
+constexpr int kLA = 3 * BM * 64;  // one table stage
+constexpr int kLRow = 1040;
+constexpr int kLX = 32 * kLRow;   // one data stage
+constexpr int kLSpare = 2 * kLA + 3 * kLX;
+constexpr int kLdsL = kLSpare + kLRow;
+
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SGL_L __attribute__((address_space(3)))
+#else
+#define SGL_L
+#endif
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+__device__ inline unsigned lds_u32(const void* p) { return (unsigned)(uintptr_t)(const SGL_L void*)p; }
+
+// One 16-byte global -> LDS copy per lane; lane l writes bytes 16 l .. 16 l + 15
+// of the wave-uniform destination.  NT marks the source as read once
+// (nontemporal cache policy), so that it does not evict what the next stage
+// reads.
+template <bool NT>
+__device__ inline void copy16_to_lds(const SGL_G void* src, unsigned char* dst) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(src, (SGL_L void*)dst, 16, 0, NT ? 2 : 0);
+#endif
+}
+
+// LDS accesses of this kernel are written in asm, each block waiting for its
+// own LDS operations before it ends (outputs are early-clobber, so none shares
+// a register with the address while reads are in flight): an LDS access that
+// the compiler emits while copies are outstanding waits for all of them.
+// Rows 8g + u, u = 0..7, of one complex column of a data stage (a: row 8g).
+__device__ inline void lds_x8(unsigned a, f2v (&r)[8]) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile(
+      "ds_read_b64 %0, %8\n\t"
+      "ds_read_b64 %1, %8 offset:1040\n\t"
+      "ds_read_b64 %2, %8 offset:2080\n\t"
+      "ds_read_b64 %3, %8 offset:3120\n\t"
+      "ds_read_b64 %4, %8 offset:4160\n\t"
+      "ds_read_b64 %5, %8 offset:5200\n\t"
+      "ds_read_b64 %6, %8 offset:6240\n\t"
+      "ds_read_b64 %7, %8 offset:7280\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7])
+      : "v"(a)
+      : "memory");
+#endif
+}
+// The three bf16 planes (8192 bytes apart) of one table fragment.
+__device__ inline void lds_a3(unsigned a, u4 (&r)[3]) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile(
+      "ds_read_b128 %0, %3\n\t"
+      "ds_read_b128 %1, %3 offset:8192\n\t"
+      "ds_read_b128 %2, %3 offset:16384\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2])
+      : "v"(a)
+      : "memory");
+#endif
+}
+// Workgroup barrier without the fence of __syncthreads (which waits for every
+// outstanding vector-memory operation); also a compiler barrier for memory.
+__device__ inline void bar_only() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("s_barrier" ::: "memory");
+#endif
+}
+// Wait until at most N of the wave's vector-memory operations are outstanding
+// (they complete in issue order).
+__device__ inline void wait_vm(int n) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (n == 6)
+    asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+  else if (n == 5)
+    asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
+  else if (n == 4)
+    asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+  else if (n == 3)
+    asm volatile("s_waitcnt vmcnt(3)" ::: "memory");
+  else
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#endif
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_legendre_split(
+    const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork) {
+  static_assert(KIND == K_B_FWD, "forward Legendre only");
+  constexpr int BK = Cfg<PREC_SPLIT>::BK, PS = Cfg<PREC_SPLIT>::PS;
+  static_assert(BK == 32 && PS == 32, "one 16x16x32 MFMA step per chunk, 64-byte table rows");
+  __shared__ __align__(16) unsigned char sm[kLdsL];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 3) * 64, wc = (wave & 7) * 16;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nac = wave < 8 ? 2 : 1;  // table copies per chunk of this wave
+  DebugArgs nodbg{0, 0, 0, nullptr, nullptr, nullptr};
+
+  int w = blockIdx.x;
+  if (w >= nwork) return;
+
+  auto tile = [&](int wi) {
+    Tile tt = make_tile<PREC_SPLIT, KIND>(cls, work, wi, nodbg);
+    tt.col0 = work[wi].w * LBNC;
+    return tt;
+  };
+  // the lane's complex column pair (clamped to the group's last pair, never stored)
+  auto col = [&](const Tile& tt) {
+    return x_col<KIND>(tt, min(tt.col0 + 2 * lane, tt.Ncc - 2), x_base<PREC_SPLIT, KIND>(tt, nullptr));
+  };
+  // table chunk k0 into stage st (2: the spare row); rows past the block clamp
+  // to its last row (they feed outputs that are never stored)
+  auto copy_a = [&](const Tile& tt, int k0, int st) {
+    const SGL_G unsigned char* tab = gmem(reinterpret_cast<const unsigned char*>(tt.tab));
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (s >= nac) break;
+      const int q = wave + 16 * s;
+      const int p = q >> 3, r = 16 * (q & 7) + (lane >> 2);
+      const int g = (lane & 3) ^ ((r >> 1) & 3);
+      const int gr = min(tt.row0 + r, tt.M - 1);
+      const int64_t off = p * tt.plane + (int64_t)gr * tt.pitch + k0 + g * 8;
+      copy16_to_lds<false>(tab + 2 * off, sm + (st == 2 ? kLSpare : st * kLA + q * 1024));
+    }
+  };
+  // data chunk k0 into stage st (3: the spare row); rows past K clamp to the
+  // last one (the table is zero there)
+  auto copy_x = [&](const Tile& tt, const XCol<float>& x, int k0, int st) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int k = min(k0 + 2 * wave + s, tt.K - 1);
+      // the spectrum is read once: streaming copies keep g cached for stage (c)
+      copy16_to_lds<true>(x.p + 2 * x_off<KIND>(tt, x, k),
+                          sm + (st == 3 ? kLSpare : 2 * kLA + st * kLX + (2 * wave + s) * kLRow));
+    }
+  };
+
+  Tile t = tile(w);
+  XCol<float> xc = col(t);
+  int run = 0;  // chunks of earlier items of this block: stage of chunk c is (run + c) % 3 (data), % 2 (table)
+  {
+    const int nc = (t.K + BK - 1) / BK;
+    copy_x(t, xc, 0, 0);
+    copy_x(t, xc, BK, nc > 1 ? 1 : 3);
+    copy_a(t, 0, 0);
+  }
+
+  for (;;) {
+    const int nc = (t.K + BK - 1) / BK;
+    f4 acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = f4{0, 0, 0, 0};
+    int nbi = 0, nbj = 0;
+    {
+      const int rleft = t.M - (t.row0 + wr);
+      nbi = rleft <= 0 ? 0 : (rleft >= 64 ? 4 : (rleft + 15) / 16);
+      nbj = t.Ncc - (t.col0 + wc) <= 0 ? 0 : 2;
+    }
+    const int cc = wc + lr;  // the lane's complex column in the tile
+    const ClassDesc& C = *t.C;
+    // (-1)^m of the -m segment: the contraction is linear, so it is applied to the outputs
+    const float sg = ((t.q & 1) && t.col0 + cc >= C.nf * C.L) ? -1.0f : 1.0f;
+
+    // Chunk c: the copies of table chunk c + 1 and data chunk c + 2 are issued
+    // (past the item's end: to the spare row, so that every iteration issues
+    // the same), then the wave waits for its copies of chunk c.  Issue order:
+    // ... X(c), A(c), X(c+1), A(c+1), X(c+2): the (2 + nac + 2) most recent
+    // may stay outstanding.  Chunk 0 waits for everything older than A(1),
+    // X(2) (its copies were issued at the item's start, the previous item's
+    // stores before or after them).
+    for (int c = 0; c < nc; ++c) {
+      bar_only();  // every wave is done with chunk c - 1: table stage (c + 1) % 2 and data stage (c + 2) % 3 are free
+      copy_a(t, min(c + 1, nc - 1) * BK, c + 1 < nc ? (run + c + 1) % 2 : 2);
+      copy_x(t, xc, min(c + 2, nc - 1) * BK, c + 2 < nc ? (run + c + 2) % 3 : 3);
+      wait_vm(c == 0 ? nac + 2 : nac + 4);
+      bar_only();  // every wave's copies of chunk c are in LDS
+      if (nbj == 0 || nbi == 0) continue;
+      f2v r[8];
+      lds_x8(lds_u32(sm + 2 * kLA + ((run + c) % 3) * kLX) + 8 * lk * kLRow + cc * 8, r);
+      bf8 b[2][3];
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        uint32_t h[3][8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) split3(r[u][part], h[0][u], h[1][u], h[2][u]);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const u4 v = {pack_hi(h[p][0], h[p][1]), pack_hi(h[p][2], h[p][3]), pack_hi(h[p][4], h[p][5]),
+                        pack_hi(h[p][6], h[p][7])};
+          b[part][p] = __builtin_bit_cast(bf8, v);
+        }
+      }
+      const unsigned ab = lds_u32(sm + ((run + c) % 2) * kLA);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i >= nbi) continue;
+        const int row = wr + i * 16 + lr;
+        u4 av[3];
+        lds_a3(ab + (row * PS + swz(row, lk) * 8) * 2, av);
+        bf8 a[3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) a[p] = __builtin_bit_cast(bf8, av[p]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          // smallest products first, the main product last
+          f4& c2 = acc[i][j];
+          c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[j][0], c2, 0, 0, 0);
+          c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][1], c2, 0, 0, 0);
+          c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][2], c2, 0, 0, 0);
+          c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[j][0], c2, 0, 0, 0);
+          c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][1], c2, 0, 0, 0);
+          c2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[j][0], c2, 0, 0, 0);
+        }
+      }
+    }
+
+    // the block's next item: its first chunks are copied while this one is
+    // written, into the stages after this item's last chunk (those held chunks
+    // nc - 3 and nc - 2, or the previous item's, which every wave finished
+    // before the last chunk's barriers)
+    const int wn = w + gridDim.x;
+    const bool more = wn < nwork;
+    Tile tn = t;
+    XCol<float> xn = xc;
+    if (more) {
+      tn = tile(wn);
+      xn = col(tn);
+      const int ncn = (tn.K + BK - 1) / BK;
+      copy_x(tn, xn, 0, (run + nc) % 3);
+      copy_x(tn, xn, BK, ncn > 1 ? (run + nc + 1) % 3 : 3);
+      copy_a(tn, 0, (run + nc) % 2);
+    }
+
+    // epilogue: each lane holds re (block 0) and im (block 1) of complex column
+    // col0 + wc + lr for rows 4 lk + v of each 16-row block: one 8-byte store
+    // per value, 16 lanes covering 128 contiguous bytes of an output row
+    constexpr int DUAL = KIND ^ 1;
+    float* obase = KIND == K_B_FWD ? reinterpret_cast<float*>(t.C->g) : reinterpret_cast<float*>(t.C->F);
+    const int c = t.col0 + cc;
+    if (nbj && c < t.Ncc) {
+      const XCol<float> oc = x_col<DUAL>(t, c, obase);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i >= nbi) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = t.row0 + wr + i * 16 + 4 * lk + v;
+          if (row < t.M) {
+            SGL_G f2v* q = reinterpret_cast<SGL_G f2v*>(oc.p + 2 * x_off<DUAL>(t, oc, row));
+            *q = f2v{sg * acc[i][0][v], sg * acc[i][1][v]};
+          }
+        }
+      }
+    }
+    if (!more) {
+      wait_vm(0);  // no copy into this block's LDS outlives the block
+      break;
+    }
+    run = (run + nc) % 6;
+    w = wn;
+    t = tn;
+    xc = xn;
+  }
+}
+
 inline int grid_for(int nwork, int max_grid) {
   const int g = max_grid > 0 ? max_grid : 8192;
   return nwork < g ? nwork : g;
@@ -742,6 +1049,12 @@ hipError_t launch_kind(int kind, const ClassDesc* d_cls, const int4* d_work, int
   if (nwork == 0) return hipSuccess;
   DebugArgs dbg{0, 0, 0, nullptr, nullptr, nullptr};
   dim3 grid(grid_for(nwork, max_grid)), block(NT);
+  if constexpr (PREC == PREC_SPLIT) {
+    if (kind == K_B_FWD) {
+      hipLaunchKernelGGL((k_legendre_split<K_B_FWD>), grid, dim3(LT), 0, s, d_cls, d_work, nwork);
+      return hipGetLastError();
+    }
+  }
   switch (kind) {
     case K_B_FWD:
       hipLaunchKernelGGL((k_gemm<PREC, K_B_FWD>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
@@ -770,6 +1083,7 @@ hipError_t launch_any(int prec, int kind, const ClassDesc* d_cls, const int4* d_
 
 int gemm_tile_m() { return BM; }
 int gemm_tile_n_complex() { return BNC; }
+int gemm_tile_n_complex_legendre(int prec, bool inverse) { return prec == PREC_SPLIT && !inverse ? LBNC : BNC; }
 int gemm_k_chunk(int prec) {
   return prec == PREC_F64 ? Cfg<PREC_F64>::BK : (prec == PREC_F32 ? Cfg<PREC_F32>::BK : Cfg<PREC_SPLIT>::BK);
 }

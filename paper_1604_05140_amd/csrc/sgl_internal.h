@@ -194,6 +194,7 @@ hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, con
                              hipStream_t s);
 int gemm_tile_m();
 int gemm_tile_n_complex();
+int gemm_tile_n_complex_legendre(int prec, bool inverse);  // column tile of the stage (b) work items
 int gemm_k_chunk(int prec);  // contraction chunk (table K padding) of a precision
 
 // Plan-time FP64 kernels (sgl_tables.hip)

@@ -286,14 +286,16 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
       for (int cb = 0; cb < ncb; ++cb) wam[mode].push_back(make_int4(ci_, j, cb, c.rpb));
     ldsm[mode] = std::max(ldsm[mode], (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
     const int kb = p->seminaive() ? B : L;  // polar-side contraction length
+    const int precb = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
+    const int BNCf = gemm_tile_n_complex_legendre(precb, false), BNCi = gemm_tile_n_complex_legendre(precb, true);
     for (int m = 0; m < B; ++m) {
       const int rows = B - m;
       const int ncc = (m ? 2 : 1) * nf * L;
-      const int nt = (ncc + BNC - 1) / BNC;
+      const int ntf = (ncc + BNCf - 1) / BNCf, nti = (ncc + BNCi - 1) / BNCi;
       for (int mt = 0; mt < (rows + BM - 1) / BM; ++mt)
-        for (int t = 0; t < nt; ++t) bf.push_back({kb, make_int4(ci_, m, mt, t)});
+        for (int t = 0; t < ntf; ++t) bf.push_back({kb, make_int4(ci_, m, mt, t)});
       for (int mt = 0; mt < (kb + BM - 1) / BM; ++mt)
-        for (int t = 0; t < nt; ++t) bi.push_back({rows, make_int4(ci_, m, mt, t)});
+        for (int t = 0; t < nti; ++t) bi.push_back({rows, make_int4(ci_, m, mt, t)});
     }
     if (p->seminaive()) {
       const int nct = (ncol + p->dct_cols - 1) / p->dct_cols;
