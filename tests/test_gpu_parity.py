@@ -298,6 +298,41 @@ def _precision_case(B, batch, decay, seed, dtypes=(("f32", 1e-5), ("split_bf16",
     return c, s_host, res
 
 
+def test_precision_forms_uneven_bandlimits():
+    """Reduced-precision plans over functions of uneven bandlimits (work items of
+    1 to 5 contraction chunks, ragged column tiles, items of different classes in
+    one persistent launch) against the FP64 plan on the same inputs; the FP64
+    results of the largest function checked against the oracle on seeded subsets."""
+    Bs = [5, 17, 40, 3, 64, 9, 33, 70]
+    p64 = sgl.sgl_plan_ex(Bs, "f64")
+    so, co = p64.offsets()
+    cs = [synth.complex_normal_coeffs(B, 1, seed=SEED + 300 + q, decay=1.0)[0] for q, B in enumerate(Bs)]
+    c_all = np.concatenate(cs)
+    s64 = gpu_inverse(p64, dev(c_all, torch.complex128))
+    c64 = gpu_forward(p64, s64)
+    q = Bs.index(70)
+    s_host = s64[so[q]:so[q] + D.num_samples(70)].cpu().numpy()
+    pts = synth.grid_points(12, 70, seed=SEED + 310)
+    ref = D.inverse(cs[q], 70, points=pts)
+    assert np.abs(s_host[psi_of(pts, 70)] - ref).max() <= 1e-12 * np.abs(ref).max()
+    oms = synth.subset(40, D.num_coeffs(70), seed=SEED + 311)
+    f_or = D.forward(s_host, 70, omegas=oms)
+    c_host = c64[co[q]:co[q] + D.num_coeffs(70)].cpu().numpy()
+    assert np.abs(c_host[oms] - f_or).max() <= 1e-12 * np.abs(f_or).max()
+    for dtype, tol in (("f32", 1e-5), ("split_bf16", 1e-6)):
+        for flags in (0, sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS):
+            p = sgl.sgl_plan_ex(Bs, dtype, flags)
+            cf = gpu_forward(p, s64.to(torch.complex64))
+            sf = gpu_inverse(p, dev(c_all, torch.complex64))
+            for q, B in enumerate(Bs):
+                ns, nc = D.num_samples(B), D.num_coeffs(B)
+                ef = einf_dev(c64[co[q]:co[q] + nc], cf[co[q]:co[q] + nc])
+                ei = einf_dev(s64[so[q]:so[q] + ns], sf[so[q]:so[q] + ns])
+                assert ef <= tol and ei <= tol, (dtype, flags, B, ef, ei)
+            p.destroy()
+    p64.destroy()
+
+
 def psi_of(pts, B):
     """psi index of (i, j, k) grid triples (Sect. 3.4 ordering)."""
     return (pts[:, 0] * 2 * B + pts[:, 1]) * 2 * B + pts[:, 2]
