@@ -842,14 +842,8 @@ __device__ inline void bar_only() {
 // (they complete in issue order).
 __device__ inline void wait_vm(int n) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  if (n == 6)
-    asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-  else if (n == 5)
-    asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
-  else if (n == 4)
-    asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
-  else if (n == 3)
-    asm volatile("s_waitcnt vmcnt(3)" ::: "memory");
+  if (n == 2)
+    asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
   else
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #endif
@@ -936,19 +930,19 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
     // (-1)^m of the -m segment: the contraction is linear, so it is applied to the outputs
     const float sg = ((t.q & 1) && t.col0 + cc >= C.nf * C.L) ? -1.0f : 1.0f;
 
-    // Chunk c: the copies of table chunk c + 1 and data chunk c + 2 are issued
-    // (past the item's end: to the spare row, so that every iteration issues
-    // the same), then the wave waits for its copies of chunk c.  Issue order:
-    // ... X(c), A(c), X(c+1), A(c+1), X(c+2): the (2 + nac + 2) most recent
-    // may stay outstanding.  Chunk 0 waits for everything older than A(1),
-    // X(2) (its copies were issued at the item's start, the previous item's
-    // stores before or after them).
+    // Chunk c: the wave waits for its copies of chunk c; one barrier then both
+    // publishes every wave's copies and frees the stages of chunk c - 1, into
+    // which the copies of table chunk c + 1 and data chunk c + 2 go (past the
+    // item's end: to the spare row, so that every iteration issues the same).
+    // Issue order: ... X(c), A(c), X(c+1), A(c+1), X(c+2): at chunk c the two
+    // copies of X(c+1) may stay outstanding.  Chunk 0 waits for everything (its
+    // copies were issued at the item's start, the previous item's stores after
+    // them).
     for (int c = 0; c < nc; ++c) {
-      bar_only();  // every wave is done with chunk c - 1: table stage (c + 1) % 2 and data stage (c + 2) % 3 are free
+      wait_vm(c == 0 ? 0 : 2);
+      bar_only();  // chunk c is in LDS; every wave is done with chunk c - 1
       copy_a(t, min(c + 1, nc - 1) * BK, c + 1 < nc ? (run + c + 1) % 2 : 2);
       copy_x(t, xc, min(c + 2, nc - 1) * BK, c + 2 < nc ? (run + c + 2) % 3 : 3);
-      wait_vm(c == 0 ? nac + 2 : nac + 4);
-      bar_only();  // every wave's copies of chunk c are in LDS
       if (nbj == 0 || nbi == 0) continue;
       f2v r[8];
       lds_x8(lds_u32(sm + 2 * kLA + ((run + c) % 3) * kLX) + 8 * lk * kLRow + cc * 8, r);
@@ -992,7 +986,7 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
     // the block's next item: its first chunks are copied while this one is
     // written, into the stages after this item's last chunk (those held chunks
     // nc - 3 and nc - 2, or the previous item's, which every wave finished
-    // before the last chunk's barriers)
+    // before the last chunk's barrier)
     const int wn = w + gridDim.x;
     const bool more = wn < nwork;
     Tile tn = t;
