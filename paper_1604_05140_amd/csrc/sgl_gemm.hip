@@ -26,10 +26,10 @@
 //   * the table operand comes pre-packed per direction (row-major, K padded to
 //     a multiple of 64 with zeros), so every table load is a 16-byte vector;
 //   * data-operand loads follow the layout the previous stage wrote: each
-//     lane holds 8 consecutive k of one column (index offsets in 32-bit
+//     thread holds BK / 8 consecutive k of one column (index offsets in 32-bit
 //     arithmetic from a per-column pointer), and the chunk goes to LDS as
-//     [column][k] (one 16-byte LDS store per column and bf16 plane); loads
-//     past the group are clamped instead of branched around;
+//     [column][k] (split form: one 8-byte LDS store per column, part and bf16
+//     plane); loads past the group are clamped instead of branched around;
 //   * the epilogue writes the accumulators straight into the next stage's
 //     layout (each store instruction covers 64-byte runs of 4 rows):
 //       F    [(m+B-1)][j][b*2B+i]                 (stage a <-> b)
@@ -37,10 +37,13 @@
 //       fhat [b][omega]                             (stage c <-> caller)
 //
 // Precisions: FP64 (v_mfma_f64_16x16x4), FP32 (v_mfma_f32_16x16x4), and a
-// three-piece bf16 split of both operands (x = x0 + x1 + x2, each a bf16
-// rounding of the remainder) whose six products of order <= 2 run on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation (main product and the five
-// corrections in separate accumulators).
+// three-piece bf16 split of both operands (x = x0 + x1 + x2: the packed tables
+// by round-to-nearest of each remainder, the data by exact truncation, split3)
+// whose six products of order <= 2 run on v_mfma_f32_16x16x32_bf16 into one
+// FP32 accumulator per output, smallest products first.
+//
+// The split forward Legendre contraction has a kernel of its own,
+// k_legendre_split below, fed by global -> LDS copies.
 #include "sgl_internal.h"
 
 namespace sgl {
