@@ -45,3 +45,14 @@ def test_roofline_takes_the_longest_stage(slow):
     nbytes = bench.stage_work(B, NF, "split_bf16")[slow][1]
     assert math.isclose(r["achieved"], nbytes / 0.25e-3 / 1e9)
     assert math.isclose(r["frac"], r["achieved"] / 8000.0)
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})])
+def test_bench_refuses_more_than_one_gpu(argv, env):
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *argv], capture_output=True, text=True,
+                       env={**os.environ, **env}, timeout=120)
+    assert r.returncode == 2
+    assert "--gpus must be 1" in r.stderr
+    assert r.stdout == ""
