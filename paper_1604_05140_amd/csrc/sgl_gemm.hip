@@ -42,8 +42,8 @@
 // whose six products of order <= 2 run on v_mfma_f32_16x16x32_bf16 into one
 // FP32 accumulator per output, smallest products first.
 //
-// The split forward Legendre contraction has a kernel of its own,
-// k_legendre_split below, fed by global -> LDS copies.
+// The split-form Legendre contractions (both directions) have a kernel of
+// their own, k_legendre_split below, fed by global -> LDS copies.
 #include "sgl_internal.h"
 
 namespace sgl {
@@ -746,19 +746,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
   }
 }
 
-// ---- split-form forward Legendre stage: operands by global -> LDS copies -----
-// The forward Legendre contraction reads the spectrum F from HBM once (K = 2B
-// contraction rows per item) and runs at the rate at which the CUs keep bytes
+// ---- split-form Legendre stages: operands by global -> LDS copies ----------
+// The Legendre contractions stream their data operand (the spectrum F forward,
+// the intermediate g inverse) and run at the rate at which the CUs keep bytes
 // in flight.  The register-staged kernel above holds one chunk ahead within
 // its register budget.  This kernel moves both operands with 16-byte global ->
 // LDS copies (no registers, no LDS stores): the table through two LDS stages,
 // the data through three, so that the data of the next two chunks are in
 // flight while a chunk is used.  All its vector-memory loads are such copies,
 // so the waits are its own (the compiler makes any use of a loaded register
-// wait for every outstanding copy).  The inverse contraction keeps the kernel
-// above: its items are short (K = B - m) and write 128 KB each, and with one
-// block per CU nothing hides the drain of those stores at the next item's
-// first wait (measured 0.213 ms against 0.150 at B = 128, batch 4).
+// wait for every outstanding copy).  The inverse writes 128 KB per item: its
+// stores are issued by every lane in a fixed number, so that the next item's
+// first wait can leave them outstanding (with one block per CU nothing else
+// would hide their drain).
 //   block: 1024 threads, 16 waves in a 2 x 8 layout; tile 128 rows x 128
 //   complex columns; wave (wr, wc) computes rows wr..wr+63 of complex columns
 //   wc..wc+15 as two 16-column MFMA blocks, real and imaginary parts;
@@ -847,15 +847,20 @@ __device__ inline void wait_vm(int n) {
 #if defined(__HIP_DEVICE_COMPILE__)
   if (n == 2)
     asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+  else if (n == 16)
+    asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
   else
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #endif
 }
 
+// target of the epilogue stores that fall outside the group (never read)
+__device__ f2v g_spare_out[64];
+
 template <int KIND>
 __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_legendre_split(
     const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork) {
-  static_assert(KIND == K_B_FWD, "forward Legendre only");
+  static_assert(KIND == K_B_FWD || KIND == K_B_INV, "Legendre kinds only");
   constexpr int BK = Cfg<PREC_SPLIT>::BK, PS = Cfg<PREC_SPLIT>::PS;
   static_assert(BK == 32 && PS == 32, "one 16x16x32 MFMA step per chunk, 64-byte table rows");
   __shared__ __align__(16) unsigned char sm[kLdsL];
@@ -899,8 +904,9 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int k = min(k0 + 2 * wave + s, tt.K - 1);
-      // the spectrum is read once: streaming copies keep g cached for stage (c)
-      copy16_to_lds<true>(x.p + 2 * x_off<KIND>(tt, x, k),
+      // the spectrum is read once: streaming copies keep g cached for stage (c);
+      // g (inverse) is read by both row tiles of a column tile
+      copy16_to_lds<KIND == K_B_FWD>(x.p + 2 * x_off<KIND>(tt, x, k),
                           sm + (st == 3 ? kLSpare : 2 * kLA + st * kLX + (2 * wave + s) * kLRow));
     }
   };
@@ -908,6 +914,7 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
   Tile t = tile(w);
   XCol<float> xc = col(t);
   int run = 0;  // chunks of earlier items of this block: stage of chunk c is (run + c) % 3 (data), % 2 (table)
+  bool first = true;  // no stores of an earlier item are outstanding
   {
     const int nc = (t.K + BK - 1) / BK;
     copy_x(t, xc, 0, 0);
@@ -938,11 +945,11 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
     // which the copies of table chunk c + 1 and data chunk c + 2 go (past the
     // item's end: to the spare row, so that every iteration issues the same).
     // Issue order: ... X(c), A(c), X(c+1), A(c+1), X(c+2): at chunk c the two
-    // copies of X(c+1) may stay outstanding.  Chunk 0 waits for everything (its
-    // copies were issued at the item's start, the previous item's stores after
-    // them).
+    // copies of X(c+1) may stay outstanding.  Chunk 0's copies were issued at
+    // the item's start, followed by the previous item's stores; in the inverse
+    // (every lane issues all 16 of them) those may stay outstanding.
     for (int c = 0; c < nc; ++c) {
-      wait_vm(c == 0 ? 0 : 2);
+      wait_vm(c > 0 ? 2 : (KIND == K_B_INV && !first ? 16 : 0));
       bar_only();  // chunk c is in LDS; every wave is done with chunk c - 1
       copy_a(t, min(c + 1, nc - 1) * BK, c + 1 < nc ? (run + c + 1) % 2 : 2);
       copy_x(t, xc, min(c + 2, nc - 1) * BK, c + 2 < nc ? (run + c + 2) % 3 : 3);
@@ -1005,22 +1012,39 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
 
     // epilogue: each lane holds re (block 0) and im (block 1) of complex column
     // col0 + wc + lr for rows 4 lk + v of each 16-row block: one 8-byte store
-    // per value, 16 lanes covering 128 contiguous bytes of an output row
+    // per value, 16 lanes covering 128 contiguous bytes of an output row.
     constexpr int DUAL = KIND ^ 1;
     float* obase = KIND == K_B_FWD ? reinterpret_cast<float*>(t.C->g) : reinterpret_cast<float*>(t.C->F);
     const int c = t.col0 + cc;
-    if (nbj && c < t.Ncc) {
-      const XCol<float> oc = x_col<DUAL>(t, c, obase);
+    const bool okc = nbj && c < t.Ncc;
+    const XCol<float> oc = x_col<DUAL>(t, min(c, t.Ncc - 1), obase);
+    if constexpr (KIND == K_B_INV) {
+      // Every lane issues all 16 stores (values outside the group go to a
+      // spare array: rare here, the inverse tiles have 128 rows), so that
+      // their number is known at the next item's first wait.  The spectrum
+      // rows stream out (read once by the iFFT).
+      SGL_G f2v* spare = gmem(&g_spare_out[lane]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = t.row0 + wr + i * 16 + 4 * lk + v;
+          const bool ok = okc && i < nbi && row < t.M;
+          SGL_G f2v* q = ok ? reinterpret_cast<SGL_G f2v*>(oc.p + 2 * x_off<DUAL>(t, oc, min(row, t.M - 1))) : spare;
+          __builtin_nontemporal_store(f2v{sg * acc[i][0][v], sg * acc[i][1][v]}, q);
+        }
+      }
+    } else if (okc) {
+      // forward: items with few rows (high orders) leave whole waves idle,
+      // whose stores are skipped
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (i >= nbi) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = t.row0 + wr + i * 16 + 4 * lk + v;
-          if (row < t.M) {
-            SGL_G f2v* q = reinterpret_cast<SGL_G f2v*>(oc.p + 2 * x_off<DUAL>(t, oc, row));
-            *q = f2v{sg * acc[i][0][v], sg * acc[i][1][v]};
-          }
+          if (row < t.M)
+            *reinterpret_cast<SGL_G f2v*>(oc.p + 2 * x_off<DUAL>(t, oc, row)) = f2v{sg * acc[i][0][v], sg * acc[i][1][v]};
         }
       }
     }
@@ -1029,6 +1053,7 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
       break;
     }
     run = (run + nc) % 6;
+    first = false;
     w = wn;
     t = tn;
     xc = xn;
@@ -1049,6 +1074,10 @@ hipError_t launch_kind(int kind, const ClassDesc* d_cls, const int4* d_work, int
   if constexpr (PREC == PREC_SPLIT) {
     if (kind == K_B_FWD) {
       hipLaunchKernelGGL((k_legendre_split<K_B_FWD>), grid, dim3(LT), 0, s, d_cls, d_work, nwork);
+      return hipGetLastError();
+    }
+    if (kind == K_B_INV) {
+      hipLaunchKernelGGL((k_legendre_split<K_B_INV>), grid, dim3(LT), 0, s, d_cls, d_work, nwork);
       return hipGetLastError();
     }
   }
@@ -1080,7 +1109,7 @@ hipError_t launch_any(int prec, int kind, const ClassDesc* d_cls, const int4* d_
 
 int gemm_tile_m() { return BM; }
 int gemm_tile_n_complex() { return BNC; }
-int gemm_tile_n_complex_legendre(int prec, bool inverse) { return prec == PREC_SPLIT && !inverse ? LBNC : BNC; }
+int gemm_tile_n_complex_legendre(int prec, bool /*inverse*/) { return prec == PREC_SPLIT ? LBNC : BNC; }
 int gemm_k_chunk(int prec) {
   return prec == PREC_F64 ? Cfg<PREC_F64>::BK : (prec == PREC_F32 ? Cfg<PREC_F32>::BK : Cfg<PREC_SPLIT>::BK);
 }
