@@ -7,7 +7,11 @@ complex-normal coefficients times 1/n (seeded), and the samples the plain FP64
 GPU path synthesizes from them, rounded to complex64 for the reduced-precision
 forms.  The headline form is the three-piece split-bf16 MFMA path; the plain
 FP64 GPU path is timed beside it, and the split results are checked against it
-(e_inf = max|delta| / max|ref| per function) before timing.
+(e_inf = max|delta| / max|ref| per function) before timing: a form over its
+bar (split-bf16 1e-6, FP32 1e-5) is not timed, and the headline then prints a
+null value with gate_failed and exits non-zero.  Every form is timed with the
+headline's plan flags (SGL_AUTOTUNE | SGL_GRAPHS); the eager FP64 plan is
+timed beside them.
 
 Prints one JSON line.  Also reports per-stage kernel times (HIP events recorded
 on the launch stream inside the timed region), the roofline position of the
@@ -184,32 +188,147 @@ def stage_rooflines(form, dtype, B, nf):
     return out
 
 
-def cpu_baseline(B, n_coef, n_pts, seed):
-    """The oracle (plain direct quadrature sums) on a bounded sample, scaled to a full transform."""
+def host_cpu():
+    """CPU model, logical CPUs and the CPUs this process may use (its worker bound:
+    at most 16, the host share of one GPU)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable, "workers": max(1, min(16, usable))}
+
+
+_ORACLE_JOB = {}
+
+
+def _oracle_forward_part(oms):
+    from oracle import direct as D
+    j = _ORACLE_JOB
+    return D.forward(j["s"], j["B"], omegas=oms)
+
+
+def _oracle_inverse_part(pts):
+    from oracle import direct as D
+    j = _ORACLE_JOB
+    return D.inverse(j["c"], j["B"], points=pts)
+
+
+def _oracle_sample(B, n_coef, n_pts, seed, workers):
+    """Time the oracle's forward sums at n_coef seeded coefficients and its
+    synthesis sums at n_pts seeded grid points, on `workers` processes (1 = this
+    process); returns (forward s, inverse s)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
     from oracle import direct as D
     from paper_1604_05140_amd import synth
 
     D.get_basis(B)  # nodes, weights and basis tables (set-up, not timed)
-    s = synth.complex_normal_samples(B, 1, seed=seed)[0]
-    c = synth.complex_normal_coeffs(B, 1, seed=seed + 1, decay=1.0)[0]
+    _ORACLE_JOB.update(B=B, s=synth.complex_normal_samples(B, 1, seed=seed)[0],
+                       c=synth.complex_normal_coeffs(B, 1, seed=seed + 1, decay=1.0)[0])
     oms = synth.subset(n_coef, D.num_coeffs(B), seed=seed + 2)
     pts = synth.grid_points(n_pts, B, seed=seed + 3)
-    t0 = time.perf_counter()
-    D.forward(s, B, omegas=oms)
-    t1 = time.perf_counter()
-    D.inverse(c, B, points=pts)
-    t2 = time.perf_counter()
-    t_full = (t1 - t0) / n_coef * D.num_coeffs(B) + (t2 - t1) / n_pts * D.num_samples(B)
+    if workers == 1:
+        t0 = time.perf_counter()
+        _oracle_forward_part(oms)
+        t1 = time.perf_counter()
+        _oracle_inverse_part(pts)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+    with mp.get_context("fork").Pool(workers) as pool:
+        pool.map(_oracle_forward_part, [oms[:1]] * workers)  # workers started and warm
+        t0 = time.perf_counter()
+        pool.map(_oracle_forward_part, np.array_split(oms, workers))
+        t1 = time.perf_counter()
+        pool.map(_oracle_inverse_part, np.array_split(pts, workers))
+        t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
+
+
+def cpu_baseline(B, n_coef, n_pts, seed):
+    """The oracle (plain direct quadrature sums, numpy, one process per worker) on a
+    bounded sample, scaled to one full forward+inverse pair: one worker, then every
+    usable host CPU (up to 16) on a sample as many times larger."""
+    from oracle import direct as D
+
+    cpu = host_cpu()
+    W = cpu["workers"]
+    f1, i1 = _oracle_sample(B, n_coef, n_pts, seed, 1)
+    fW, iW = _oracle_sample(B, n_coef * W, n_pts * W, seed, W) if W > 1 else (f1, i1)
+    per_pair = lambda tf, ti, k: tf / (n_coef * k) * D.num_coeffs(B) + ti / (n_pts * k) * D.num_samples(B)
+    t1, tW = per_pair(f1, i1, 1), per_pair(fW, iW, W)
     return {
-        "value": 1.0 / t_full,
+        "value": 1.0 / tW,
         "unit": "transforms/s",
-        "cores": 1,
+        "cores": W,
         "kind": "oracle",
-        "sample": (f"B={B}: forward quadrature sum for {n_coef} seeded coefficients ({t1 - t0:.1f} s) and "
-                   f"inverse synthesis sum at {n_pts} seeded grid points ({t2 - t1:.1f} s), scaled to all "
-                   f"{D.num_coeffs(B)} coefficients and {D.num_samples(B)} points of one forward+inverse pair "
-                   f"(extrapolated {t_full:.3g} s per pair); numpy, single thread"),
+        "host_cpu": cpu["model"],
+        "host_logical_cpus": cpu["logical_cpus"],
+        "host_usable_cpus": cpu["usable_cpus"],
+        "single_core_value": 1.0 / t1,
+        "sample": (f"B={B}: the oracle's forward quadrature sums at seeded coefficients and inverse synthesis "
+                   f"sums at seeded grid points, scaled to all {D.num_coeffs(B)} coefficients and "
+                   f"{D.num_samples(B)} points of one forward+inverse pair (extrapolated); {W} worker processes: "
+                   f"{n_coef * W} coefficients ({fW:.1f} s) + {n_pts * W} points ({iW:.1f} s) -> {tW:.3g} s per "
+                   f"pair; 1 process: {n_coef} coefficients ({f1:.1f} s) + {n_pts} points ({i1:.1f} s) -> "
+                   f"{t1:.3g} s per pair; host {cpu['model']}, {cpu['usable_cpus']} usable of "
+                   f"{cpu['logical_cpus']} logical CPUs"),
     }
+
+
+def bench_oracle(args):
+    """The oracle's full direct transforms (Alg. 1 forward over every coefficient,
+    Alg. 2 synthesis at every grid point) at B = 2..max, on one process and on
+    every usable host CPU (up to 16), as in the paper's Table 2 protocol (one
+    inverse and one forward transform of coefficients with Re, Im uniform on
+    (-1, 1)); CPU only."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from oracle import direct as D
+    from paper_1604_05140_amd import synth
+
+    cpu = host_cpu()
+    W = cpu["workers"]
+    rows = []
+    for B in [b for b in (2, 4, 8, 16, 32) if b <= args.oracle_max_b]:
+        c = synth.uniform_coeffs(B, 1, seed=synth.BASE_SEED + 60 + B)[0]
+        D.get_basis(B)
+        row = {"B": B}
+        for w in sorted({1, W}):
+            t0 = time.perf_counter()
+            if w == 1:
+                s = D.inverse(c, B)
+                t1 = time.perf_counter()
+                f = D.forward(s, B)
+            else:
+                pts = np.stack(np.meshgrid(*(np.arange(2 * B),) * 3, indexing="ij"), -1).reshape(-1, 3)
+                _ORACLE_JOB.update(B=B, c=c)
+                with mp.get_context("fork").Pool(w) as pool:
+                    s = np.concatenate(pool.map(_oracle_inverse_part, np.array_split(pts, w)))
+                t1 = time.perf_counter()
+                _ORACLE_JOB["s"] = s  # the forward's workers are forked with the synthesized samples
+                with mp.get_context("fork").Pool(w) as pool:
+                    f = np.concatenate(pool.map(_oracle_forward_part, np.array_split(np.arange(D.num_coeffs(B)), w)))
+            t2 = time.perf_counter()
+            row[f"workers_{w}"] = {"inverse_s": t1 - t0, "forward_s": t2 - t1, "pair_s": t2 - t0,
+                                   "max_abs_err": float(np.abs(f - c).max())}
+            print(f"[bench] oracle B={B} workers={w}: inverse {t1 - t0:.3g} s, forward {t2 - t1:.3g} s",
+                  file=sys.stderr, flush=True)
+        rows.append(row)
+    print(json.dumps({
+        "metric": "CPU oracle: full direct SGL forward+inverse transform (Alg. 1/2), seconds per pair",
+        "unit": "s", "dtype": "f64", "data": "synthetic", "host_cpu": cpu,
+        "config": {"workload": "one inverse then one forward direct transform, coefficients with Re, Im "
+                               "uniform on (-1, 1)"},
+        "rows": rows}), flush=True)
 
 
 def bench_batched(args, torch, sgl, synth, dev):
@@ -428,12 +547,14 @@ def main():
     ap.add_argument("--dtype", default="split_bf16", choices=["split_bf16", "f32", "f64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and FP32 side runs")
-    ap.add_argument("--workload", default="b128", choices=["b128", "batched", "naive", "midpoint", "seminaive"],
+    ap.add_argument("--workload", default="b128", choices=["b128", "batched", "naive", "midpoint", "seminaive", "oracle"],
                     help="b128: B=128 batch 4 (headline); batched: 256 functions, B uniform in {16..96}; "
                          "naive: naive vs fast FP64 transforms at B = 2..32 (the paper's Sect. 4 protocol); "
                          "midpoint: Cartesian midpoint-rule projection vs the sampling-theorem transform; "
-                         "seminaive: the seminaive (cosine-domain) Legendre step beside the direct sums")
+                         "seminaive: the seminaive (cosine-domain) Legendre step beside the direct sums; "
+                         "oracle: the CPU oracle's full direct transforms at B = 2..32 (no GPU)")
     ap.add_argument("--naive-max-b", type=int, default=32, help="largest bandlimit of the naive workload")
+    ap.add_argument("--oracle-max-b", type=int, default=32, help="largest bandlimit of the oracle workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -443,6 +564,8 @@ def main():
               "(--gpus must be 1).", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "oracle":
+        return bench_oracle(args)
     import torch
 
     from paper_1604_05140_amd import sgl, synth
@@ -475,6 +598,11 @@ def main():
         return bench_seminaive(args, torch, sgl, synth, dev)
     B, nf = args.B, args.batch
     ns, nc = 8 * B ** 3, num_coeffs(B)
+    cpu_base = None
+    if not args.no_cpu_baseline:
+        # the oracle's worker processes are forked before this process touches the GPU
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu_base = cpu_baseline(B, 24, 300, synth.BASE_SEED + 7)
     print(f"[bench] B={B} batch={nf} form={args.dtype}: building inputs", file=sys.stderr, flush=True)
     # coefficient decay n^-p: p = 1 up to B = 128, 1.5 for the B = 256 configuration
     decay = 1.5 if B >= 256 else 1.0
@@ -493,31 +621,56 @@ def main():
         return float(((got - ref).abs().amax(dim=1) / ref.abs().amax(dim=1)).max())
 
     rt64 = einf(c128, c_ref, nc)
+    # the error bar of each form against the plain FP64 GPU path (FP64: its round
+    # trip); a form over its bar is reported without a throughput
+    bar = {"split_bf16": 1e-6, "f32": 1e-5, "f64": 1e-12}
     forms = {}
-    order = [args.dtype] + ([] if args.no_compare else [d for d in ("f64", "f32") if d != args.dtype])
-    for dtype in order:
-        head_form = dtype == args.dtype
-        flags = (sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS) if head_form else 0
-        plan = p64 if (dtype == "f64" and not head_form) else sgl.sgl_plan_ex([B] * nf, dtype, flags)
+    # every form is timed as the headline form is built (SGL_AUTOTUNE | SGL_GRAPHS);
+    # the plain eager FP64 plan of the reference inputs is timed beside it
+    order = [args.dtype] + ([] if args.no_compare else [d for d in ("f64", "f32") if d != args.dtype] + ["f64_eager"])
+    for key in order:
+        head_form = key == args.dtype
+        dtype = "f64" if key == "f64_eager" else key
+        eager = key == "f64_eager"
+        plan = p64 if eager else sgl.sgl_plan_ex([B] * nf, dtype, sgl.SGL_AUTOTUNE | sgl.SGL_GRAPHS)
         s_in = s128 if dtype == "f64" else s128.to(torch.complex64)
         c_in = c128 if dtype == "f64" else c128.to(torch.complex64)
+        # precision gate, before any timing: one forward and one inverse of the
+        # timed plan on the timed inputs against the FP64 GPU results
+        cout = torch.empty(plan.total_coeffs, dtype=plan.complex_dtype, device=dev)
+        sout = torch.empty(plan.total_samples, dtype=plan.complex_dtype, device=dev)
+        sgl.sgl_forward(plan, s_in, cout)
+        sgl.sgl_inverse(plan, c_in, sout)
+        torch.cuda.synchronize()
+        # (an FP64 plan's forward is held to the seeded coefficients themselves)
+        ef, ei = einf(c128 if dtype == "f64" else c_ref, cout, nc), einf(s128, sout, ns)
+        del cout, sout
+        gate_ok = max(ef, ei) <= bar[dtype]
+        print(f"[bench] gate {key}: forward e_inf {ef:.2e}, inverse e_inf {ei:.2e} (bar {bar[dtype]:g}) "
+              f"{'ok' if gate_ok else 'FAILED'}", file=sys.stderr, flush=True)
+        if head_form and not gate_ok:
+            print(json.dumps({"metric": "SGL fwd+inv transforms/s at B=128 (MFMA split vs FP64), rel err <=1e-6",
+                              "value": None, "unit": "transforms/s", "n_gpus": 1, "gate_failed": True,
+                              "e_inf_forward_vs_f64": ef, "e_inf_inverse_vs_f64": ei, "bar": bar[dtype]}),
+                  flush=True)
+            sys.exit(1)
         steps = args.steps if head_form else max(3, args.steps // 4)
         warm = args.warmup if head_form else 2
-        print(f"[bench] timing {dtype}: {warm} warmup + {steps} steps", file=sys.stderr, flush=True)
+        print(f"[bench] timing {key}: {warm} warmup + {steps} steps", file=sys.stderr, flush=True)
         ms, ms_inst, per_stage, cout, sout = run_form(sgl, torch, plan, c_in, s_in, steps, warm)
-        forms[dtype] = {
+        forms[key] = {
             "ms_per_step": ms,
             "transforms_per_s": nf * 1000.0 / ms,
-            "graphs": head_form,
+            "plan_flags": "none (eager launches, default grids)" if eager else "SGL_AUTOTUNE|SGL_GRAPHS",
             "ms_per_step_with_stage_events": ms_inst,
             "stage_ms": per_stage,
             "steps": steps,
-            "e_inf_forward_vs_f64": einf(c_ref, cout, nc),
-            "e_inf_inverse_vs_f64": einf(s128, sout, ns),
+            "e_inf_forward_vs_f64": ef,
+            "e_inf_inverse_vs_f64": ei,
+            "within_bar": gate_ok,
+            "launch_grids": plan.launch_grids(),
         }
-        if head_form:
-            forms[dtype]["launch_grids"] = plan.launch_grids()
-        print(f"[bench] {dtype}: {ms:.3f} ms/step, {nf * 1000.0 / ms:.1f} transforms/s "
+        print(f"[bench] {key}: {ms:.3f} ms/step, {nf * 1000.0 / ms:.1f} transforms/s "
               f"(stage-timed pass {ms_inst:.3f} ms/step)", file=sys.stderr, flush=True)
         del cout, sout
         if plan is not p64:
@@ -556,10 +709,11 @@ def main():
         "coefficients_per_s": head["transforms_per_s"] * nc,
     }
     if "f64" in forms and args.dtype != "f64":
+        # like for like: both plans built with SGL_AUTOTUNE | SGL_GRAPHS
         out["speedup_vs_f64"] = head["transforms_per_s"] / forms["f64"]["transforms_per_s"]
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(B, 48, 600, synth.BASE_SEED + 7)
+        out["speedup_vs_f64_eager"] = head["transforms_per_s"] / forms["f64_eager"]["transforms_per_s"]
+    if cpu_base is not None:
+        out["cpu_baseline"] = cpu_base
     print(json.dumps(out), flush=True)
 
 
