@@ -98,7 +98,8 @@ typedef enum { SGL_F64 = 0, SGL_F32 = 1, SGL_SPLIT_BF16 = 2 } sgl_dtype_t;
                               l - (m mod 2)); the inverse is the transpose (the
                               contraction, then the inverse DCT).  Same results as
                               the direct sums up to rounding.  Power-of-two
-                              bandlimits 8..256 only (SGL_ERR_UNSUPPORTED otherwise). */
+                              bandlimits 8..256 only, and 8..128 in SGL_SPLIT_BF16
+                              (SGL_ERR_UNSUPPORTED otherwise). */
 
 #define SGL_MAX_B 256 /* largest supported bandlimit */
 
@@ -141,6 +142,45 @@ sgl_status_t sgl_plan_scaled(sgl_plan_t* out, const int* B_list, int nfunc, int 
  * with no work reports 0.  grids: host array of SGL_NUM_SLOTS ints. */
 #define SGL_NUM_SLOTS 10
 sgl_status_t sgl_launch_grids(sgl_plan_t plan, int* grids);
+
+/* Tile of each launch slot's contraction kernel (slot order as in
+ * sgl_launch_grids).  tiles: host array of 2 * SGL_NUM_SLOTS ints; receives, per
+ * slot, the rows and complex columns of one work item's output tile (0, 0 for
+ * the FFT slots).  The stage (b)/(c) slots of the register-staged MFMA GEMM (all
+ * of stage (c), and stage (b) in SGL_F64 and SGL_F32) have two tile geometries:
+ *   geometry 0: 128 rows x 64 complex columns, 8 wavefronts (the default),
+ *   geometry 1:  64 rows x 32 complex columns, 4 wavefronts,
+ * and SGL_AUTOTUNE times both (with each persistent grid) and keeps the fastest.
+ * The split-form Legendre kernel has one tile, 128 rows x 128 complex columns. */
+sgl_status_t sgl_launch_tiles(sgl_plan_t plan, int* tiles);
+
+/* Select the tile geometry (0 or 1, see sgl_launch_tiles) of one launch slot.
+ * SGL_ERR_UNSUPPORTED for a geometry the slot does not have; SGL_ERR_INVALID_ARG
+ * for a slot outside [0, SGL_NUM_SLOTS).  The slot keeps its persistent-grid
+ * bound; graphs the plan captured earlier are dropped (the next call with each
+ * buffer pair captures again).  Not to be called while the plan runs a call. */
+sgl_status_t sgl_set_launch_tile(sgl_plan_t plan, int slot, int geometry);
+
+/* Launch schedule of stages (a) and (b).  Whole (0): each stage is one launch
+ * over every function, and the spectrum between the azimuthal FFT and the
+ * Legendre projection (Alg. 3 / Alg. 4; (2B-1) (2B)^2 complex values per
+ * function) passes through HBM.  Slabs (1): the (function, radius) columns of
+ * each bandlimit class are cut into slabs whose spectrum fits the last-level
+ * (Infinity) cache (at most 160 MB each); the forward runs, slab by slab, the FFT
+ * then the Legendre launch, and the inverse the Legendre then the FFT launch,
+ * so each slab's spectrum is read back from the cache (Legendre columns are
+ * independent, Eq. DLT).  The radial stage is one launch either way.  Results
+ * are the same (same kernels and per-element arithmetic).  Classes whose ring
+ * blocks or column tiles do not align with a slab run as one slab.
+ * slabs: 1 if the slab schedule is in use; nslab: slabs of the schedule;
+ * slab_columns: the widest slab in columns (0: no class splits, the slab
+ * schedule is the whole schedule).  Any pointer may be NULL.  SGL_AUTOTUNE
+ * times both schedules and keeps the faster; otherwise the whole schedule. */
+sgl_status_t sgl_launch_schedule(sgl_plan_t plan, int* slabs, int* nslab, int* slab_columns);
+
+/* Select the launch schedule (0 whole, 1 slabs).  SGL_ERR_UNSUPPORTED for 1 when
+ * no class splits; drops captured graphs as sgl_set_launch_tile does. */
+sgl_status_t sgl_set_launch_schedule(sgl_plan_t plan, int slabs);
 
 /* Forward transform (Alg. 3) of every function of the plan.
  * d_samples: device, const, total_samples complex values (complex128 for

@@ -49,10 +49,24 @@
 namespace sgl {
 namespace {
 
-constexpr int BM = 128;      // rows per tile
-constexpr int BN = 128;      // real columns per tile
-constexpr int BNC = BN / 2;  // complex columns per tile
-constexpr int NT = 512;      // 8 waves, 2 x 4 layout of 64 x 32
+// Tile geometries of k_gemm; the plan-time autotuner picks one per launch slot.
+//   TG 0: 128 rows x 64 complex columns, 512 threads, 8 waves (2 x 4) of 64 x 32
+//         real outputs;
+//   TG 1:  64 rows x 32 complex columns, 256 threads, 4 waves (1 x 4) of 64 x 16.
+// Both stage the same number of operand elements per thread, so their register
+// budgets are the same; TG 1 wastes less of its tile on the short row ranges of
+// the high orders / degrees and the narrow column ranges of low degrees and
+// small batches, at the price of more table re-reads per column.
+template <int TG> struct Geo {
+  static constexpr int BM = TG == 0 ? 128 : 64;   // rows per tile
+  static constexpr int BNC = TG == 0 ? 64 : 32;   // complex columns per tile
+  static constexpr int BN = 2 * BNC;              // real columns per tile
+  static constexpr int NT = TG == 0 ? 512 : 256;  // threads per block
+  static constexpr int WN = BN / 4;               // real columns per wave (4 waves across)
+  static constexpr int NBJ = WN / 16;             // 16-column MFMA blocks per wave
+};
+constexpr int kNumGeo = 2;
+constexpr int BM = Geo<0>::BM, BN = Geo<0>::BN, BNC = Geo<0>::BNC, NT = Geo<0>::NT;  // the default tile
 
 enum Kind { K_B_FWD = 0, K_B_INV = 1, K_C_FWD = 2, K_C_INV = 3, K_DEBUG = 4 };
 
@@ -63,14 +77,15 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));  // 16-byte operand
 
 // Contraction chunk per precision: 32 for the bf16-split and FP32 forms (two
 // blocks of 60 KB LDS fit a CU), 64 for FP64.  The packed tables pad K to it.
-template <int PREC> struct Cfg {
+template <int PREC, int TG = 0> struct Cfg {
   static constexpr int BK = PREC == PREC_F64 ? 64 : 32;
   static constexpr int PS = BK;      // bf16 LDS row (elements): unpadded, 16-byte slots swizzled (swz)
   static constexpr int PF = BK + 4;  // f32/f64 LDS pitch (elements)
   static constexpr int XN = BK / 8;  // k per thread in the data-operand staging (8 k groups)
   // 16-byte table vectors per row and per thread
   static constexpr int VR = PREC == PREC_SPLIT ? BK / 8 : (PREC == PREC_F32 ? BK / 4 : BK / 2);
-  static constexpr int NA = (PREC == PREC_SPLIT ? 3 : 1) * BM * VR / NT;
+  static constexpr int NA = (PREC == PREC_SPLIT ? 3 : 1) * Geo<TG>::BM * VR / Geo<TG>::NT;
+  static_assert(NA * Geo<TG>::NT == (PREC == PREC_SPLIT ? 3 : 1) * Geo<TG>::BM * VR, "whole table vectors per thread");
   // register stages of the operand pipeline (loads run 1 or 2 chunks ahead):
   // one keeps the split form within 128 registers (4 waves per SIMD) and FP64
   // free of spills; FP32 has room for two
@@ -80,13 +95,13 @@ template <int PREC> struct Cfg {
   // Data-operand LDS rows per plane: the split form keeps real and imaginary
   // parts in two halves 8 rows apart; FP32 and FP64 interleave them.
   static constexpr int XPAD = PREC == PREC_SPLIT ? 4 : 0;
-  static constexpr int XROWS = 2 * BNC + XPAD;
+  static constexpr int XROWS = 2 * Geo<TG>::BNC + XPAD;
 };
 
 // LDS row of real column (complex column cc, part re 0 / im 1) of the data operand
-template <int PREC>
+template <int PREC, int TG>
 __device__ inline int xrow(int cc, int part) {
-  return PREC == PREC_SPLIT ? part * (BNC + Cfg<PREC>::XPAD) + cc : 2 * cc + part;
+  return PREC == PREC_SPLIT ? part * (Geo<TG>::BNC + Cfg<PREC, TG>::XPAD) + cc : 2 * cc + part;
 }
 
 // Split-form LDS rows are 64 bytes (32 bf16) of four 16-byte slots; slot g of
@@ -100,17 +115,22 @@ __device__ inline int xrow(int cc, int part) {
 // cost 4 extra cycles per operand read.
 __device__ inline int swz(int r, int g) { return g ^ ((r >> 1) & 3); }
 
-// Thread -> (complex column cc, k group kg) of the data-operand staging.  In
-// the split form 32 lanes cover 16 columns x 2 k groups.
-template <int PREC>
+// Thread -> (complex column cc, k group kg of 8) of the data-operand staging.
+// In the split form 32 lanes cover 16 columns x 2 k groups.
+template <int PREC, int TG>
 __device__ inline void x_thread(int tid, int& cc, int& kg) {
   if constexpr (PREC == PREC_SPLIT) {
     const int lane = tid & 63, wave = tid >> 6;
-    cc = (lane & 15) | ((lane >> 5) << 4) | ((wave & 1) << 5);
-    kg = ((wave >> 1) << 1) | ((lane >> 4) & 1);
+    if constexpr (TG == 0) {
+      cc = (lane & 15) | ((lane >> 5) << 4) | ((wave & 1) << 5);
+      kg = ((wave >> 1) << 1) | ((lane >> 4) & 1);
+    } else {
+      cc = (lane & 15) | ((lane >> 5) << 4);
+      kg = (wave << 1) | ((lane >> 4) & 1);
+    }
   } else {
-    cc = tid & 63;
-    kg = tid >> 6;
+    cc = tid & (Geo<TG>::BNC - 1);
+    kg = tid / Geo<TG>::BNC;
   }
 }
 
@@ -126,14 +146,14 @@ __device__ inline uint16_t f2bf(float f) {
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
-template <int PREC> struct Lds {
-  static constexpr int a = BM * Cfg<PREC>::PF * (int)sizeof(typename DT<PREC>::t);
-  static constexpr int x = Cfg<PREC>::XROWS * Cfg<PREC>::PF * (int)sizeof(typename DT<PREC>::t);
+template <int PREC, int TG = 0> struct Lds {
+  static constexpr int a = Geo<TG>::BM * Cfg<PREC, TG>::PF * (int)sizeof(typename DT<PREC>::t);
+  static constexpr int x = Cfg<PREC, TG>::XROWS * Cfg<PREC, TG>::PF * (int)sizeof(typename DT<PREC>::t);
   static constexpr int total = a + x;
 };
-template <> struct Lds<PREC_SPLIT> {
-  static constexpr int a = 3 * BM * Cfg<PREC_SPLIT>::PS * 2;
-  static constexpr int x = 3 * Cfg<PREC_SPLIT>::XROWS * Cfg<PREC_SPLIT>::PS * 2;
+template <int TG> struct Lds<PREC_SPLIT, TG> {
+  static constexpr int a = 3 * Geo<TG>::BM * Cfg<PREC_SPLIT, TG>::PS * 2;
+  static constexpr int x = 3 * Cfg<PREC_SPLIT, TG>::XROWS * Cfg<PREC_SPLIT, TG>::PS * 2;
   static constexpr int total = a + x;
 };
 
@@ -166,8 +186,9 @@ __device__ inline T load_uniform(const T* p) {
 #endif
 }
 
-template <int PREC, int KIND>
+template <int PREC, int KIND, int TG>
 __device__ inline Tile make_tile(const ClassDesc* cls, const int4* work, int w, const DebugArgs& dbg) {
+  constexpr int BM = Geo<TG>::BM, BN = Geo<TG>::BN, BNC = Geo<TG>::BNC;
   using T = typename DT<PREC>::t;
   Tile t;
   if constexpr (KIND == K_DEBUG) {
@@ -211,17 +232,18 @@ __device__ inline Tile make_tile(const ClassDesc* cls, const int4* work, int w, 
 
 // ---- per-thread register staging of one K chunk -----------------------------
 // A: NA 16-byte table vectors; X: XN consecutive k of one complex column.
-template <int PREC> struct Stage {
-  static constexpr int NA = Cfg<PREC>::NA;
+template <int PREC, int TG> struct Stage {
+  static constexpr int NA = Cfg<PREC, TG>::NA;
   u4 a[NA];
-  typename DT<PREC>::t xr[Cfg<PREC>::XN], xi[Cfg<PREC>::XN];
+  typename DT<PREC>::t xr[Cfg<PREC, TG>::XN], xi[Cfg<PREC, TG>::XN];
 };
 
 // A chunk: BM rows x BK from a packed table block.  Rows past the block are
 // clamped to its last row: they feed only output rows that are never stored.
-template <int PREC>
-__device__ inline void load_a(Stage<PREC>& st, const Tile& t, int k0, int tid) {
-  using C = Cfg<PREC>;
+template <int PREC, int TG>
+__device__ inline void load_a(Stage<PREC, TG>& st, const Tile& t, int k0, int tid) {
+  using C = Cfg<PREC, TG>;
+  constexpr int BM = Geo<TG>::BM, NT = Geo<TG>::NT;
   const int rmax = t.M - 1;
   constexpr int EV = PREC == PREC_SPLIT ? 8 : (PREC == PREC_F32 ? 4 : 2);  // elements per vector
   constexpr int ES = PREC == PREC_SPLIT ? 2 : (PREC == PREC_F32 ? 4 : 8);  // element bytes
@@ -238,9 +260,10 @@ __device__ inline void load_a(Stage<PREC>& st, const Tile& t, int k0, int tid) {
   }
 }
 
-template <int PREC>
-__device__ inline void store_a(const Stage<PREC>& st, unsigned char* sm, int tid) {
-  using C = Cfg<PREC>;
+template <int PREC, int TG>
+__device__ inline void store_a(const Stage<PREC, TG>& st, unsigned char* sm, int tid) {
+  using C = Cfg<PREC, TG>;
+  constexpr int BM = Geo<TG>::BM, NT = Geo<TG>::NT;
   constexpr int EV = PREC == PREC_SPLIT ? 8 : (PREC == PREC_F32 ? 4 : 2);
   constexpr int ES = PREC == PREC_SPLIT ? 2 : (PREC == PREC_F32 ? 4 : 8);
   constexpr int P = PREC == PREC_SPLIT ? C::PS : C::PF;
@@ -322,14 +345,14 @@ template <> struct V2<double> { using t = double2; };
 // X chunk: thread -> (complex column cc, k group kg of XN rows), see x_thread.
 // rows).  Columns and rows past the group are clamped to its last ones: the
 // packed tables are zero past K, and extra columns are never stored.
-template <int PREC, int KIND>
-__device__ inline void load_x(Stage<PREC>& st, const Tile& t, const XCol<typename DT<PREC>::t>& xc,
+template <int PREC, int KIND, int TG>
+__device__ inline void load_x(Stage<PREC, TG>& st, const Tile& t, const XCol<typename DT<PREC>::t>& xc,
                               const DebugArgs& dbg, int k0, int tid) {
   using T = typename DT<PREC>::t;
   using T2 = typename V2<T>::t;
-  constexpr int XN = Cfg<PREC>::XN;
+  constexpr int XN = Cfg<PREC, TG>::XN;
   int cc, kg;
-  x_thread<PREC>(tid, cc, kg);
+  x_thread<PREC, TG>(tid, cc, kg);
   const int kb = k0 + kg * XN;
   if constexpr (KIND == K_DEBUG) {
     const int c = t.col0 + cc;
@@ -389,15 +412,15 @@ __device__ inline void split3(float v, uint32_t& h0, uint32_t& h1, uint32_t& h2)
 __device__ inline uint32_t pack_hi(uint32_t lo, uint32_t hi) { return __builtin_amdgcn_perm(hi, lo, 0x07060302u); }
 
 // X chunk to LDS as [column][k]; sgn carries the (-1)^m of the -m segment.
-template <int PREC>
-__device__ inline void store_x(const Stage<PREC>& st, typename DT<PREC>::t sgn, unsigned char* sm, int tid) {
-  using C = Cfg<PREC>;
+template <int PREC, int TG>
+__device__ inline void store_x(const Stage<PREC, TG>& st, typename DT<PREC>::t sgn, unsigned char* sm, int tid) {
+  using C = Cfg<PREC, TG>;
   constexpr int XN = C::XN;
   int cc, kg;
-  x_thread<PREC>(tid, cc, kg);
+  x_thread<PREC, TG>(tid, cc, kg);
   if constexpr (PREC == PREC_SPLIT) {
     static_assert(XN == 4, "split staging holds 4 k per thread");
-    uint16_t* Xs = reinterpret_cast<uint16_t*>(sm + Lds<PREC>::a);
+    uint16_t* Xs = reinterpret_cast<uint16_t*>(sm + Lds<PREC, TG>::a);
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
       uint32_t h[3][XN];
@@ -408,21 +431,21 @@ __device__ inline void store_x(const Stage<PREC>& st, typename DT<PREC>::t sgn, 
         uint2 w;
         w.x = pack_hi(h[p][0], h[p][1]);
         w.y = pack_hi(h[p][2], h[p][3]);
-        const int row = xrow<PREC>(cc, part);
+        const int row = xrow<PREC, TG>(cc, part);
         *reinterpret_cast<uint2*>(&Xs[(p * C::XROWS + row) * C::PS + swz(row, kg >> 1) * 8 + (kg & 1) * 4]) = w;
       }
     }
   } else if constexpr (PREC == PREC_F32) {
     static_assert(XN == 4, "f32 staging holds 4 k per thread");
-    float* Xs = reinterpret_cast<float*>(sm + Lds<PREC>::a);
-    *reinterpret_cast<float4*>(&Xs[xrow<PREC>(cc, 0) * C::PF + kg * XN]) =
+    float* Xs = reinterpret_cast<float*>(sm + Lds<PREC, TG>::a);
+    *reinterpret_cast<float4*>(&Xs[xrow<PREC, TG>(cc, 0) * C::PF + kg * XN]) =
         make_float4(sgn * st.xr[0], sgn * st.xr[1], sgn * st.xr[2], sgn * st.xr[3]);
-    *reinterpret_cast<float4*>(&Xs[xrow<PREC>(cc, 1) * C::PF + kg * XN]) =
+    *reinterpret_cast<float4*>(&Xs[xrow<PREC, TG>(cc, 1) * C::PF + kg * XN]) =
         make_float4(sgn * st.xi[0], sgn * st.xi[1], sgn * st.xi[2], sgn * st.xi[3]);
   } else {
-    double* Xs = reinterpret_cast<double*>(sm + Lds<PREC>::a);
-    double* r0 = &Xs[xrow<PREC>(cc, 0) * C::PF + kg * XN];
-    double* r1 = &Xs[xrow<PREC>(cc, 1) * C::PF + kg * XN];
+    double* Xs = reinterpret_cast<double*>(sm + Lds<PREC, TG>::a);
+    double* r0 = &Xs[xrow<PREC, TG>(cc, 0) * C::PF + kg * XN];
+    double* r1 = &Xs[xrow<PREC, TG>(cc, 1) * C::PF + kg * XN];
 #pragma unroll
     for (int u = 0; u < XN; u += 2) {
       *reinterpret_cast<double2*>(r0 + u) = make_double2(sgn * st.xr[u], sgn * st.xr[u + 1]);
@@ -446,17 +469,20 @@ __device__ inline typename DT<PREC>::t* x_base(const Tile& t, const void* cin) {
 // first chunks of the block's next item are already being loaded (split and
 // FP32 forms), so the load latency of short contractions overlaps the stores.  Outputs go straight
 // from the accumulators to the next stage's layout.
-template <int PREC, int KIND>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PREC>::WAVES))) k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work,
-                                             int nwork, const void* __restrict__ cin, void* __restrict__ cout,
-                                             DebugArgs dbg) {
+template <int PREC, int KIND, int TG>
+__global__ void __launch_bounds__(Geo<TG>::NT) __attribute__((amdgpu_waves_per_eu(Cfg<PREC>::WAVES)))
+k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork, const void* __restrict__ cin,
+       void* __restrict__ cout, DebugArgs dbg) {
   using T = typename DT<PREC>::t;
   using AccT = typename Acc<PREC>::t;
-  constexpr int BK = Cfg<PREC>::BK, PS = Cfg<PREC>::PS, PF = Cfg<PREC>::PF;
-  __shared__ __align__(16) unsigned char sm[Lds<PREC>::total];
+  using G = Geo<TG>;
+  constexpr int BM = G::BM, BN = G::BN, NT = G::NT, NBJ = G::NBJ;
+  constexpr int BK = Cfg<PREC, TG>::BK, PS = Cfg<PREC, TG>::PS, PF = Cfg<PREC, TG>::PF;
+  __shared__ __align__(16) unsigned char sm[Lds<PREC, TG>::total];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave >> 2) * 64, wc = (wave & 3) * 32;
+  // wave tile: 64 rows x WN real columns (TG 0: waves 2 x 4, TG 1: 1 x 4)
+  const int wr = (wave >> 2) * 64, wc = (wave & 3) * G::WN;
   const int lr = lane & 15, lk = lane >> 4;
 
   const int nitems = KIND == K_DEBUG ? ((dbg.M + BM - 1) / BM) * ((dbg.N + BN - 1) / BN) : nwork;
@@ -467,21 +493,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
     XCol<T> x{nullptr, 0, 0, (T)1};
     if constexpr (KIND != K_DEBUG) {
       int cc, kg;
-      x_thread<PREC>(tid, cc, kg);
+      x_thread<PREC, TG>(tid, cc, kg);
       x = x_col<KIND>(tt, min(tt.col0 + cc, tt.Ncc - 1), x_base<PREC, KIND>(tt, cin));
     }
     return x;
   };
-  auto fetch = [&](Stage<PREC>& st, const Tile& tt, const XCol<T>& x, int k0) {
-    if constexpr (KIND != K_DEBUG) load_a<PREC>(st, tt, k0, tid);
-    load_x<PREC, KIND>(st, tt, x, dbg, k0, tid);
+  auto fetch = [&](Stage<PREC, TG>& st, const Tile& tt, const XCol<T>& x, int k0) {
+    if constexpr (KIND != K_DEBUG) load_a<PREC, TG>(st, tt, k0, tid);
+    load_x<PREC, KIND, TG>(st, tt, x, dbg, k0, tid);
   };
 
-  Tile t = make_tile<PREC, KIND>(cls, work, w, dbg);
+  Tile t = make_tile<PREC, KIND, TG>(cls, work, w, dbg);
   XCol<T> xc = column(t);
-  Stage<PREC> s0, s1;
+  Stage<PREC, TG> s0, s1;
   if constexpr (KIND == K_DEBUG) {
-    for (int v = 0; v < Stage<PREC>::NA; ++v) s0.a[v] = s1.a[v] = u4{0, 0, 0, 0};
+    for (int v = 0; v < Stage<PREC, TG>::NA; ++v) s0.a[v] = s1.a[v] = u4{0, 0, 0, 0};
   }
   // FP64 stages are too large to stay live across the epilogue: its items load
   // their first chunks at their start.
@@ -500,11 +526,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
       fetch(s0, t, xc, 0);
       if (NS == 2 && BK < t.K) fetch(s1, t, xc, BK);
     }
-    AccT acc[4][2], acc2[4][2];
+    AccT acc[4][NBJ], acc2[4][NBJ];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < NBJ; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           acc[a][b][v] = 0;
@@ -516,11 +542,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
       const int rleft = t.M - (t.row0 + wr);
       nbi = rleft <= 0 ? 0 : (rleft >= 64 ? 4 : (rleft + 15) / 16);
       const int cleft = 2 * t.Ncc - (2 * t.col0 + wc);
-      nbj = cleft <= 0 ? 0 : (cleft >= 32 ? 2 : (cleft + 15) / 16);
+      nbj = cleft <= 0 ? 0 : (cleft >= 16 * NBJ ? NBJ : (cleft + 15) / 16);
     }
 
     // stage one chunk into LDS: A (table or debug matrix) and X
-    auto to_lds = [&](const Stage<PREC>& st, int k0) {
+    auto to_lds = [&](const Stage<PREC, TG>& st, int k0) {
       if constexpr (KIND == K_DEBUG) {
         for (int e = tid; e < BM * BK; e += NT) {
           const int r = e / BK, k = e - r * BK;
@@ -540,26 +566,27 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
           }
         }
       } else {
-        store_a<PREC>(st, sm, tid);
+        store_a<PREC, TG>(st, sm, tid);
       }
-      store_x<PREC>(st, xc.sgn, sm, tid);
+      store_x<PREC, TG>(st, xc.sgn, sm, tid);
     };
     // MFMAs of the chunk in LDS; k sub-steps wholly beyond K are skipped
     auto compute = [&](int k0) {
       const int kend = t.K - k0 < BK ? t.K - k0 : BK;
       if constexpr (PREC == PREC_SPLIT) {
         const uint16_t* As = reinterpret_cast<const uint16_t*>(sm);
-        const uint16_t* Xs = reinterpret_cast<const uint16_t*>(sm + Lds<PREC>::a);
+        const uint16_t* Xs = reinterpret_cast<const uint16_t*>(sm + Lds<PREC, TG>::a);
         static_assert(BK == 32, "one 16x16x32 MFMA step per chunk: lane slot lk covers k 8lk..8lk+7");
         if (kend > 0) {
-          bf8 b[2][3];
+          bf8 b[NBJ][3];
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < NBJ; ++j)
             if (j < nbj)
 #pragma unroll
               for (int p = 0; p < 3; ++p) {
-                const int row = xrow<PREC>((wc + j * 16 + lr) >> 1, lr & 1);
-                b[j][p] = *reinterpret_cast<const bf8*>(&Xs[(p * Cfg<PREC>::XROWS + row) * PS + swz(row, lk) * 8]);
+                const int row = xrow<PREC, TG>((wc + j * 16 + lr) >> 1, lr & 1);
+                b[j][p] =
+                    *reinterpret_cast<const bf8*>(&Xs[(p * Cfg<PREC, TG>::XROWS + row) * PS + swz(row, lk) * 8]);
               }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -569,7 +596,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
             for (int p = 0; p < 3; ++p)
               a[p] = *reinterpret_cast<const bf8*>(&As[(p * BM + wr + i * 16 + lr) * PS + swz(wr + i * 16 + lr, lk) * 8]);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < NBJ; ++j) {
               if (j >= nbj) continue;
               // smallest products first, the main product last
               AccT& c2 = kCorr ? acc2[i][j] : acc[i][j];
@@ -584,19 +611,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
         }
       } else {
         const T* As = reinterpret_cast<const T*>(sm);
-        const T* Xs = reinterpret_cast<const T*>(sm + Lds<PREC>::a);
+        const T* Xs = reinterpret_cast<const T*>(sm + Lds<PREC, TG>::a);
         for (int kk = 0; kk < BK; kk += 4) {
           if (kk >= kend) break;
-          T a[4], b[2];
+          T a[4], b[NBJ];
 #pragma unroll
           for (int i = 0; i < 4; ++i) a[i] = As[(wr + i * 16 + lr) * PF + kk + lk];
 #pragma unroll
-          for (int j = 0; j < 2; ++j) b[j] = Xs[xrow<PREC>((wc + j * 16 + lr) >> 1, lr & 1) * PF + kk + lk];
+          for (int j = 0; j < NBJ; ++j) b[j] = Xs[xrow<PREC, TG>((wc + j * 16 + lr) >> 1, lr & 1) * PF + kk + lk];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (i >= nbi) continue;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < NBJ; ++j) {
               if (j >= nbj) continue;
               if constexpr (PREC == PREC_F64)
                 acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
@@ -638,7 +665,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
     Tile tn = t;
     XCol<T> xn = xc;
     if (more) {
-      tn = make_tile<PREC, KIND>(cls, work, wn, dbg);
+      tn = make_tile<PREC, KIND, TG>(cls, work, wn, dbg);
       xn = column(tn);
       if (kAhead) {
         fetch(s0, tn, xn, 0);
@@ -660,7 +687,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
     auto row_of = [&](int i, int v) { return t.row0 + wr + i * 16 + (PREC == PREC_F64 ? 4 * v + lk : 4 * lk + v); };
     if constexpr (KIND == K_DEBUG) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NBJ; ++j) {
         const int nr = 2 * t.col0 + wc + j * 16 + lr;
         if (j >= nbj || nr >= dbg.N) continue;
 #pragma unroll
@@ -674,7 +701,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
     } else if constexpr (KIND == K_C_INV) {
       T* gout = reinterpret_cast<T*>(t.C->g);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NBJ; ++j) {
         const int rc = wc + j * 16 + lr;  // real column in the tile
         const int c = t.col0 + (rc >> 1);
         if (j >= nbj) continue;
@@ -713,8 +740,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
       constexpr int DUAL = KIND ^ 1;
       T* obase = KIND == K_B_FWD ? reinterpret_cast<T*>(t.C->g)
                                  : (KIND == K_B_INV ? reinterpret_cast<T*>(t.C->F) : reinterpret_cast<T*>(cout));
+      const int keep_f = KIND == K_B_INV ? load_uniform(&t.C->keep_f) : 0;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NBJ; ++j) {
         const int rc = wc + j * 16 + lr;
         const int c = t.col0 + (rc >> 1);
         if (j >= nbj) continue;
@@ -730,9 +758,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Cfg<PRE
             if (okc && row < t.M) {
               // the spectrum rows of the inverse Legendre stage stream out (they
               // are read once, in full, by the inverse FFT)
-              if constexpr (KIND == K_B_INV)
-                __builtin_nontemporal_store(value(i, j, v), &op[2 * x_off<DUAL>(t, oc, row)]);
-              else
+              if constexpr (KIND == K_B_INV) {
+                if (keep_f)  // slab schedule: read back from the last-level cache
+                  op[2 * x_off<DUAL>(t, oc, row)] = value(i, j, v);
+                else
+                  __builtin_nontemporal_store(value(i, j, v), &op[2 * x_off<DUAL>(t, oc, row)]);
+              } else
                 op[2 * x_off<DUAL>(t, oc, row)] = value(i, j, v);
             }
           }
@@ -875,7 +906,7 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
   if (w >= nwork) return;
 
   auto tile = [&](int wi) {
-    Tile tt = make_tile<PREC_SPLIT, KIND>(cls, work, wi, nodbg);
+    Tile tt = make_tile<PREC_SPLIT, KIND, 0>(cls, work, wi, nodbg);
     tt.col0 = work[wi].w * LBNC;
     return tt;
   };
@@ -1024,6 +1055,7 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
       // their number is known at the next item's first wait.  The spectrum
       // rows stream out (read once by the iFFT).
       SGL_G f2v* spare = gmem(&g_spare_out[lane]);
+      const int keep_f = load_uniform(&t.C->keep_f);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -1031,7 +1063,11 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
           const int row = t.row0 + wr + i * 16 + 4 * lk + v;
           const bool ok = okc && i < nbi && row < t.M;
           SGL_G f2v* q = ok ? reinterpret_cast<SGL_G f2v*>(oc.p + 2 * x_off<DUAL>(t, oc, min(row, t.M - 1))) : spare;
-          __builtin_nontemporal_store(f2v{sg * acc[i][0][v], sg * acc[i][1][v]}, q);
+          const f2v o = f2v{sg * acc[i][0][v], sg * acc[i][1][v]};
+          if (keep_f)
+            *q = o;  // slab schedule: read back from the last-level cache
+          else
+            __builtin_nontemporal_store(o, q);
         }
       }
     } else if (okc) {
@@ -1065,12 +1101,33 @@ inline int grid_for(int nwork, int max_grid) {
   return nwork < g ? nwork : g;
 }
 
-template <int PREC>
-hipError_t launch_kind(int kind, const ClassDesc* d_cls, const int4* d_work, int nwork, const void* cin, void* cout,
-                       int max_grid, hipStream_t s) {
-  if (nwork == 0) return hipSuccess;
+template <int PREC, int TG>
+hipError_t launch_gemm(int kind, const ClassDesc* d_cls, const int4* d_work, int nwork, const void* cin, void* cout,
+                       dim3 grid, hipStream_t s) {
   DebugArgs dbg{0, 0, 0, nullptr, nullptr, nullptr};
-  dim3 grid(grid_for(nwork, max_grid)), block(NT);
+  const dim3 block(Geo<TG>::NT);
+  switch (kind) {
+    case K_B_FWD:
+      hipLaunchKernelGGL((k_gemm<PREC, K_B_FWD, TG>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
+      break;
+    case K_B_INV:
+      hipLaunchKernelGGL((k_gemm<PREC, K_B_INV, TG>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
+      break;
+    case K_C_FWD:
+      hipLaunchKernelGGL((k_gemm<PREC, K_C_FWD, TG>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gemm<PREC, K_C_INV, TG>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_kind(int kind, int tg, const ClassDesc* d_cls, const int4* d_work, int nwork, const void* cin,
+                       void* cout, int max_grid, hipStream_t s) {
+  if (nwork == 0) return hipSuccess;
+  dim3 grid(grid_for(nwork, max_grid));
   if constexpr (PREC == PREC_SPLIT) {
     if (kind == K_B_FWD) {
       hipLaunchKernelGGL((k_legendre_split<K_B_FWD>), grid, dim3(LT), 0, s, d_cls, d_work, nwork);
@@ -1081,47 +1138,38 @@ hipError_t launch_kind(int kind, const ClassDesc* d_cls, const int4* d_work, int
       return hipGetLastError();
     }
   }
-  switch (kind) {
-    case K_B_FWD:
-      hipLaunchKernelGGL((k_gemm<PREC, K_B_FWD>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
-      break;
-    case K_B_INV:
-      hipLaunchKernelGGL((k_gemm<PREC, K_B_INV>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
-      break;
-    case K_C_FWD:
-      hipLaunchKernelGGL((k_gemm<PREC, K_C_FWD>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
-      break;
-    default:
-      hipLaunchKernelGGL((k_gemm<PREC, K_C_INV>), grid, block, 0, s, d_cls, d_work, nwork, cin, cout, dbg);
-      break;
-  }
-  return hipGetLastError();
+  return tg == 0 ? launch_gemm<PREC, 0>(kind, d_cls, d_work, nwork, cin, cout, grid, s)
+                 : launch_gemm<PREC, 1>(kind, d_cls, d_work, nwork, cin, cout, grid, s);
 }
 
-hipError_t launch_any(int prec, int kind, const ClassDesc* d_cls, const int4* d_work, int nwork, const void* cin,
-                      void* cout, int max_grid, hipStream_t s) {
-  if (prec == PREC_F64) return launch_kind<PREC_F64>(kind, d_cls, d_work, nwork, cin, cout, max_grid, s);
-  if (prec == PREC_F32) return launch_kind<PREC_F32>(kind, d_cls, d_work, nwork, cin, cout, max_grid, s);
-  return launch_kind<PREC_SPLIT>(kind, d_cls, d_work, nwork, cin, cout, max_grid, s);
+hipError_t launch_any(int prec, int kind, int tg, const ClassDesc* d_cls, const int4* d_work, int nwork,
+                      const void* cin, void* cout, int max_grid, hipStream_t s) {
+  if (prec == PREC_F64) return launch_kind<PREC_F64>(kind, tg, d_cls, d_work, nwork, cin, cout, max_grid, s);
+  if (prec == PREC_F32) return launch_kind<PREC_F32>(kind, tg, d_cls, d_work, nwork, cin, cout, max_grid, s);
+  return launch_kind<PREC_SPLIT>(kind, tg, d_cls, d_work, nwork, cin, cout, max_grid, s);
 }
 
 }  // namespace
 
-int gemm_tile_m() { return BM; }
-int gemm_tile_n_complex() { return BNC; }
-int gemm_tile_n_complex_legendre(int prec, bool /*inverse*/) { return prec == PREC_SPLIT ? LBNC : BNC; }
+int gemm_num_geometries() { return kNumGeo; }
+int gemm_tile_m(int tg) { return tg == 0 ? Geo<0>::BM : Geo<1>::BM; }
+int gemm_tile_n_complex(int tg) { return tg == 0 ? Geo<0>::BNC : Geo<1>::BNC; }
+bool gemm_legendre_has_geometries(int prec) { return prec != PREC_SPLIT; }
+int gemm_tile_n_complex_legendre(int prec, int tg) { return prec == PREC_SPLIT ? LBNC : gemm_tile_n_complex(tg); }
+int gemm_tile_m_legendre(int prec, int tg) { return prec == PREC_SPLIT ? BM : gemm_tile_m(tg); }
 int gemm_k_chunk(int prec) {
   return prec == PREC_F64 ? Cfg<PREC_F64>::BK : (prec == PREC_F32 ? Cfg<PREC_F32>::BK : Cfg<PREC_SPLIT>::BK);
 }
 
-hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
+hipError_t launch_legendre(int prec, bool inverse, int tg, const ClassDesc* d_cls, const int4* d_work, int nwork,
                            int max_grid, hipStream_t s) {
-  return launch_any(prec, inverse ? K_B_INV : K_B_FWD, d_cls, d_work, nwork, nullptr, nullptr, max_grid, s);
+  return launch_any(prec, inverse ? K_B_INV : K_B_FWD, tg, d_cls, d_work, nwork, nullptr, nullptr, max_grid, s);
 }
 
-hipError_t launch_radial(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
+hipError_t launch_radial(int prec, bool inverse, int tg, const ClassDesc* d_cls, const int4* d_work, int nwork,
                          const void* coeffs_in, void* coeffs_out, int max_grid, hipStream_t s) {
-  return launch_any(prec, inverse ? K_C_INV : K_C_FWD, d_cls, d_work, nwork, coeffs_in, coeffs_out, max_grid, s);
+  return launch_any(prec, inverse ? K_C_INV : K_C_FWD, tg, d_cls, d_work, nwork, coeffs_in, coeffs_out, max_grid,
+                    s);
 }
 
 hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, const double* X, double* C,
@@ -1131,11 +1179,11 @@ hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, con
   if (tiles == 0) return hipSuccess;
   dim3 grid(grid_for(tiles, 0)), block(NT);
   if (prec == PREC_F64)
-    hipLaunchKernelGGL((k_gemm<PREC_F64, K_DEBUG>), grid, block, 0, s, nullptr, nullptr, 0, nullptr, nullptr, dbg);
+    hipLaunchKernelGGL((k_gemm<PREC_F64, K_DEBUG, 0>), grid, block, 0, s, nullptr, nullptr, 0, nullptr, nullptr, dbg);
   else if (prec == PREC_F32)
-    hipLaunchKernelGGL((k_gemm<PREC_F32, K_DEBUG>), grid, block, 0, s, nullptr, nullptr, 0, nullptr, nullptr, dbg);
+    hipLaunchKernelGGL((k_gemm<PREC_F32, K_DEBUG, 0>), grid, block, 0, s, nullptr, nullptr, 0, nullptr, nullptr, dbg);
   else
-    hipLaunchKernelGGL((k_gemm<PREC_SPLIT, K_DEBUG>), grid, block, 0, s, nullptr, nullptr, 0, nullptr, nullptr,
+    hipLaunchKernelGGL((k_gemm<PREC_SPLIT, K_DEBUG, 0>), grid, block, 0, s, nullptr, nullptr, 0, nullptr, nullptr,
                        dbg);
   return hipGetLastError();
 }

@@ -16,6 +16,13 @@ namespace sgl {
 // ---------------------------------------------------------------------------
 void set_error(const std::string& msg);
 
+// Every device allocation the library makes goes through dev_malloc.  For the
+// tests of all-or-nothing plan creation, the environment variable
+// SGL_TEST_FAIL_ALLOC=k (read when a plan creation starts) makes the k-th
+// device allocation of that creation fail as hipMalloc does when memory runs
+// out (no device call is made for it); unset or 0, nothing is injected.
+hipError_t dev_malloc(void** p, size_t bytes);
+
 #define SGL_HIP_TRY(expr)                                                          \
   do {                                                                             \
     hipError_t e_ = (expr);                                                        \
@@ -117,6 +124,10 @@ struct ClassDesc {
   // (seminaive step: cosine-domain sums over k < B, Sect. 3.3.1)
   int kb;
   const void* dct;  // DCT constants of the seminaive step (dct_const_count(B) complex), else null
+  // 1 in the descriptors of the slab schedule: the spectrum F is stored with the
+  // default cache policy (read back from the last-level cache by the next
+  // launch), 0: streaming stores (F passes through HBM)
+  int keep_f;
 };
 // naive / midpoint forward items group this many consecutive degrees n
 constexpr int kNaiveGroup = 8;
@@ -172,9 +183,13 @@ inline int fft_pow2_rpb(int L, int threads) {
   while (r1 * r1 < L) r1 <<= 1;  // R1 = sqrt(L) or sqrt(2L)
   return threads / r1;
 }
-hipError_t launch_legendre(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
+// Stage (b) / (c) launches; tg selects the tile geometry of the register-staged
+// GEMM (0: 128 rows x 64 complex columns, 1: 64 x 32; see gemm_tile_m), ignored
+// by the split-form Legendre kernel.  The work list must have been built for
+// the same geometry.
+hipError_t launch_legendre(int prec, bool inverse, int tg, const ClassDesc* d_cls, const int4* d_work, int nwork,
                            int max_grid, hipStream_t s);
-hipError_t launch_radial(int prec, bool inverse, const ClassDesc* d_cls, const int4* d_work, int nwork,
+hipError_t launch_radial(int prec, bool inverse, int tg, const ClassDesc* d_cls, const int4* d_work, int nwork,
                          const void* coeffs_in, void* coeffs_out, int max_grid, hipStream_t s);
 // Naive transforms (Alg. 1, Alg. 2) of every function of an FP64 plan; d_pre
 // holds the per-class prefix of work items (ncls + 1 entries).
@@ -192,9 +207,12 @@ hipError_t launch_synthesize_points(const ClassDesc* d_cls, const int64_t* d_pre
                                     const void* coeffs, int npts, const double* xyz, void* values, hipStream_t s);
 hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, const double* X, double* C,
                              hipStream_t s);
-int gemm_tile_m();
-int gemm_tile_n_complex();
-int gemm_tile_n_complex_legendre(int prec, bool inverse);  // column tile of the stage (b) work items
+int gemm_num_geometries();                         // tile geometries of the register-staged GEMM
+int gemm_tile_m(int tg);                           // rows per tile of geometry tg
+int gemm_tile_n_complex(int tg);                   // complex columns per tile of geometry tg
+bool gemm_legendre_has_geometries(int prec);       // false: the split-form Legendre kernel has one tile
+int gemm_tile_m_legendre(int prec, int tg);        // tile of the stage (b) work items
+int gemm_tile_n_complex_legendre(int prec, int tg);
 int gemm_k_chunk(int prec);  // contraction chunk (table K padding) of a precision
 
 // Plan-time FP64 kernels (sgl_tables.hip)

@@ -3,8 +3,10 @@
 // inverse entry points.  See include/sgl.h for the contract.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <numeric>
 #include <memory>
 #include <string>
 #include <vector>
@@ -15,6 +17,16 @@ namespace sgl {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+// allocations left before the injected failure of the current plan creation (0 = none)
+static thread_local long g_fail_countdown = 0;
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (g_fail_countdown > 0 && --g_fail_countdown == 0) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
 
 namespace {
 
@@ -73,17 +85,38 @@ struct sgl_plan_s {
   std::vector<ClassHost> classes;
   std::vector<void*> allocs;
   ClassDesc* d_cls = nullptr;
+  ClassDesc* d_cls_keep = nullptr;  // the same descriptors with keep_f = 1 (slab schedule)
   int4* d_work = nullptr;
   int64_t* d_naive_pre = nullptr;  // [forward prefix][inverse prefix][function-count prefix], ncls + 1 each
   int64_t n_naive_f = 0, n_naive_i = 0;
-  int off_a = 0, n_a = 0, off_bf = 0, n_bf = 0, off_bi = 0, n_bi = 0, off_cf = 0, n_cf = 0, off_ci = 0, n_ci = 0;
+  // stage (b)/(c) work lists per GEMM tile geometry (index tg): Legendre forward /
+  // inverse, radial forward / inverse
+  int off_bf[2] = {0, 0}, n_bf[2] = {0, 0}, off_bi[2] = {0, 0}, n_bi[2] = {0, 0};
+  int off_cf[2] = {0, 0}, n_cf[2] = {0, 0}, off_ci[2] = {0, 0}, n_ci[2] = {0, 0};
   // seminaive Legendre step: DCT work items {class, m + B - 1, column tile, columns per tile}
   int off_dct = 0, n_dct = 0, dct_cols = 16, dct_lds = 0;
   bool seminaive() const { return (flags & SGL_SEMINAIVE) != 0; }
   // stage (a) work by FFT mode (see fft_mode): offsets, counts, LDS bytes
   int off_am[3] = {0, 0, 0}, n_am[3] = {0, 0, 0}, lds_am[3] = {0, 0, 0};
-  // persistent grid bound per launch slot (0 = kernel default; set by the autotuner)
+  // persistent grid bound per launch slot (0 = kernel default) and GEMM tile
+  // geometry per launch slot (0 = the default tile); both set by the autotuner
   int grid[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int tile[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // Slab schedule: the (function, radius) columns of every class split into
+  // slabs whose spectrum fits the last-level cache; stage (a) and stage (b) run
+  // slab by slab (forward: FFT then Legendre; inverse: Legendre then FFT), each
+  // slab's spectrum read back while still cached.  Every class has at least one
+  // slab (a class whose rings or tiles do not align has one slab of all its
+  // columns).  Work sub-lists per slab: FFT by mode, Legendre per direction and
+  // tile geometry.
+  struct Slab {
+    int cls, col0, col1;
+    int off_am[3], n_am[3];
+    int off_bf[2], n_bf[2], off_bi[2], n_bi[2];
+  };
+  std::vector<Slab> slabs;
+  int slab_max_cols = 0;   // widest slab (columns), 0 if no class splits
+  bool use_slabs = false;  // the schedule in use
   // captured launch sequences, keyed by (direction, input, output)
   struct GraphEntry {
     int dir;
@@ -114,7 +147,7 @@ struct sgl_plan_s {
   sgl_status_t alloc(void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = dev_malloc(p, bytes);
     if (e != hipSuccess) {
       *p = nullptr;
       set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
@@ -263,9 +296,29 @@ sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t /*s*/) {
   return SGL_OK;
 }
 
+// Largest spectrum slab of the slab schedule: the last-level (Infinity) cache
+// of MI355X holds 256 MB; a slab leaves room for the stage (b) output and the
+// tables that pass through it at the same time.
+constexpr size_t kSlabBytes = size_t(160) << 20;
+
+// Slab width (columns of the (function, radius) axis) of a class: the widest
+// multiple of the alignment unit (rings per FFT block, the stage (b) column
+// tiles of every geometry) whose spectrum fits kSlabBytes; 0 = not split.
+int slab_width(const sgl_plan_s* p, const ClassHost& c) {
+  if (p->seminaive()) return 0;  // its DCT pass runs over whole orders
+  const int prec = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
+  const int B = c.B, L = 2 * B, ncol = (int)c.funcs.size() * L;
+  int unit = c.rpb;
+  for (int tg = 0; tg < (gemm_legendre_has_geometries(prec) ? gemm_num_geometries() : 1); ++tg)
+    unit = std::lcm(unit, gemm_tile_n_complex_legendre(prec, tg));
+  if (L % unit != 0) return 0;  // a ring block or column tile would straddle two slabs
+  const size_t fcol = (size_t)(2 * B - 1) * L * p->esz();
+  const int W = (int)(kSlabBytes / fcol) / unit * unit;
+  return (W == 0 || W >= ncol) ? 0 : W;
+}
+
 sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
-  const int BM = gemm_tile_m(), BNC = gemm_tile_n_complex();
-  std::vector<int4> wam[3], wbf, wbi, wcf, wci, wdct;
+  std::vector<int4> wam[3], wdct;
   if (p->seminaive()) {
     // columns per DCT block: 16 unless the 4B-point FP64 column buffers of
     // B = 256 need the room of 8
@@ -274,7 +327,14 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
       if (dct_lds_bytes(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.B, 16) > 160 * 1024) p->dct_cols = 8;
   }
   struct Item { int cost; int4 w; };
-  std::vector<Item> bf, bi, cf, ci;
+  const int precb = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
+  const int ngeo = gemm_num_geometries();
+  std::vector<Item> bf[2], bi[2], cf[2], ci[2];
+  // slab schedule sub-lists, per slab
+  struct SlabItems { std::vector<int4> am[3]; std::vector<Item> bf[2], bi[2]; };
+  std::vector<SlabItems> sl;
+  p->slabs.clear();
+  p->slab_max_cols = 0;
   int ldsm[3] = {0, 0, 0};
   for (int ci_ = 0; ci_ < (int)p->classes.size(); ++ci_) {
     const ClassHost& c = p->classes[ci_];
@@ -282,35 +342,63 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
     const int ncol = nf * L;
     const int ncb = (ncol + c.rpb - 1) / c.rpb;
     const int mode = fft_mode(L);
+    const int W = slab_width(p, c);
+    const int s0 = (int)p->slabs.size(), ns = W ? (ncol + W - 1) / W : 1;
+    for (int q = 0; q < ns; ++q) {
+      sgl_plan_s::Slab z{};
+      z.cls = ci_;
+      z.col0 = W ? q * W : 0;
+      z.col1 = W ? std::min(ncol, (q + 1) * W) : ncol;
+      p->slabs.push_back(z);
+    }
+    sl.resize(p->slabs.size());
+    p->slab_max_cols = std::max(p->slab_max_cols, W);
+    auto slab_of = [&](int col) { return s0 + (W ? col / W : 0); };  // col: first column of an item
     for (int j = 0; j < L; ++j)
-      for (int cb = 0; cb < ncb; ++cb) wam[mode].push_back(make_int4(ci_, j, cb, c.rpb));
+      for (int cb = 0; cb < ncb; ++cb) {
+        wam[mode].push_back(make_int4(ci_, j, cb, c.rpb));
+        sl[slab_of(cb * c.rpb)].am[mode].push_back(make_int4(ci_, j, cb, c.rpb));
+      }
     ldsm[mode] = std::max(ldsm[mode], (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
     const int kb = p->seminaive() ? B : L;  // polar-side contraction length
-    const int precb = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
-    const int BNCf = gemm_tile_n_complex_legendre(precb, false), BNCi = gemm_tile_n_complex_legendre(precb, true);
-    for (int m = 0; m < B; ++m) {
-      const int rows = B - m;
-      const int ncc = (m ? 2 : 1) * nf * L;
-      const int ntf = (ncc + BNCf - 1) / BNCf, nti = (ncc + BNCi - 1) / BNCi;
-      for (int mt = 0; mt < (rows + BM - 1) / BM; ++mt)
-        for (int t = 0; t < ntf; ++t) bf.push_back({kb, make_int4(ci_, m, mt, t)});
-      for (int mt = 0; mt < (kb + BM - 1) / BM; ++mt)
-        for (int t = 0; t < nti; ++t) bi.push_back({rows, make_int4(ci_, m, mt, t)});
+    for (int tg = 0; tg < ngeo; ++tg) {
+      // stage (b): the split-form Legendre kernel has one tile (geometry 0)
+      if (tg == 0 || gemm_legendre_has_geometries(precb)) {
+        const int BMb = gemm_tile_m_legendre(precb, tg), BNb = gemm_tile_n_complex_legendre(precb, tg);
+        for (int m = 0; m < B; ++m) {
+          const int rows = B - m;
+          const int ncc = (m ? 2 : 1) * nf * L;
+          const int nt = (ncc + BNb - 1) / BNb;
+          // the slab of a column tile: its first column within its +m / -m segment
+          auto tslab = [&](int t) { return slab_of((t * BNb) % ncol); };
+          for (int mt = 0; mt < (rows + BMb - 1) / BMb; ++mt)
+            for (int t = 0; t < nt; ++t) {
+              bf[tg].push_back({kb, make_int4(ci_, m, mt, t)});
+              sl[tslab(t)].bf[tg].push_back({kb, make_int4(ci_, m, mt, t)});
+            }
+          for (int mt = 0; mt < (kb + BMb - 1) / BMb; ++mt)
+            for (int t = 0; t < nt; ++t) {
+              bi[tg].push_back({rows, make_int4(ci_, m, mt, t)});
+              sl[tslab(t)].bi[tg].push_back({rows, make_int4(ci_, m, mt, t)});
+            }
+        }
+      }
+      const int BM = gemm_tile_m(tg), BNC = gemm_tile_n_complex(tg);
+      for (int l = 0; l < B; ++l) {
+        const int rows = B - l;
+        const int ncc = (2 * l + 1) * nf;
+        const int nt = (ncc + BNC - 1) / BNC;
+        for (int mt = 0; mt < (rows + BM - 1) / BM; ++mt)
+          for (int t = 0; t < nt; ++t) cf[tg].push_back({L, make_int4(ci_, l, mt, t)});
+        for (int mt = 0; mt < (L + BM - 1) / BM; ++mt)
+          for (int t = 0; t < nt; ++t) ci[tg].push_back({rows, make_int4(ci_, l, mt, t)});
+      }
     }
     if (p->seminaive()) {
       const int nct = (ncol + p->dct_cols - 1) / p->dct_cols;
       for (int mi = 0; mi < 2 * B - 1; ++mi)
         for (int t = 0; t < nct; ++t) wdct.push_back(make_int4(ci_, mi, t, p->dct_cols));
       p->dct_lds = std::max(p->dct_lds, (int)dct_lds_bytes(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, B, p->dct_cols));
-    }
-    for (int l = 0; l < B; ++l) {
-      const int rows = B - l;
-      const int ncc = (2 * l + 1) * nf;
-      const int nt = (ncc + BNC - 1) / BNC;
-      for (int mt = 0; mt < (rows + BM - 1) / BM; ++mt)
-        for (int t = 0; t < nt; ++t) cf.push_back({L, make_int4(ci_, l, mt, t)});
-      for (int mt = 0; mt < (L + BM - 1) / BM; ++mt)
-        for (int t = 0; t < nt; ++t) ci.push_back({rows, make_int4(ci_, l, mt, t)});
     }
   }
   // XCD-aware order.  Blocks of a launch go round-robin to the chip's 8 XCDs
@@ -357,10 +445,6 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
       }
     }
   };
-  order(bf, wbf);
-  order(bi, wbi);
-  order(cf, wcf);
-  order(ci, wci);
   std::vector<int4> all;
   for (int md = 0; md < 3; ++md) {
     p->off_am[md] = (int)all.size();
@@ -368,10 +452,31 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
     p->lds_am[md] = ldsm[md];
     all.insert(all.end(), wam[md].begin(), wam[md].end());
   }
-  p->off_bf = (int)all.size(); p->n_bf = (int)wbf.size(); all.insert(all.end(), wbf.begin(), wbf.end());
-  p->off_bi = (int)all.size(); p->n_bi = (int)wbi.size(); all.insert(all.end(), wbi.begin(), wbi.end());
-  p->off_cf = (int)all.size(); p->n_cf = (int)wcf.size(); all.insert(all.end(), wcf.begin(), wcf.end());
-  p->off_ci = (int)all.size(); p->n_ci = (int)wci.size(); all.insert(all.end(), wci.begin(), wci.end());
+  auto append = [&](std::vector<Item>& v, int& off, int& n) {
+    std::vector<int4> w;
+    order(v, w);
+    off = (int)all.size();
+    n = (int)w.size();
+    all.insert(all.end(), w.begin(), w.end());
+  };
+  for (int tg = 0; tg < ngeo; ++tg) {
+    append(bf[tg], p->off_bf[tg], p->n_bf[tg]);
+    append(bi[tg], p->off_bi[tg], p->n_bi[tg]);
+    append(cf[tg], p->off_cf[tg], p->n_cf[tg]);
+    append(ci[tg], p->off_ci[tg], p->n_ci[tg]);
+  }
+  for (size_t q = 0; q < p->slabs.size(); ++q) {
+    sgl_plan_s::Slab& z = p->slabs[q];
+    for (int md = 0; md < 3; ++md) {
+      z.off_am[md] = (int)all.size();
+      z.n_am[md] = (int)sl[q].am[md].size();
+      all.insert(all.end(), sl[q].am[md].begin(), sl[q].am[md].end());
+    }
+    for (int tg = 0; tg < ngeo; ++tg) {
+      append(sl[q].bf[tg], z.off_bf[tg], z.n_bf[tg]);
+      append(sl[q].bi[tg], z.off_bi[tg], z.n_bi[tg]);
+    }
+  }
   p->off_dct = (int)all.size(); p->n_dct = (int)wdct.size(); all.insert(all.end(), wdct.begin(), wdct.end());
   SGL_TRY(p->alloc((void**)&p->d_work, all.size() * sizeof(int4)));
   SGL_HIP_TRY(hipMemcpy(p->d_work, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice));
@@ -456,6 +561,9 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
   }
   SGL_TRY(p->alloc((void**)&p->d_cls, descs.size() * sizeof(ClassDesc)));
   SGL_HIP_TRY(hipMemcpy(p->d_cls, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
+  for (auto& d : descs) d.keep_f = 1;
+  SGL_TRY(p->alloc((void**)&p->d_cls_keep, descs.size() * sizeof(ClassDesc)));
+  SGL_HIP_TRY(hipMemcpy(p->d_cls_keep, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
   SGL_TRY(build_work(p, s));
   prepare_fft_kernels(p->lds_am);
   if (p->seminaive()) prepare_dct_kernels(p->dct_lds);
@@ -515,64 +623,105 @@ int slot_work(const sgl_plan_s* p, int slot) {
     case S_FFT_F0: case S_FFT_I0: return p->n_am[0];
     case S_FFT_F1: case S_FFT_I1: return p->n_am[1];
     case S_FFT_F2: case S_FFT_I2: return p->n_am[2];
-    case S_LEG_F: return p->n_bf;
-    case S_LEG_I: return p->n_bi;
-    case S_RAD_F: return p->n_cf;
-    default: return p->n_ci;
+    case S_LEG_F: return p->n_bf[p->tile[slot]];
+    case S_LEG_I: return p->n_bi[p->tile[slot]];
+    case S_RAD_F: return p->n_cf[p->tile[slot]];
+    default: return p->n_ci[p->tile[slot]];
   }
 }
 
-// One stage launch.  in/out: the caller's buffers of this direction.
-hipError_t launch_slot(sgl_plan_s* p, int slot, const void* in, void* out, hipStream_t s) {
+// One stage launch.  in/out: the caller's buffers of this direction.  slab:
+// null for the slot's whole work list, else the slab's sub-list (FFT and
+// Legendre slots only) with the descriptors that keep the spectrum cached.
+hipError_t launch_slot(sgl_plan_s* p, int slot, const void* in, void* out, hipStream_t s,
+                       const sgl_plan_s::Slab* slab = nullptr) {
   const int prec = prec_of(p->dtype);
   const bool raw = (p->flags & SGL_SAMPLES_RAW) != 0;
   const int g = p->grid[slot];
+  const int tg = p->tile[slot];
+  const ClassDesc* cls = slab ? p->d_cls_keep : p->d_cls;
   switch (slot) {
     case S_FFT_F0: case S_FFT_F1: case S_FFT_F2: {
       const int md = slot - S_FFT_F0;
-      return launch_fft_forward(prec, raw, p->d_cls, p->d_work + p->off_am[md], p->n_am[md], p->lds_am[md], md, in,
-                                g, s);
+      const int off = slab ? slab->off_am[md] : p->off_am[md], n = slab ? slab->n_am[md] : p->n_am[md];
+      return launch_fft_forward(prec, raw, cls, p->d_work + off, n, p->lds_am[md], md, in, g, s);
     }
     case S_FFT_I0: case S_FFT_I1: case S_FFT_I2: {
       const int md = slot - S_FFT_I0;
-      return launch_fft_inverse(prec, raw, p->d_cls, p->d_work + p->off_am[md], p->n_am[md], p->lds_am[md], md, out,
-                                g, s);
+      const int off = slab ? slab->off_am[md] : p->off_am[md], n = slab ? slab->n_am[md] : p->n_am[md];
+      return launch_fft_inverse(prec, raw, cls, p->d_work + off, n, p->lds_am[md], md, out, g, s);
     }
-    case S_LEG_F:
+    case S_LEG_F: {
       if (p->seminaive()) {
         // seminaive step: DCT over the polar index, then the cosine-domain contraction
-        hipError_t e = launch_dct(prec == PREC_F64 ? PREC_F64 : PREC_F32, false, p->d_cls, p->d_work + p->off_dct,
+        hipError_t e = launch_dct(prec == PREC_F64 ? PREC_F64 : PREC_F32, false, cls, p->d_work + p->off_dct,
                                   p->n_dct, p->dct_lds, p->dct_cols, s);
         if (e != hipSuccess) return e;
       }
-      return launch_legendre(prec, false, p->d_cls, p->d_work + p->off_bf, p->n_bf, g, s);
+      const int off = slab ? slab->off_bf[tg] : p->off_bf[tg], n = slab ? slab->n_bf[tg] : p->n_bf[tg];
+      return launch_legendre(prec, false, tg, cls, p->d_work + off, n, g, s);
+    }
     case S_RAD_F:
-      return launch_radial(prec, false, p->d_cls, p->d_work + p->off_cf, p->n_cf, nullptr, out, g, s);
+      return launch_radial(prec, false, tg, cls, p->d_work + p->off_cf[tg], p->n_cf[tg], nullptr, out, g, s);
     case S_RAD_I:
-      return launch_radial(prec, true, p->d_cls, p->d_work + p->off_ci, p->n_ci, in, nullptr, g, s);
+      return launch_radial(prec, true, tg, cls, p->d_work + p->off_ci[tg], p->n_ci[tg], in, nullptr, g, s);
     default: {
-      hipError_t e = launch_legendre(prec, true, p->d_cls, p->d_work + p->off_bi, p->n_bi, g, s);
+      const int off = slab ? slab->off_bi[tg] : p->off_bi[tg], n = slab ? slab->n_bi[tg] : p->n_bi[tg];
+      hipError_t e = launch_legendre(prec, true, tg, cls, p->d_work + off, n, g, s);
       if (e != hipSuccess || !p->seminaive()) return e;
-      return launch_dct(prec == PREC_F64 ? PREC_F64 : PREC_F32, true, p->d_cls, p->d_work + p->off_dct, p->n_dct,
+      return launch_dct(prec == PREC_F64 ? PREC_F64 : PREC_F32, true, cls, p->d_work + p->off_dct, p->n_dct,
                         p->dct_lds, p->dct_cols, s);
     }
   }
 }
 
+// Work items of a slot's launch (whole list or one slab's sub-list).
+int slot_items(const sgl_plan_s* p, int slot, const sgl_plan_s::Slab* slab) {
+  if (!slab) return slot_work(p, slot);
+  const int tg = p->tile[slot];
+  switch (slot) {
+    case S_FFT_F0: case S_FFT_I0: return slab->n_am[0];
+    case S_FFT_F1: case S_FFT_I1: return slab->n_am[1];
+    case S_FFT_F2: case S_FFT_I2: return slab->n_am[2];
+    case S_LEG_F: return slab->n_bf[tg];
+    case S_LEG_I: return slab->n_bi[tg];
+    default: return 0;
+  }
+}
+
+// Stage launches of one direction.  Whole schedule: one launch per slot over
+// all classes.  Slab schedule: forward, per slab the FFT then the Legendre
+// launch, then one radial launch; inverse, one radial launch, then per slab
+// the Legendre then the FFT launch.  With timing on, events bracket each run of
+// consecutive launches of one stage.
 hipError_t launch_sequence(sgl_plan_s* p, int dir, const void* in, void* out, hipStream_t s, bool timed) {
   int open_stage = -1;
-  for (int q = 0; q < 5; ++q) {
-    const int slot = kSeq[dir][q];
-    if (slot_work(p, slot) == 0) continue;
-    const int st = kStage[dir][q];
+  auto one = [&](int slot, int st, const sgl_plan_s::Slab* slab) -> hipError_t {
+    if (slot_items(p, slot, slab) == 0) return hipSuccess;
     if (timed && st != open_stage) {
       if (open_stage >= 0) time_end(p, open_stage, s);
       time_begin(p, st, s);
       open_stage = st;
     }
-    hipError_t e = launch_slot(p, slot, in, out, s);
-    if (e != hipSuccess) return e;
+    return launch_slot(p, slot, in, out, s, slab);
+  };
+  hipError_t e = hipSuccess;
+  if (!p->use_slabs) {
+    for (int q = 0; q < 5 && e == hipSuccess; ++q) e = one(kSeq[dir][q], kStage[dir][q], nullptr);
+  } else if (dir == 0) {
+    for (const auto& z : p->slabs) {
+      for (int md = 0; md < 3 && e == hipSuccess; ++md) e = one(S_FFT_F0 + md, 0, &z);
+      if (e == hipSuccess) e = one(S_LEG_F, 1, &z);
+    }
+    if (e == hipSuccess) e = one(S_RAD_F, 2, nullptr);
+  } else {
+    e = one(S_RAD_I, 3, nullptr);
+    for (const auto& z : p->slabs) {
+      if (e == hipSuccess) e = one(S_LEG_I, 4, &z);
+      for (int md = 0; md < 3 && e == hipSuccess; ++md) e = one(S_FFT_I0 + md, 5, &z);
+    }
   }
+  if (e != hipSuccess) return e;
   if (timed && open_stage >= 0) time_end(p, open_stage, s);
   return hipSuccess;
 }
@@ -620,11 +769,22 @@ sgl_status_t run_direction(sgl_plan_s* p, int dir, const void* in, void* out, hi
   return SGL_OK;
 }
 
-// Plan-time autotuner: for every launch slot, time the persistent grid bounds
-// {1, 2, 4, 8, 16} x CUs and "one block per work item" on scratch buffers and
-// keep the fastest.  The candidates are timed in three interleaved rounds (a
-// warm-up launch and three timed launches each) and each keeps its best round,
-// so that clock drift during tuning does not favour the candidates timed first.
+// Tile geometries a launch slot can run with: the stage (b)/(c) slots of the
+// register-staged GEMM have two (see gemm_tile_m), the FFT slots and the
+// split-form Legendre kernel one.
+int slot_geometries(const sgl_plan_s* p, int slot) {
+  if (slot == S_RAD_F || slot == S_RAD_I) return gemm_num_geometries();
+  if (slot == S_LEG_F || slot == S_LEG_I)
+    return gemm_legendre_has_geometries(prec_of(p->dtype)) ? gemm_num_geometries() : 1;
+  return 1;
+}
+
+// Plan-time autotuner: for every launch slot, time each tile geometry the slot
+// has with the persistent grid bounds {1, 2, 4, 8, 16} x CUs and "one block per
+// work item" on scratch buffers, and keep the fastest pair.  The candidates are
+// timed in three interleaved rounds (a warm-up launch and three timed launches
+// each) and each keeps its best round, so that clock drift during tuning does
+// not favour the candidates timed first.
 sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
   int dev = 0, ncu = 256;
   SGL_HIP_TRY(hipGetDevice(&dev));
@@ -645,14 +805,20 @@ sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
     const bool inv = slot >= S_RAD_I;  // inverse slots read coefficients, write samples
     const void* in = inv ? tout : tin;
     void* out = inv ? tin : tout;
-    std::vector<int> cand;
-    for (int mult : {1, 2, 4, 8, 16})
-      if (mult * ncu < n) cand.push_back(mult * ncu);
-    cand.push_back(n);
+    struct Cand { int tg, grid; };
+    std::vector<Cand> cand;
+    for (int tg = 0; tg < slot_geometries(p, slot); ++tg) {
+      p->tile[slot] = tg;
+      const int ntg = slot_work(p, slot);
+      for (int mult : {1, 2, 4, 8, 16})
+        if (mult * ncu < ntg) cand.push_back({tg, mult * ncu});
+      cand.push_back({tg, ntg});
+    }
     std::vector<float> tbest(cand.size(), 1e30f);
     for (int round = 0; round < 3 && st == SGL_OK; ++round) {
       for (size_t ci = 0; ci < cand.size(); ++ci) {
-        p->grid[slot] = cand[ci];
+        p->tile[slot] = cand[ci].tg;
+        p->grid[slot] = cand[ci].grid;
         hipError_t e = launch_slot(p, slot, in, out, s);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_slot(p, slot, in, out, s);
@@ -671,7 +837,34 @@ sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
     size_t bi = 0;
     for (size_t ci = 1; ci < cand.size(); ++ci)
       if (tbest[ci] < tbest[bi]) bi = ci;
-    p->grid[slot] = cand[bi];
+    p->tile[slot] = cand[bi].tg;
+    p->grid[slot] = cand[bi].grid;
+  }
+  // launch schedule (whole stages, or slabs when some class splits), timed as
+  // forward + inverse pairs
+  if (st == SGL_OK && p->slab_max_cols > 0) {
+    float tb[2] = {1e30f, 1e30f};
+    for (int round = 0; round < 3 && st == SGL_OK; ++round)
+      for (int sch = 0; sch < 2; ++sch) {
+        p->use_slabs = sch == 1;
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < 4 && e == hipSuccess; ++r) {  // a warm-up pair, then three timed
+          if (r == 1) e = hipEventRecord(e0, s);
+          if (e == hipSuccess) e = launch_sequence(p, 0, tin, tout, s, false);
+          if (e == hipSuccess) e = launch_sequence(p, 1, tout, tin, s, false);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          set_error(std::string("autotune: ") + hipGetErrorString(e));
+          st = SGL_ERR_HIP;
+          break;
+        }
+        tb[sch] = std::min(tb[sch], ms);
+      }
+    p->use_slabs = tb[1] < tb[0];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -744,6 +937,13 @@ sgl_status_t sgl_plan_scaled(sgl_plan_t* out, const int* B_list, int nfunc, int 
       set_error("the seminaive Legendre step needs power-of-two bandlimits >= 8");
       return SGL_ERR_UNSUPPORTED;
     }
+    if ((flags & SGL_SEMINAIVE) && dtype == SGL_SPLIT_BF16 && B > 128) {
+      // odd orders contract against P_lm / sin(theta) in the cosine domain, whose
+      // entries reach ~l^1.5; with the spectrum held in FP32 the split form's error
+      // at B = 256 exceeds its 1e-6 bar (2e-6 measured at n = 256, l = 255, m = 1)
+      set_error("the seminaive Legendre step in split-bf16 precision needs B <= 128");
+      return SGL_ERR_UNSUPPORTED;
+    }
   }
   std::unique_ptr<sgl_plan_s> p(new (std::nothrow) sgl_plan_s());
   if (!p) { set_error("host allocation failed"); return SGL_ERR_OOM; }
@@ -758,8 +958,13 @@ sgl_status_t sgl_plan_scaled(sgl_plan_t* out, const int* B_list, int nfunc, int 
     p->tot_c += num_coeffs(B_list[f]);
   }
   hipStream_t s = nullptr;
+  {
+    const char* fa = std::getenv("SGL_TEST_FAIL_ALLOC");
+    g_fail_countdown = fa ? std::max(0L, std::strtol(fa, nullptr, 10)) : 0;
+  }
   sgl_status_t st = make_plan(p.get(), s);
   if (st == SGL_OK && (flags & SGL_AUTOTUNE)) st = autotune(p.get(), s);
+  g_fail_countdown = 0;
   if (st != SGL_OK) return st;  // unique_ptr frees everything allocated so far
   *out = p.release();
   return SGL_OK;
@@ -901,6 +1106,62 @@ sgl_status_t sgl_table(sgl_plan_t plan, int B, int which, double* host_out) {
 sgl_status_t sgl_launch_grids(sgl_plan_t plan, int* grids) {
   if (!plan || !grids) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
   for (int q = 0; q < NSLOT; ++q) grids[q] = plan->grid[q] ? plan->grid[q] : slot_work(plan, q);
+  return SGL_OK;
+}
+
+sgl_status_t sgl_launch_tiles(sgl_plan_t plan, int* tiles) {
+  if (!plan || !tiles) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
+  const int prec = prec_of(plan->dtype);
+  for (int q = 0; q < NSLOT; ++q) {
+    const int tg = plan->tile[q];
+    int rows = 0, cols = 0;
+    if (q == S_LEG_F || q == S_LEG_I) {
+      rows = gemm_tile_m_legendre(prec, tg);
+      cols = gemm_tile_n_complex_legendre(prec, tg);
+    } else if (q == S_RAD_F || q == S_RAD_I) {
+      rows = gemm_tile_m(tg);
+      cols = gemm_tile_n_complex(tg);
+    }
+    tiles[2 * q] = rows;
+    tiles[2 * q + 1] = cols;
+  }
+  return SGL_OK;
+}
+
+sgl_status_t sgl_set_launch_tile(sgl_plan_t plan, int slot, int geometry) {
+  if (!plan || slot < 0 || slot >= NSLOT || geometry < 0) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
+  if (geometry >= slot_geometries(plan, slot)) {
+    set_error("this launch slot has no such tile geometry");
+    return SGL_ERR_UNSUPPORTED;
+  }
+  if (plan->tile[slot] != geometry) {
+    plan->tile[slot] = geometry;
+    // captured graphs hold the previous kernels and work lists
+    for (auto& g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+    plan->graphs.clear();
+  }
+  return SGL_OK;
+}
+
+sgl_status_t sgl_launch_schedule(sgl_plan_t plan, int* slabs, int* nslab, int* slab_columns) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  if (slabs) *slabs = plan->use_slabs ? 1 : 0;
+  if (nslab) *nslab = (int)plan->slabs.size();
+  if (slab_columns) *slab_columns = plan->slab_max_cols;
+  return SGL_OK;
+}
+
+sgl_status_t sgl_set_launch_schedule(sgl_plan_t plan, int slabs) {
+  if (!plan || (slabs != 0 && slabs != 1)) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
+  if (slabs && plan->slab_max_cols == 0) {
+    set_error("no class of this plan splits into slabs");
+    return SGL_ERR_UNSUPPORTED;
+  }
+  if (plan->use_slabs != (slabs == 1)) {
+    plan->use_slabs = slabs == 1;
+    for (auto& g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+    plan->graphs.clear();
+  }
   return SGL_OK;
 }
 

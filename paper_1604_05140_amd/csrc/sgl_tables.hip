@@ -460,9 +460,9 @@ sgl_status_t build_grid(GridBuild& g, hipStream_t s) {
 
   double* buf = nullptr;
   const size_t nbuf = (size_t)edges.size() + 2 * kGL + 4 * (size_t)M + 2 * (size_t)N;
-  SGL_HIP_TRY(hipMalloc(&buf, nbuf * sizeof(double)));
+  SGL_HIP_TRY(dev_malloc((void**)&buf, nbuf * sizeof(double)));
   int* d_status = nullptr;
-  hipError_t e = hipMalloc(&d_status, sizeof(int));
+  hipError_t e = dev_malloc((void**)&d_status, sizeof(int));
   if (e != hipSuccess) {
     (void)hipFree(buf);
     set_error(std::string("hipMalloc: ") + hipGetErrorString(e));

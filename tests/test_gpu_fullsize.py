@@ -125,12 +125,21 @@ def test_inverse_against_stored_oracle_sums(B, dtype, tol):
     check_inverse(B, dtype, tol)
 
 
-@pytest.mark.parametrize("B", [128, 256])
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("split_bf16", 1e-6)])
+@pytest.mark.parametrize("B,dtype,tol", [(128, "f64", 1e-12), (256, "f64", 1e-12), (128, "split_bf16", 1e-6),
+                                         (128, "f32", 1e-5), (256, "f32", 1e-5)])
 def test_seminaive_against_stored_oracle_sums(B, dtype, tol):
     """The seminaive Legendre step (Sect. 3.3.1) on the same fixtures."""
     check_forward(B, dtype, tol, sgl.SGL_SEMINAIVE)
     check_inverse(B, dtype, tol, sgl.SGL_SEMINAIVE)
+
+
+def test_seminaive_split_refused_above_128():
+    """Split-bf16 seminaive plans stop at B = 128: at B = 256 the odd-order
+    cosine-domain tables (P_lm / sin theta) amplify the FP32 spectrum's rounding
+    past the 1e-6 bar (2.0e-6 on the B = 256 fixture)."""
+    with pytest.raises(sgl.SglError) as ei:
+        sgl.sgl_plan_ex([256], "split_bf16", sgl.SGL_SEMINAIVE)
+    assert ei.value.status == 2  # SGL_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("B", [129, 150, 251])

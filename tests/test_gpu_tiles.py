@@ -1,0 +1,157 @@
+"""GEMM tile geometries of the stage (b)/(c) launch slots (the per-order and
+per-degree grouped contractions of Alg. 3 / Alg. 4, Eq. DLT and Eq. DRT).
+
+The register-staged MFMA GEMM runs with a 128 x 64 (complex) or a 64 x 32 tile;
+the plan-time autotuner picks one per launch slot.  Every geometry must give the
+default plan's results (same per-element accumulation order, so equal up to
+rounding), hold the oracle's quadrature sums on small ragged plans, and survive
+graph capture.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import direct as D  # noqa: E402
+from paper_1604_05140_amd import sgl, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SEED = synth.BASE_SEED + 7000
+GEMM_SLOTS = (3, 4, 5, 6)  # forward Legendre, forward radial, inverse radial, inverse Legendre
+TOL = {"f64": 1e-12, "f32": 1e-5, "split_bf16": 1e-6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def dev(x, ct):
+    return torch.from_numpy(np.ascontiguousarray(x).reshape(-1)).to(DEV, ct)
+
+
+def run(plan, fn, x):
+    n = plan.total_coeffs if fn is sgl.sgl_forward else plan.total_samples
+    out = torch.full((n,), float("nan"), dtype=plan.complex_dtype, device=DEV)
+    fn(plan, x, out)
+    torch.cuda.synchronize()
+    return out
+
+
+def einf(ref, got):
+    return float((ref - got).abs().max() / ref.abs().max())
+
+
+def slot_geometries(plan, slot):
+    out = []
+    for g in (0, 1):
+        try:
+            plan.set_launch_tile(slot, g)
+            out.append(g)
+        except sgl.SglError as e:
+            assert e.status == 2  # SGL_ERR_UNSUPPORTED
+    plan.set_launch_tile(slot, 0)
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "split_bf16"])
+def test_every_geometry_matches_default(dtype):
+    """Ragged groups: two bandlimits (one with a Bluestein ring length), a
+    class of two functions, rows and columns that end mid-tile."""
+    Bs = [24, 24, 17]
+    print(f"tile geometries {dtype} B={Bs}", flush=True)
+    ct = torch.complex128 if dtype == "f64" else torch.complex64
+    base = sgl.sgl_plan_ex(Bs, dtype)
+    s = dev(np.concatenate([synth.complex_normal_samples(B, 1, seed=SEED + q)[0] for q, B in enumerate(Bs)]), ct)
+    c = dev(np.concatenate([synth.complex_normal_coeffs(B, 1, seed=SEED + 10 + q, decay=1.0)[0]
+                            for q, B in enumerate(Bs)]), ct)
+    f0, i0 = run(base, sgl.sgl_forward, s), run(base, sgl.sgl_inverse, c)
+    tiles0 = base.launch_tiles()
+    assert tiles0[0] == (0, 0) and tiles0[7] == (0, 0)
+    assert tiles0[4] == (128, 64) and tiles0[5] == (128, 64)
+    geos = {q: slot_geometries(base, q) for q in GEMM_SLOTS}
+    assert geos[4] == geos[5] == [0, 1]
+    # split-form Legendre: one tile (the copy-fed kernel); other forms: two
+    assert geos[3] == geos[6] == ([0] if dtype == "split_bf16" else [0, 1])
+    p = sgl.sgl_plan_ex(Bs, dtype)
+    for q in GEMM_SLOTS:
+        for g in geos[q]:
+            p.set_launch_tile(q, g)
+            want = (64, 32) if g == 1 else ((128, 128) if dtype == "split_bf16" and q in (3, 6) else (128, 64))
+            assert p.launch_tiles()[q] == want
+            f1, i1 = run(p, sgl.sgl_forward, s), run(p, sgl.sgl_inverse, c)
+            assert torch.isfinite(f1).all() and torch.isfinite(i1).all()
+            ef, ei = einf(f0, f1), einf(i0, i1)
+            print(f"  slot {q} geometry {g}: forward {ef:.1e}, inverse {ei:.1e}", flush=True)
+            assert ef <= TOL[dtype] and ei <= TOL[dtype], (q, g, ef, ei)
+        p.set_launch_tile(q, 0)
+    # all slots on the small tile at once
+    for q in GEMM_SLOTS:
+        p.set_launch_tile(q, geos[q][-1])
+    assert einf(f0, run(p, sgl.sgl_forward, s)) <= TOL[dtype]
+    assert einf(i0, run(p, sgl.sgl_inverse, c)) <= TOL[dtype]
+    p.destroy()
+    base.destroy()
+
+
+def test_small_tile_against_oracle():
+    """FP64 plan with every GEMM slot on the 64 x 32 tile against the oracle's
+    quadrature sums (forward of non-bandlimited samples, Thm. 3.4) and
+    synthesis sums, for two bandlimits at once."""
+    Bs = [9, 6]
+    p = sgl.sgl_plan_ex(Bs, "f64")
+    for q in GEMM_SLOTS:
+        p.set_launch_tile(q, 1)
+    so, co = p.offsets()
+    ss = [synth.complex_normal_samples(B, 1, seed=SEED + 20 + q)[0] for q, B in enumerate(Bs)]
+    cs = [synth.complex_normal_coeffs(B, 1, seed=SEED + 30 + q)[0] for q, B in enumerate(Bs)]
+    f = run(p, sgl.sgl_forward, dev(np.concatenate(ss), torch.complex128)).cpu().numpy()
+    i = run(p, sgl.sgl_inverse, dev(np.concatenate(cs), torch.complex128)).cpu().numpy()
+    for q, B in enumerate(Bs):
+        ref_f = D.forward(ss[q], B)
+        ref_i = D.inverse(cs[q], B)
+        got_f = f[co[q]:co[q] + D.num_coeffs(B)]
+        got_i = i[so[q]:so[q] + D.num_samples(B)]
+        assert np.abs(got_f - ref_f).max() <= 1e-12 * np.abs(ref_f).max(), B
+        assert np.abs(got_i - ref_i).max() <= 1e-12 * np.abs(ref_i).max(), B
+    p.destroy()
+
+
+def test_tile_change_recaptures_graphs():
+    B, batch = 16, 2
+    p = sgl.sgl_plan_ex([B] * batch, "f32", sgl.SGL_GRAPHS)
+    s = dev(synth.complex_normal_samples(B, batch, seed=SEED + 40), torch.complex64)
+    out = torch.empty(p.total_coeffs, dtype=torch.complex64, device=DEV)
+    sgl.sgl_forward(p, s, out)  # captured with geometry 0
+    torch.cuda.synchronize()
+    ref = out.clone()
+    for q in GEMM_SLOTS:
+        p.set_launch_tile(q, 1)
+    out.fill_(float("nan"))
+    sgl.sgl_forward(p, s, out)  # same buffers: captured again with geometry 1
+    sgl.sgl_forward(p, s, out)  # and replayed
+    torch.cuda.synchronize()
+    assert einf(ref, out) <= 1e-5
+    p.destroy()
+
+
+def test_bad_tile_requests():
+    p = sgl.sgl_plan(8, 1, "f32")
+    for slot, g, status in ((0, 1, 2), (7, 1, 2), (4, 2, 2), (10, 0, 1), (-1, 0, 1), (4, -1, 1)):
+        with pytest.raises(sgl.SglError) as ei:
+            p.set_launch_tile(slot, g)
+        assert ei.value.status == status, (slot, g)
+    p.destroy()
+
+
+def test_autotuner_reports_its_tiles():
+    Bs = synth.batched_bandlimits(24, 16, 40, seed=SEED + 50)
+    p = sgl.sgl_plan_ex(list(Bs), "f32", sgl.SGL_AUTOTUNE)
+    tiles = p.launch_tiles()
+    print(f"autotuned tiles {tiles}", flush=True)
+    for q in GEMM_SLOTS:
+        assert tiles[q] in ((128, 64), (64, 32)), (q, tiles[q])
+    p.destroy()
