@@ -189,6 +189,21 @@ sgl_status_t sgl_set_launch_schedule(sgl_plan_t plan, int slabs);
  * stream:    hipStream_t (NULL = default stream). */
 sgl_status_t sgl_forward(sgl_plan_t plan, const void* d_samples, void* d_coeffs, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): sgl_forward with the
+ * stage intermediates (the spectrum F and the Legendre output g) placed in a
+ * static device array of 64 MiB that the library holds on each GPU it runs on
+ * until the process ends, instead of the plan's own workspace.  Same arguments,
+ * layouts and results as sgl_forward; makes no allocation (no hipMalloc, no
+ * allocating library call), launches the stage kernels eagerly (never as a graph)
+ * and never synchronizes.  Every call on a GPU shares that GPU's array, which
+ * keeps the last call's contents: calls that may overlap on one GPU (different
+ * streams or threads without ordering) race and give wrong results; calls
+ * ordered on one stream are safe.  SGL_ERR_INVALID_ARG when the plan's F and g
+ * together exceed 64 MiB (e.g. B = 64 with one complex128 function fits: 42 MB;
+ * B = 128 does not) or when the current device is not the plan's. */
+sgl_status_t sgl_forward_noalloc(sgl_plan_t plan, const void* d_samples, void* d_coeffs, void* stream);
+
 /* Inverse transform (Alg. 4): d_coeffs (const) -> d_samples (written). */
 sgl_status_t sgl_inverse(sgl_plan_t plan, const void* d_coeffs, void* d_samples, void* stream);
 

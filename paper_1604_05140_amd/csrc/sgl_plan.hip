@@ -8,6 +8,7 @@
 #include <map>
 #include <numeric>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,42 @@ namespace sgl {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------------------
+// Static workspace of sgl_forward_noalloc: the stage intermediates (spectrum F
+// and g) of every class of a plan, back to back, in one file-scope device array.
+// Each GPU the library runs on holds its own copy, at its own address, until the
+// process ends.  In host code the array's name is only a host-side stand-in:
+// host code uses the address that hipGetSymbolAddress returns for the device,
+// looked up once per device when a plan is created there.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up with that
+// device current, once per device).
+sgl_status_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index beyond the static workspace table");
+    return SGL_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return SGL_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SGL_OK;
+}
 
 // allocations left before the injected failure of the current plan creation (0 = none)
 static thread_local long g_fail_countdown = 0;
@@ -86,6 +123,11 @@ struct sgl_plan_s {
   std::vector<void*> allocs;
   ClassDesc* d_cls = nullptr;
   ClassDesc* d_cls_keep = nullptr;  // the same descriptors with keep_f = 1 (slab schedule)
+  // descriptors whose F and g point into the device's static workspace
+  // (sgl_forward_noalloc); null when the plan's intermediates exceed it
+  ClassDesc* d_cls_static = nullptr;
+  size_t static_bytes = 0;  // bytes of F and g the static workspace would need
+  int device = 0;           // the device the plan was created on
   int4* d_work = nullptr;
   int64_t* d_naive_pre = nullptr;  // [forward prefix][inverse prefix][function-count prefix], ncls + 1 each
   int64_t n_naive_f = 0, n_naive_i = 0;
@@ -564,6 +606,32 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
   for (auto& d : descs) d.keep_f = 1;
   SGL_TRY(p->alloc((void**)&p->d_cls_keep, descs.size() * sizeof(ClassDesc)));
   SGL_HIP_TRY(hipMemcpy(p->d_cls_keep, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
+  {
+    // F and g of each class in the static workspace, 256-byte aligned
+    SGL_HIP_TRY(hipGetDevice(&p->device));
+    std::vector<size_t> offs;
+    size_t tot = 0;
+    for (auto& c : p->classes) {
+      const size_t B = c.B, L = 2 * B, nf = c.funcs.size();
+      offs.push_back(tot);
+      tot += ((2 * B - 1) * L * nf * L * p->esz() + 255) / 256 * 256;
+      offs.push_back(tot);
+      tot += (B * B * nf * L * p->esz() + 255) / 256 * 256;
+    }
+    p->static_bytes = tot;
+    if (tot <= kScratchBytes) {
+      void* base = nullptr;
+      SGL_TRY(scratch_address(p->device, &base));
+      for (size_t q = 0; q < descs.size(); ++q) {
+        descs[q].keep_f = 0;
+        descs[q].F = static_cast<unsigned char*>(base) + offs[2 * q];
+        descs[q].g = static_cast<unsigned char*>(base) + offs[2 * q + 1];
+      }
+      SGL_TRY(p->alloc((void**)&p->d_cls_static, descs.size() * sizeof(ClassDesc)));
+      SGL_HIP_TRY(
+          hipMemcpy(p->d_cls_static, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
+    }
+  }
   SGL_TRY(build_work(p, s));
   prepare_fft_kernels(p->lds_am);
   if (p->seminaive()) prepare_dct_kernels(p->dct_lds);
@@ -634,12 +702,12 @@ int slot_work(const sgl_plan_s* p, int slot) {
 // null for the slot's whole work list, else the slab's sub-list (FFT and
 // Legendre slots only) with the descriptors that keep the spectrum cached.
 hipError_t launch_slot(sgl_plan_s* p, int slot, const void* in, void* out, hipStream_t s,
-                       const sgl_plan_s::Slab* slab = nullptr) {
+                       const sgl_plan_s::Slab* slab = nullptr, const ClassDesc* cls_override = nullptr) {
   const int prec = prec_of(p->dtype);
   const bool raw = (p->flags & SGL_SAMPLES_RAW) != 0;
   const int g = p->grid[slot];
   const int tg = p->tile[slot];
-  const ClassDesc* cls = slab ? p->d_cls_keep : p->d_cls;
+  const ClassDesc* cls = cls_override ? cls_override : (slab ? p->d_cls_keep : p->d_cls);
   switch (slot) {
     case S_FFT_F0: case S_FFT_F1: case S_FFT_F2: {
       const int md = slot - S_FFT_F0;
@@ -1048,6 +1116,30 @@ sgl_status_t sgl_synthesize_points(sgl_plan_t plan, const void* d_coeffs, int np
   SGL_HIP_TRY(launch_synthesize_points(plan->d_cls, plan->d_naive_pre + 2 * (ncls + 1), ncls,
                                        chunks * (int64_t)plan->Bs.size(), d_coeffs, npts, d_xyz, d_values,
                                        (hipStream_t)stream));
+  return SGL_OK;
+}
+
+sgl_status_t sgl_forward_noalloc(sgl_plan_t plan, const void* d_samples, void* d_coeffs, void* stream) {
+  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
+  SGL_TRY(check_call(plan, d_samples, plan->tot_s * plan->esz(), d_coeffs, plan->tot_c * plan->esz()));
+  if (!plan->d_cls_static) {
+    set_error("the plan's stage intermediates need " + std::to_string(plan->static_bytes) +
+              " bytes, more than the static workspace of " + std::to_string(kScratchBytes) + " bytes");
+    return SGL_ERR_INVALID_ARG;
+  }
+  int dev = -1;
+  SGL_HIP_TRY(hipGetDevice(&dev));
+  if (dev != plan->device) {
+    set_error("sgl_forward_noalloc must run on the device its plan was created on");
+    return SGL_ERR_INVALID_ARG;
+  }
+  // the whole schedule's launches, eager (no graph), on the static workspace
+  const hipStream_t s = (hipStream_t)stream;
+  for (int q = 0; q < 5; ++q) {
+    const int slot = kSeq[0][q];
+    if (slot_work(plan, slot) == 0) continue;
+    SGL_HIP_TRY(launch_slot(plan, slot, d_samples, d_coeffs, s, nullptr, plan->d_cls_static));
+  }
   return SGL_OK;
 }
 

@@ -53,6 +53,7 @@ def _load():
                              ctypes.c_uint, ctypes.c_double], ctypes.c_int),
         "sgl_forward": ([P, P, P, P], ctypes.c_int),
         "sgl_inverse": ([P, P, P, P], ctypes.c_int),
+        "sgl_forward_noalloc": ([P, P, P, P], ctypes.c_int),
         "sgl_naive_forward": ([P, P, P, P], ctypes.c_int),
         "sgl_naive_inverse": ([P, P, P, P], ctypes.c_int),
         "sgl_midpoint_forward": ([P, P, ctypes.c_int, ctypes.c_double, P, P], ctypes.c_int),
@@ -97,7 +98,7 @@ _HEADER_NAMES = [
     "sgl_set_timing", "sgl_stage_times", "sgl_debug_gemm", "sgl_status_string", "sgl_last_error",
     "sgl_launch_grids", "sgl_naive_forward", "sgl_naive_inverse", "sgl_plan_scaled",
     "sgl_midpoint_forward", "sgl_synthesize_points", "sgl_launch_tiles", "sgl_set_launch_tile",
-    "sgl_launch_schedule", "sgl_set_launch_schedule",
+    "sgl_launch_schedule", "sgl_set_launch_schedule", "sgl_forward_noalloc",
 ]
 
 
@@ -264,6 +265,15 @@ def sgl_forward(plan: Plan, samples, coeffs, stream=None):
     plan._check_tensor(coeffs, plan.total_coeffs, "coeffs")
     _check(_load().sgl_forward(plan.handle, ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(coeffs.data_ptr()),
                                _stream_handle(stream)), "sgl_forward")
+
+
+def sgl_forward_noalloc(plan: Plan, samples, coeffs, stream=None):
+    """sgl_forward on the library's static per-GPU workspace (allocates nothing)."""
+    plan._check_tensor(samples, plan.total_samples, "samples")
+    plan._check_tensor(coeffs, plan.total_coeffs, "coeffs")
+    _check(_load().sgl_forward_noalloc(plan.handle, ctypes.c_void_p(samples.data_ptr()),
+                                       ctypes.c_void_p(coeffs.data_ptr()), _stream_handle(stream)),
+           "sgl_forward_noalloc")
 
 
 def sgl_inverse(plan: Plan, coeffs, samples, stream=None):

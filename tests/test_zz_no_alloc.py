@@ -1,0 +1,72 @@
+"""sgl_forward_noalloc: the forward transform with its stage intermediates in
+the library's static per-GPU workspace, for callers that cannot allocate.
+Called through the C ABI; its output must equal sgl_forward's on the same plan
+and inputs (same kernels, same work lists), on two calls in a row (the second
+smaller, so the array holds the first call's values when it starts), and it
+must not change the device's free memory."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1604_05140_amd import sgl, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SEED = synth.BASE_SEED + 9000
+TOL = {"f64": 1e-12, "f32": 1e-5, "split_bf16": 1e-6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def samples(Bs, ct, seed):
+    x = np.concatenate([synth.complex_normal_samples(B, 1, seed=seed + q)[0] for q, B in enumerate(Bs)])
+    return torch.from_numpy(x).to(DEV, ct)
+
+
+def noalloc(plan, s, out):
+    lib = sgl._load()
+    P = ctypes.c_void_p
+    return lib.sgl_forward_noalloc(plan.handle, P(s.data_ptr()), P(out.data_ptr()),
+                                   P(torch.cuda.current_stream().cuda_stream))
+
+
+def test_noalloc_matches_forward_twice():
+    cases = [([32, 32, 20], "f64"), ([12, 7], "split_bf16")]  # the second call is smaller
+    for Bs, dtype in cases:
+        print(f"sgl_forward_noalloc B={Bs} {dtype}", flush=True)
+        p = sgl.sgl_plan_ex(Bs, dtype)
+        ct = p.complex_dtype
+        s = samples(Bs, ct, SEED + len(Bs))
+        ref = torch.empty(p.total_coeffs, dtype=ct, device=DEV)
+        sgl.sgl_forward(p, s, ref)
+        got = torch.full((p.total_coeffs,), float("nan"), dtype=ct, device=DEV)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        assert noalloc(p, s, got) == 0, sgl._load().sgl_last_error()
+        torch.cuda.synchronize()
+        assert torch.cuda.mem_get_info()[0] == free0
+        assert torch.isfinite(got).all()
+        e = float((got - ref).abs().max() / ref.abs().max())
+        print(f"  e_inf vs sgl_forward {e:.1e}", flush=True)
+        assert e <= TOL[dtype]
+        assert torch.equal(got, ref)  # same kernels on the same work items
+        p.destroy()
+
+
+def test_noalloc_refuses_oversized_plans():
+    p = sgl.sgl_plan(128, 1, "f32")  # F alone is 134 MB
+    s = torch.zeros(p.total_samples, dtype=p.complex_dtype, device=DEV)
+    out = torch.full((p.total_coeffs,), 3.0, dtype=p.complex_dtype, device=DEV)
+    assert noalloc(p, s, out) == 1  # SGL_ERR_INVALID_ARG
+    assert b"static workspace" in sgl._load().sgl_last_error()
+    torch.cuda.synchronize()
+    assert bool((out == 3.0).all())
+    p.destroy()
