@@ -357,6 +357,7 @@ def bench_batched(args, torch, sgl, synth, dev):
                                "coefficients", "form": dtype, "total_coeffs": plan.total_coeffs,
                    "total_samples": plan.total_samples},
         "stage_ms": per_stage, "ms_per_step_with_stage_events": ms_inst, "launch_grids": plan.launch_grids(),
+        "launch_tiles": plan.launch_tiles(),
     }
     print(json.dumps(out), flush=True)
 
@@ -669,6 +670,7 @@ def main():
             "e_inf_inverse_vs_f64": ei,
             "within_bar": gate_ok,
             "launch_grids": plan.launch_grids(),
+            "launch_tiles": plan.launch_tiles(),
         }
         print(f"[bench] {key}: {ms:.3f} ms/step, {nf * 1000.0 / ms:.1f} transforms/s "
               f"(stage-timed pass {ms_inst:.3f} ms/step)", file=sys.stderr, flush=True)

@@ -161,27 +161,6 @@ sgl_status_t sgl_launch_tiles(sgl_plan_t plan, int* tiles);
  * buffer pair captures again).  Not to be called while the plan runs a call. */
 sgl_status_t sgl_set_launch_tile(sgl_plan_t plan, int slot, int geometry);
 
-/* Launch schedule of stages (a) and (b).  Whole (0): each stage is one launch
- * over every function, and the spectrum between the azimuthal FFT and the
- * Legendre projection (Alg. 3 / Alg. 4; (2B-1) (2B)^2 complex values per
- * function) passes through HBM.  Slabs (1): the (function, radius) columns of
- * each bandlimit class are cut into slabs whose spectrum fits the last-level
- * (Infinity) cache (at most 160 MB each); the forward runs, slab by slab, the FFT
- * then the Legendre launch, and the inverse the Legendre then the FFT launch,
- * so each slab's spectrum is read back from the cache (Legendre columns are
- * independent, Eq. DLT).  The radial stage is one launch either way.  Results
- * are the same (same kernels and per-element arithmetic).  Classes whose ring
- * blocks or column tiles do not align with a slab run as one slab.
- * slabs: 1 if the slab schedule is in use; nslab: slabs of the schedule;
- * slab_columns: the widest slab in columns (0: no class splits, the slab
- * schedule is the whole schedule).  Any pointer may be NULL.  SGL_AUTOTUNE
- * times both schedules and keeps the faster; otherwise the whole schedule. */
-sgl_status_t sgl_launch_schedule(sgl_plan_t plan, int* slabs, int* nslab, int* slab_columns);
-
-/* Select the launch schedule (0 whole, 1 slabs).  SGL_ERR_UNSUPPORTED for 1 when
- * no class splits; drops captured graphs as sgl_set_launch_tile does. */
-sgl_status_t sgl_set_launch_schedule(sgl_plan_t plan, int slabs);
-
 /* Forward transform (Alg. 3) of every function of the plan.
  * d_samples: device, const, total_samples complex values (complex128 for
  *            SGL_F64, complex64 otherwise), psi order per function.

@@ -134,7 +134,7 @@ __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int
         T2 o = y[k2];
         o.x *= wj;
         o.y *= wj;
-        store_spectrum(&F[((int64_t)mi * L + j) * ncol + col0 + r], o, C.keep_f);
+        store_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r], o);
       }
     }
   }
@@ -324,7 +324,7 @@ __device__ inline void fwd_blue(const ClassDesc& C, int j, int col0, int nr, int
       T2 o = cmul(z[n1], chirp[idx]);
       o.x *= wj;
       o.y *= wj;
-      store_spectrum(&F[((int64_t)mi * L + j) * ncol + col0 + r], o, C.keep_f);
+      store_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r], o);
     }
   }
   __syncthreads();
@@ -528,7 +528,7 @@ __device__ inline void fwd512(const ClassDesc& C, int j, int col0, int nr, const
     SGL_G T2* dst = gmem(reinterpret_cast<T2*>(C.F)) + ((int64_t)mi * L + j) * ncol + col0 + r;
     for (; mi < nm; mi += blockDim.x / kRings512, dst += step) {
       const int m = mi - (B - 1);
-      store_spectrum(dst, stage[m >= 0 ? m : L + m], C.keep_f);
+      store_stream(dst, stage[m >= 0 ? m : L + m]);
     }
   }
   __syncthreads();
@@ -731,7 +731,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       T2 v = cur[r * L + bin];
       v.x *= wj;
       v.y *= wj;
-      store_spectrum(&F[((int64_t)mi * L + j) * ncol + col0 + r], v, C.keep_f);
+      store_stream(&F[((int64_t)mi * L + j) * ncol + col0 + r], v);
     }
     __syncthreads();
   }

@@ -740,7 +740,6 @@ k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwo
       constexpr int DUAL = KIND ^ 1;
       T* obase = KIND == K_B_FWD ? reinterpret_cast<T*>(t.C->g)
                                  : (KIND == K_B_INV ? reinterpret_cast<T*>(t.C->F) : reinterpret_cast<T*>(cout));
-      const int keep_f = KIND == K_B_INV ? load_uniform(&t.C->keep_f) : 0;
 #pragma unroll
       for (int j = 0; j < NBJ; ++j) {
         const int rc = wc + j * 16 + lr;
@@ -758,12 +757,9 @@ k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwo
             if (okc && row < t.M) {
               // the spectrum rows of the inverse Legendre stage stream out (they
               // are read once, in full, by the inverse FFT)
-              if constexpr (KIND == K_B_INV) {
-                if (keep_f)  // slab schedule: read back from the last-level cache
-                  op[2 * x_off<DUAL>(t, oc, row)] = value(i, j, v);
-                else
-                  __builtin_nontemporal_store(value(i, j, v), &op[2 * x_off<DUAL>(t, oc, row)]);
-              } else
+              if constexpr (KIND == K_B_INV)
+                __builtin_nontemporal_store(value(i, j, v), &op[2 * x_off<DUAL>(t, oc, row)]);
+              else
                 op[2 * x_off<DUAL>(t, oc, row)] = value(i, j, v);
             }
           }
@@ -1055,7 +1051,6 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
       // their number is known at the next item's first wait.  The spectrum
       // rows stream out (read once by the iFFT).
       SGL_G f2v* spare = gmem(&g_spare_out[lane]);
-      const int keep_f = load_uniform(&t.C->keep_f);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -1063,11 +1058,7 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
           const int row = t.row0 + wr + i * 16 + 4 * lk + v;
           const bool ok = okc && i < nbi && row < t.M;
           SGL_G f2v* q = ok ? reinterpret_cast<SGL_G f2v*>(oc.p + 2 * x_off<DUAL>(t, oc, min(row, t.M - 1))) : spare;
-          const f2v o = f2v{sg * acc[i][0][v], sg * acc[i][1][v]};
-          if (keep_f)
-            *q = o;  // slab schedule: read back from the last-level cache
-          else
-            __builtin_nontemporal_store(o, q);
+          __builtin_nontemporal_store(f2v{sg * acc[i][0][v], sg * acc[i][1][v]}, q);
         }
       }
     } else if (okc) {

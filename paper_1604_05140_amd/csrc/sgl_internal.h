@@ -124,10 +124,6 @@ struct ClassDesc {
   // (seminaive step: cosine-domain sums over k < B, Sect. 3.3.1)
   int kb;
   const void* dct;  // DCT constants of the seminaive step (dct_const_count(B) complex), else null
-  // 1 in the descriptors of the slab schedule: the spectrum F is stored with the
-  // default cache policy (read back from the last-level cache by the next
-  // launch), 0: streaming stores (F passes through HBM)
-  int keep_f;
 };
 // naive / midpoint forward items group this many consecutive degrees n
 constexpr int kNaiveGroup = 8;
@@ -224,10 +220,11 @@ struct GridBuild {
   double* sig;
   double* theta;
   double* btilde;
+  double* sig_m;  // sigma_i = sig_m * 2^sig_e (mantissa to double-double accuracy, exponent)
+  double* sig_e;
 };
 sgl_status_t build_grid(GridBuild& g, hipStream_t s);
-hipError_t build_tables(int B, const double* r, const double* log_sig, const double* theta, double* P64,
-                        double* R64, hipStream_t s);
+hipError_t build_tables(int B, const GridBuild& g, double* P64, double* R64, hipStream_t s);
 hipError_t build_twiddles(int L, void* tw, bool f32, hipStream_t s);
 // FP64 Bluestein tables for ring length L and convolution length M (see ClassDesc),
 // written in FP64 (f32 = false) or rounded to FP32.

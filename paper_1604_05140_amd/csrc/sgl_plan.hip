@@ -6,7 +6,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
-#include <numeric>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -70,7 +69,7 @@ namespace {
 struct ClassHost {
   int B = 0;
   std::vector<int> funcs;
-  double* grid = nullptr;  // r, log_a, log_sig, sig, theta, btilde (6 x 2B)
+  double* grid = nullptr;  // r, log_a, log_sig, sig, theta, btilde, sig_m, sig_e (8 x 2B)
   double* P64 = nullptr;
   double* R64 = nullptr;
   void* A[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -122,7 +121,6 @@ struct sgl_plan_s {
   std::vector<ClassHost> classes;
   std::vector<void*> allocs;
   ClassDesc* d_cls = nullptr;
-  ClassDesc* d_cls_keep = nullptr;  // the same descriptors with keep_f = 1 (slab schedule)
   // descriptors whose F and g point into the device's static workspace
   // (sgl_forward_noalloc); null when the plan's intermediates exceed it
   ClassDesc* d_cls_static = nullptr;
@@ -144,21 +142,6 @@ struct sgl_plan_s {
   // geometry per launch slot (0 = the default tile); both set by the autotuner
   int grid[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   int tile[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  // Slab schedule: the (function, radius) columns of every class split into
-  // slabs whose spectrum fits the last-level cache; stage (a) and stage (b) run
-  // slab by slab (forward: FFT then Legendre; inverse: Legendre then FFT), each
-  // slab's spectrum read back while still cached.  Every class has at least one
-  // slab (a class whose rings or tiles do not align has one slab of all its
-  // columns).  Work sub-lists per slab: FFT by mode, Legendre per direction and
-  // tile geometry.
-  struct Slab {
-    int cls, col0, col1;
-    int off_am[3], n_am[3];
-    int off_bf[2], n_bf[2], off_bi[2], n_bi[2];
-  };
-  std::vector<Slab> slabs;
-  int slab_max_cols = 0;   // widest slab (columns), 0 if no class splits
-  bool use_slabs = false;  // the schedule in use
   // captured launch sequences, keyed by (direction, input, output)
   struct GraphEntry {
     int dir;
@@ -238,12 +221,13 @@ sgl_status_t build_class(sgl_plan_s* p, ClassHost& c, const ClassHost* share, hi
     c.dct = share->dct;
     return build_class_data(p, c, s);
   }
-  SGL_TRY(p->alloc((void**)&c.grid, 6 * (size_t)L * sizeof(double)));
-  GridBuild gb{B, c.grid, c.grid + L, c.grid + 2 * L, c.grid + 3 * L, c.grid + 4 * L, c.grid + 5 * L};
+  SGL_TRY(p->alloc((void**)&c.grid, 8 * (size_t)L * sizeof(double)));
+  GridBuild gb{B,         c.grid,         c.grid + L,     c.grid + 2 * L, c.grid + 3 * L,
+               c.grid + 4 * L, c.grid + 5 * L, c.grid + 6 * L, c.grid + 7 * L};
   SGL_TRY(build_grid(gb, s));
   SGL_TRY(p->alloc((void**)&c.P64, ts * sizeof(double)));
   SGL_TRY(p->alloc((void**)&c.R64, ts * sizeof(double)));
-  SGL_HIP_TRY(build_tables(B, gb.r, gb.log_sig, gb.theta, c.P64, c.R64, s));
+  SGL_HIP_TRY(build_tables(B, gb, c.P64, c.R64, s));
   const bool semi = p->seminaive();
   if (semi) {
     // seminaive step: cosine-domain Legendre table and the DCT constants
@@ -338,27 +322,6 @@ sgl_status_t build_class_data(sgl_plan_s* p, ClassHost& c, hipStream_t /*s*/) {
   return SGL_OK;
 }
 
-// Largest spectrum slab of the slab schedule: the last-level (Infinity) cache
-// of MI355X holds 256 MB; a slab leaves room for the stage (b) output and the
-// tables that pass through it at the same time.
-constexpr size_t kSlabBytes = size_t(160) << 20;
-
-// Slab width (columns of the (function, radius) axis) of a class: the widest
-// multiple of the alignment unit (rings per FFT block, the stage (b) column
-// tiles of every geometry) whose spectrum fits kSlabBytes; 0 = not split.
-int slab_width(const sgl_plan_s* p, const ClassHost& c) {
-  if (p->seminaive()) return 0;  // its DCT pass runs over whole orders
-  const int prec = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
-  const int B = c.B, L = 2 * B, ncol = (int)c.funcs.size() * L;
-  int unit = c.rpb;
-  for (int tg = 0; tg < (gemm_legendre_has_geometries(prec) ? gemm_num_geometries() : 1); ++tg)
-    unit = std::lcm(unit, gemm_tile_n_complex_legendre(prec, tg));
-  if (L % unit != 0) return 0;  // a ring block or column tile would straddle two slabs
-  const size_t fcol = (size_t)(2 * B - 1) * L * p->esz();
-  const int W = (int)(kSlabBytes / fcol) / unit * unit;
-  return (W == 0 || W >= ncol) ? 0 : W;
-}
-
 sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
   std::vector<int4> wam[3], wdct;
   if (p->seminaive()) {
@@ -372,11 +335,6 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
   const int precb = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
   const int ngeo = gemm_num_geometries();
   std::vector<Item> bf[2], bi[2], cf[2], ci[2];
-  // slab schedule sub-lists, per slab
-  struct SlabItems { std::vector<int4> am[3]; std::vector<Item> bf[2], bi[2]; };
-  std::vector<SlabItems> sl;
-  p->slabs.clear();
-  p->slab_max_cols = 0;
   int ldsm[3] = {0, 0, 0};
   for (int ci_ = 0; ci_ < (int)p->classes.size(); ++ci_) {
     const ClassHost& c = p->classes[ci_];
@@ -384,23 +342,8 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
     const int ncol = nf * L;
     const int ncb = (ncol + c.rpb - 1) / c.rpb;
     const int mode = fft_mode(L);
-    const int W = slab_width(p, c);
-    const int s0 = (int)p->slabs.size(), ns = W ? (ncol + W - 1) / W : 1;
-    for (int q = 0; q < ns; ++q) {
-      sgl_plan_s::Slab z{};
-      z.cls = ci_;
-      z.col0 = W ? q * W : 0;
-      z.col1 = W ? std::min(ncol, (q + 1) * W) : ncol;
-      p->slabs.push_back(z);
-    }
-    sl.resize(p->slabs.size());
-    p->slab_max_cols = std::max(p->slab_max_cols, W);
-    auto slab_of = [&](int col) { return s0 + (W ? col / W : 0); };  // col: first column of an item
     for (int j = 0; j < L; ++j)
-      for (int cb = 0; cb < ncb; ++cb) {
-        wam[mode].push_back(make_int4(ci_, j, cb, c.rpb));
-        sl[slab_of(cb * c.rpb)].am[mode].push_back(make_int4(ci_, j, cb, c.rpb));
-      }
+      for (int cb = 0; cb < ncb; ++cb) wam[mode].push_back(make_int4(ci_, j, cb, c.rpb));
     ldsm[mode] = std::max(ldsm[mode], (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
     const int kb = p->seminaive() ? B : L;  // polar-side contraction length
     for (int tg = 0; tg < ngeo; ++tg) {
@@ -411,18 +354,10 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
           const int rows = B - m;
           const int ncc = (m ? 2 : 1) * nf * L;
           const int nt = (ncc + BNb - 1) / BNb;
-          // the slab of a column tile: its first column within its +m / -m segment
-          auto tslab = [&](int t) { return slab_of((t * BNb) % ncol); };
           for (int mt = 0; mt < (rows + BMb - 1) / BMb; ++mt)
-            for (int t = 0; t < nt; ++t) {
-              bf[tg].push_back({kb, make_int4(ci_, m, mt, t)});
-              sl[tslab(t)].bf[tg].push_back({kb, make_int4(ci_, m, mt, t)});
-            }
+            for (int t = 0; t < nt; ++t) bf[tg].push_back({kb, make_int4(ci_, m, mt, t)});
           for (int mt = 0; mt < (kb + BMb - 1) / BMb; ++mt)
-            for (int t = 0; t < nt; ++t) {
-              bi[tg].push_back({rows, make_int4(ci_, m, mt, t)});
-              sl[tslab(t)].bi[tg].push_back({rows, make_int4(ci_, m, mt, t)});
-            }
+            for (int t = 0; t < nt; ++t) bi[tg].push_back({rows, make_int4(ci_, m, mt, t)});
         }
       }
       const int BM = gemm_tile_m(tg), BNC = gemm_tile_n_complex(tg);
@@ -506,18 +441,6 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
     append(bi[tg], p->off_bi[tg], p->n_bi[tg]);
     append(cf[tg], p->off_cf[tg], p->n_cf[tg]);
     append(ci[tg], p->off_ci[tg], p->n_ci[tg]);
-  }
-  for (size_t q = 0; q < p->slabs.size(); ++q) {
-    sgl_plan_s::Slab& z = p->slabs[q];
-    for (int md = 0; md < 3; ++md) {
-      z.off_am[md] = (int)all.size();
-      z.n_am[md] = (int)sl[q].am[md].size();
-      all.insert(all.end(), sl[q].am[md].begin(), sl[q].am[md].end());
-    }
-    for (int tg = 0; tg < ngeo; ++tg) {
-      append(sl[q].bf[tg], z.off_bf[tg], z.n_bf[tg]);
-      append(sl[q].bi[tg], z.off_bi[tg], z.n_bi[tg]);
-    }
   }
   p->off_dct = (int)all.size(); p->n_dct = (int)wdct.size(); all.insert(all.end(), wdct.begin(), wdct.end());
   SGL_TRY(p->alloc((void**)&p->d_work, all.size() * sizeof(int4)));
@@ -603,9 +526,6 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
   }
   SGL_TRY(p->alloc((void**)&p->d_cls, descs.size() * sizeof(ClassDesc)));
   SGL_HIP_TRY(hipMemcpy(p->d_cls, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
-  for (auto& d : descs) d.keep_f = 1;
-  SGL_TRY(p->alloc((void**)&p->d_cls_keep, descs.size() * sizeof(ClassDesc)));
-  SGL_HIP_TRY(hipMemcpy(p->d_cls_keep, descs.data(), descs.size() * sizeof(ClassDesc), hipMemcpyHostToDevice));
   {
     // F and g of each class in the static workspace, 256-byte aligned
     SGL_HIP_TRY(hipGetDevice(&p->device));
@@ -623,7 +543,6 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
       void* base = nullptr;
       SGL_TRY(scratch_address(p->device, &base));
       for (size_t q = 0; q < descs.size(); ++q) {
-        descs[q].keep_f = 0;
         descs[q].F = static_cast<unsigned char*>(base) + offs[2 * q];
         descs[q].g = static_cast<unsigned char*>(base) + offs[2 * q + 1];
       }
@@ -698,26 +617,25 @@ int slot_work(const sgl_plan_s* p, int slot) {
   }
 }
 
-// One stage launch.  in/out: the caller's buffers of this direction.  slab:
-// null for the slot's whole work list, else the slab's sub-list (FFT and
-// Legendre slots only) with the descriptors that keep the spectrum cached.
+// One stage launch.  in/out: the caller's buffers of this direction;
+// cls_override: class descriptors to use instead of the plan's (null: the plan's).
 hipError_t launch_slot(sgl_plan_s* p, int slot, const void* in, void* out, hipStream_t s,
-                       const sgl_plan_s::Slab* slab = nullptr, const ClassDesc* cls_override = nullptr) {
+                       const ClassDesc* cls_override = nullptr) {
   const int prec = prec_of(p->dtype);
   const bool raw = (p->flags & SGL_SAMPLES_RAW) != 0;
   const int g = p->grid[slot];
   const int tg = p->tile[slot];
-  const ClassDesc* cls = cls_override ? cls_override : (slab ? p->d_cls_keep : p->d_cls);
+  const ClassDesc* cls = cls_override ? cls_override : p->d_cls;
   switch (slot) {
     case S_FFT_F0: case S_FFT_F1: case S_FFT_F2: {
       const int md = slot - S_FFT_F0;
-      const int off = slab ? slab->off_am[md] : p->off_am[md], n = slab ? slab->n_am[md] : p->n_am[md];
-      return launch_fft_forward(prec, raw, cls, p->d_work + off, n, p->lds_am[md], md, in, g, s);
+      return launch_fft_forward(prec, raw, cls, p->d_work + p->off_am[md], p->n_am[md], p->lds_am[md], md, in, g,
+                                s);
     }
     case S_FFT_I0: case S_FFT_I1: case S_FFT_I2: {
       const int md = slot - S_FFT_I0;
-      const int off = slab ? slab->off_am[md] : p->off_am[md], n = slab ? slab->n_am[md] : p->n_am[md];
-      return launch_fft_inverse(prec, raw, cls, p->d_work + off, n, p->lds_am[md], md, out, g, s);
+      return launch_fft_inverse(prec, raw, cls, p->d_work + p->off_am[md], p->n_am[md], p->lds_am[md], md, out, g,
+                                s);
     }
     case S_LEG_F: {
       if (p->seminaive()) {
@@ -726,16 +644,14 @@ hipError_t launch_slot(sgl_plan_s* p, int slot, const void* in, void* out, hipSt
                                   p->n_dct, p->dct_lds, p->dct_cols, s);
         if (e != hipSuccess) return e;
       }
-      const int off = slab ? slab->off_bf[tg] : p->off_bf[tg], n = slab ? slab->n_bf[tg] : p->n_bf[tg];
-      return launch_legendre(prec, false, tg, cls, p->d_work + off, n, g, s);
+      return launch_legendre(prec, false, tg, cls, p->d_work + p->off_bf[tg], p->n_bf[tg], g, s);
     }
     case S_RAD_F:
       return launch_radial(prec, false, tg, cls, p->d_work + p->off_cf[tg], p->n_cf[tg], nullptr, out, g, s);
     case S_RAD_I:
       return launch_radial(prec, true, tg, cls, p->d_work + p->off_ci[tg], p->n_ci[tg], in, nullptr, g, s);
     default: {
-      const int off = slab ? slab->off_bi[tg] : p->off_bi[tg], n = slab ? slab->n_bi[tg] : p->n_bi[tg];
-      hipError_t e = launch_legendre(prec, true, tg, cls, p->d_work + off, n, g, s);
+      hipError_t e = launch_legendre(prec, true, tg, cls, p->d_work + p->off_bi[tg], p->n_bi[tg], g, s);
       if (e != hipSuccess || !p->seminaive()) return e;
       return launch_dct(prec == PREC_F64 ? PREC_F64 : PREC_F32, true, cls, p->d_work + p->off_dct, p->n_dct,
                         p->dct_lds, p->dct_cols, s);
@@ -743,53 +659,22 @@ hipError_t launch_slot(sgl_plan_s* p, int slot, const void* in, void* out, hipSt
   }
 }
 
-// Work items of a slot's launch (whole list or one slab's sub-list).
-int slot_items(const sgl_plan_s* p, int slot, const sgl_plan_s::Slab* slab) {
-  if (!slab) return slot_work(p, slot);
-  const int tg = p->tile[slot];
-  switch (slot) {
-    case S_FFT_F0: case S_FFT_I0: return slab->n_am[0];
-    case S_FFT_F1: case S_FFT_I1: return slab->n_am[1];
-    case S_FFT_F2: case S_FFT_I2: return slab->n_am[2];
-    case S_LEG_F: return slab->n_bf[tg];
-    case S_LEG_I: return slab->n_bi[tg];
-    default: return 0;
-  }
-}
-
-// Stage launches of one direction.  Whole schedule: one launch per slot over
-// all classes.  Slab schedule: forward, per slab the FFT then the Legendre
-// launch, then one radial launch; inverse, one radial launch, then per slab
-// the Legendre then the FFT launch.  With timing on, events bracket each run of
-// consecutive launches of one stage.
+// Stage launches of one direction, one per slot with work.  With timing on,
+// events bracket each run of consecutive launches of one stage.
 hipError_t launch_sequence(sgl_plan_s* p, int dir, const void* in, void* out, hipStream_t s, bool timed) {
   int open_stage = -1;
-  auto one = [&](int slot, int st, const sgl_plan_s::Slab* slab) -> hipError_t {
-    if (slot_items(p, slot, slab) == 0) return hipSuccess;
+  for (int q = 0; q < 5; ++q) {
+    const int slot = kSeq[dir][q];
+    if (slot_work(p, slot) == 0) continue;
+    const int st = kStage[dir][q];
     if (timed && st != open_stage) {
       if (open_stage >= 0) time_end(p, open_stage, s);
       time_begin(p, st, s);
       open_stage = st;
     }
-    return launch_slot(p, slot, in, out, s, slab);
-  };
-  hipError_t e = hipSuccess;
-  if (!p->use_slabs) {
-    for (int q = 0; q < 5 && e == hipSuccess; ++q) e = one(kSeq[dir][q], kStage[dir][q], nullptr);
-  } else if (dir == 0) {
-    for (const auto& z : p->slabs) {
-      for (int md = 0; md < 3 && e == hipSuccess; ++md) e = one(S_FFT_F0 + md, 0, &z);
-      if (e == hipSuccess) e = one(S_LEG_F, 1, &z);
-    }
-    if (e == hipSuccess) e = one(S_RAD_F, 2, nullptr);
-  } else {
-    e = one(S_RAD_I, 3, nullptr);
-    for (const auto& z : p->slabs) {
-      if (e == hipSuccess) e = one(S_LEG_I, 4, &z);
-      for (int md = 0; md < 3 && e == hipSuccess; ++md) e = one(S_FFT_I0 + md, 5, &z);
-    }
+    hipError_t e = launch_slot(p, slot, in, out, s);
+    if (e != hipSuccess) return e;
   }
-  if (e != hipSuccess) return e;
   if (timed && open_stage >= 0) time_end(p, open_stage, s);
   return hipSuccess;
 }
@@ -849,10 +734,10 @@ int slot_geometries(const sgl_plan_s* p, int slot) {
 
 // Plan-time autotuner: for every launch slot, time each tile geometry the slot
 // has with the persistent grid bounds {1, 2, 4, 8, 16} x CUs and "one block per
-// work item" on scratch buffers, and keep the fastest pair.  The candidates are
-// timed in three interleaved rounds (a warm-up launch and three timed launches
-// each) and each keeps its best round, so that clock drift during tuning does
-// not favour the candidates timed first.
+// work item" on scratch buffers (three interleaved rounds of a warm-up launch
+// and three timed launches, each candidate keeping its best round, so that
+// clock drift during tuning does not favour the candidates timed first), then
+// choose between each slot's two fastest inside whole transform pairs.
 sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
   int dev = 0, ncu = 256;
   SGL_HIP_TRY(hipGetDevice(&dev));
@@ -867,13 +752,14 @@ sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
   SGL_HIP_TRY(hipEventCreate(&e0));
   SGL_HIP_TRY(hipEventCreate(&e1));
   sgl_status_t st = SGL_OK;
+  struct Cand { int tg, grid; };
+  std::vector<std::vector<Cand>> shortlist(NSLOT);  // the two fastest candidates of each slot
   for (int slot = 0; slot < NSLOT && st == SGL_OK; ++slot) {
     const int n = slot_work(p, slot);
     if (n == 0) continue;
     const bool inv = slot >= S_RAD_I;  // inverse slots read coefficients, write samples
     const void* in = inv ? tout : tin;
     void* out = inv ? tin : tout;
-    struct Cand { int tg, grid; };
     std::vector<Cand> cand;
     for (int tg = 0; tg < slot_geometries(p, slot); ++tg) {
       p->tile[slot] = tg;
@@ -902,21 +788,27 @@ sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
         tbest[ci] = std::min(tbest[ci], ms);
       }
     }
-    size_t bi = 0;
-    for (size_t ci = 1; ci < cand.size(); ++ci)
-      if (tbest[ci] < tbest[bi]) bi = ci;
-    p->tile[slot] = cand[bi].tg;
-    p->grid[slot] = cand[bi].grid;
+    std::vector<size_t> order(cand.size());
+    for (size_t ci = 0; ci < cand.size(); ++ci) order[ci] = ci;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return tbest[a] < tbest[b]; });
+    for (size_t k = 0; k < order.size() && k < 2; ++k) shortlist[slot].push_back(cand[order[k]]);
+    p->tile[slot] = cand[order[0]].tg;
+    p->grid[slot] = cand[order[0]].grid;
   }
-  // launch schedule (whole stages, or slabs when some class splits), timed as
-  // forward + inverse pairs
-  if (st == SGL_OK && p->slab_max_cols > 0) {
+  // In context: a launch timed alone does not show what its grid and tile do
+  // to the neighbouring stages (cache contents, the tail of one launch against
+  // the start of the next), so the two fastest candidates of each slot are
+  // timed again inside whole forward + inverse pairs (one warm-up pair, two
+  // timed, two interleaved rounds), one slot at a time, and the faster kept.
+  for (int slot = 0; slot < NSLOT && st == SGL_OK; ++slot) {
+    if (shortlist[slot].size() < 2) continue;
     float tb[2] = {1e30f, 1e30f};
-    for (int round = 0; round < 3 && st == SGL_OK; ++round)
-      for (int sch = 0; sch < 2; ++sch) {
-        p->use_slabs = sch == 1;
+    for (int round = 0; round < 2 && st == SGL_OK; ++round)
+      for (int c = 0; c < 2; ++c) {
+        p->tile[slot] = shortlist[slot][c].tg;
+        p->grid[slot] = shortlist[slot][c].grid;
         hipError_t e = hipSuccess;
-        for (int r = 0; r < 4 && e == hipSuccess; ++r) {  // a warm-up pair, then three timed
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
           if (r == 1) e = hipEventRecord(e0, s);
           if (e == hipSuccess) e = launch_sequence(p, 0, tin, tout, s, false);
           if (e == hipSuccess) e = launch_sequence(p, 1, tout, tin, s, false);
@@ -930,9 +822,11 @@ sgl_status_t autotune(sgl_plan_s* p, hipStream_t s) {
           st = SGL_ERR_HIP;
           break;
         }
-        tb[sch] = std::min(tb[sch], ms);
+        tb[c] = std::min(tb[c], ms);
       }
-    p->use_slabs = tb[1] < tb[0];
+    const int c = tb[1] < tb[0] ? 1 : 0;
+    p->tile[slot] = shortlist[slot][c].tg;
+    p->grid[slot] = shortlist[slot][c].grid;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1133,12 +1027,12 @@ sgl_status_t sgl_forward_noalloc(sgl_plan_t plan, const void* d_samples, void* d
     set_error("sgl_forward_noalloc must run on the device its plan was created on");
     return SGL_ERR_INVALID_ARG;
   }
-  // the whole schedule's launches, eager (no graph), on the static workspace
+  // the stage launches, eager (no graph), on the static workspace
   const hipStream_t s = (hipStream_t)stream;
   for (int q = 0; q < 5; ++q) {
     const int slot = kSeq[0][q];
     if (slot_work(plan, slot) == 0) continue;
-    SGL_HIP_TRY(launch_slot(plan, slot, d_samples, d_coeffs, s, nullptr, plan->d_cls_static));
+    SGL_HIP_TRY(launch_slot(plan, slot, d_samples, d_coeffs, s, plan->d_cls_static));
   }
   return SGL_OK;
 }
@@ -1229,28 +1123,6 @@ sgl_status_t sgl_set_launch_tile(sgl_plan_t plan, int slot, int geometry) {
   if (plan->tile[slot] != geometry) {
     plan->tile[slot] = geometry;
     // captured graphs hold the previous kernels and work lists
-    for (auto& g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
-    plan->graphs.clear();
-  }
-  return SGL_OK;
-}
-
-sgl_status_t sgl_launch_schedule(sgl_plan_t plan, int* slabs, int* nslab, int* slab_columns) {
-  if (!plan) { set_error("null plan"); return SGL_ERR_INVALID_ARG; }
-  if (slabs) *slabs = plan->use_slabs ? 1 : 0;
-  if (nslab) *nslab = (int)plan->slabs.size();
-  if (slab_columns) *slab_columns = plan->slab_max_cols;
-  return SGL_OK;
-}
-
-sgl_status_t sgl_set_launch_schedule(sgl_plan_t plan, int slabs) {
-  if (!plan || (slabs != 0 && slabs != 1)) { set_error("bad argument"); return SGL_ERR_INVALID_ARG; }
-  if (slabs && plan->slab_max_cols == 0) {
-    set_error("no class of this plan splits into slabs");
-    return SGL_ERR_UNSUPPORTED;
-  }
-  if (plan->use_slabs != (slabs == 1)) {
-    plan->use_slabs = slabs == 1;
     for (auto& g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
     plan->graphs.clear();
   }

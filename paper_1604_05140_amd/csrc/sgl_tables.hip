@@ -3,22 +3,33 @@
 // precision of the contraction stages.
 //
 // Half-range Gauss-Hermite rule of order N (Thm. 3.3).  The paper computes it
-// with special recurrences in high-precision arithmetic and does not give the
-// procedure; here it is computed in FP64 on the GPU:
+// with special recurrences in high-precision arithmetic and stores the values
+// in double precision; it does not give the procedure.  Here it is computed on
+// the GPU in double-double arithmetic (about 106 bits) and rounded once to FP64:
 //   1. discretize the weight exp(-r^2) dr on [0, T] by composite 32-point
 //      Gauss-Legendre panels (width min(0.5, 40/N), halved repeatedly towards
 //      r = 0 where the zeros of p_N crowd; T = 1.6 sqrt(N) + 8);
 //   2. run the Lanczos iteration on diag(x) with the square-root weights as
-//      start vector: its recurrence coefficients alpha_k, beta_k (k < N) equal
-//      those of the continuous weight to rounding (the start vector is carried
-//      times e^300 so that no entry underflows out to r = T);
-//   3. nodes r_i = zeros of p_N: Sturm-sequence bisection on the Jacobi matrix,
-//      then Newton on p_N evaluated by the three-term recurrence;
-//   4. weights a_i = 1 / sum_k phat_k(r_i)^2 (orthonormal phat_k), formed in
-//      log space because a_i underflows FP64 for N >~ 280.
+//      start vector, in double-double: its recurrence coefficients alpha_k,
+//      beta_k (k < N) are those of the continuous weight up to the FP64
+//      rounding of the discretization (the start vector is carried times e^300
+//      so that no entry underflows out to r = T);
+//   3. nodes r_i = zeros of p_N: Sturm-sequence bisection on the Jacobi matrix
+//      in FP64, then Newton on p_N evaluated by the three-term recurrence in
+//      double-double;
+//   4. weights a_i = 1 / sum_k phat_k(r_i)^2 (orthonormal phat_k) in
+//      double-double, formed in log space because a_i underflows FP64 for
+//      N >~ 280.
 #include <math.h>
 
 #include "sgl_internal.h"
+
+// No floating-point contraction in this file: the double-double arithmetic
+// below relies on every sum and product being rounded separately (a multiply
+// fused into a following add by the compiler breaks its error-free
+// transformations), and the plan-time tables are cheap enough to build with
+// separately rounded operations throughout.
+#pragma clang fp contract(off)
 
 namespace sgl {
 
@@ -27,6 +38,71 @@ namespace {
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kGL = 32;           // Gauss-Legendre points per panel
 constexpr double kStartScale = 300.0;  // ln of the start-vector scale
+
+// ---------------------------------------------------------------------------
+// Double-double arithmetic: value = hi + lo with |lo| <= ulp(hi) / 2, from the
+// error-free transformations of a sum (Knuth's two-sum) and of a product (FMA).
+// ---------------------------------------------------------------------------
+struct dd {
+  double hi, lo;
+};
+__device__ inline dd ddv(double a) { return dd{a, 0.0}; }
+__device__ inline dd two_sum(double a, double b) {
+  const double s = a + b, bb = s - a;
+  return dd{s, (a - (s - bb)) + (b - bb)};
+}
+__device__ inline dd fast_two_sum(double a, double b) {  // |a| >= |b| or a == 0
+  const double s = a + b;
+  return dd{s, b - (s - a)};
+}
+__device__ inline dd operator+(dd x, dd y) {
+  dd s = two_sum(x.hi, y.hi);
+  const dd t = two_sum(x.lo, y.lo);
+  s = fast_two_sum(s.hi, s.lo + t.hi);
+  return fast_two_sum(s.hi, s.lo + t.lo);
+}
+__device__ inline dd operator-(dd x) { return dd{-x.hi, -x.lo}; }
+__device__ inline dd operator-(dd x, dd y) { return x + (-y); }
+__device__ inline dd operator*(dd x, dd y) {
+  const double p = x.hi * y.hi;
+  double e = fma(x.hi, y.hi, -p);
+  e = fma(x.hi, y.lo, e);
+  e = fma(x.lo, y.hi, e);
+  return fast_two_sum(p, e);
+}
+__device__ inline dd operator*(dd x, double y) {
+  const double p = x.hi * y;
+  return fast_two_sum(p, fma(x.lo, y, fma(x.hi, y, -p)));
+}
+__device__ inline dd dd_div(dd x, dd y) {
+  const double q1 = x.hi / y.hi;
+  dd r = x - y * q1;
+  const double q2 = r.hi / y.hi;
+  r = r - y * q2;
+  const double q3 = r.hi / y.hi;
+  return fast_two_sum(q1, q2) + ddv(q3);
+}
+__device__ inline dd dd_sqrt(dd x) {  // x > 0: one Newton step from the FP64 root
+  const double s = sqrt(x.hi);
+  const dd r = x - ddv(s) * ddv(s);
+  return fast_two_sum(s, r.hi / (2.0 * s));
+}
+__device__ inline dd dd_scale(dd x, int e) { return dd{ldexp(x.hi, e), ldexp(x.lo, e)}; }  // exact
+// e^x for |x| < 700: x = k ln2 + r with |r| <= ln2 / 2, e^(r / 1024) - 1 by its
+// Taylor series (nine terms reach 1e-33), squared back ten times as
+// s <- 2 s + s^2 (s = e^t - 1), then scaled by 2^k.
+__device__ inline dd dd_exp(dd x) {
+  const dd ln2{0.6931471805599453, 2.3190468138462996e-17};
+  const double k = rint(x.hi / ln2.hi);
+  const dd r = dd_scale(x - ln2 * k, -10);
+  dd term = r, sum = r;
+  for (int n = 2; n <= 9; ++n) {
+    term = dd_div(term * r, ddv((double)n));
+    sum = sum + term;
+  }
+  for (int q = 0; q < 10; ++q) sum = dd_scale(sum, 1) + sum * sum;
+  return dd_scale(sum + ddv(1.0), (int)k);
+}
 
 // ---------------------------------------------------------------------------
 // S^2 grid: theta_j and b~_j = (pi/B) b_j (Thm. 3.1 with the azimuthal step)
@@ -41,106 +117,126 @@ __global__ void k_polar(int B, double* theta, double* btilde) {
   btilde[j] = (kPi / B) * sinpi(q) * (2.0 / B) * s;
 }
 
-// 32-point Gauss-Legendre rule on [-1, 1] by Newton on P_32.
-__global__ void k_gauss_legendre(double* x, double* w) {
-  int i = threadIdx.x;
-  if (i >= kGL) return;
-  const int n = kGL;
-  double z = cos(kPi * (i + 0.75) / (n + 0.5));
-  double dp = 1.0;
-  for (int it = 0; it < 100; ++it) {
-    double p0 = 1.0, p1 = z;
-    for (int k = 2; k <= n; ++k) {
-      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-      p0 = p1;
-      p1 = p2;
-    }
-    dp = n * (z * p1 - p0) / (z * z - 1.0);
-    double dz = p1 / dp;
-    z -= dz;
-    if (fabs(dz) < 1e-17) break;
-  }
-  // recompute the derivative at the converged point
-  double p0 = 1.0, p1 = z;
+// 32-point Gauss-Legendre rule on [-1, 1] by Newton on P_32, in double-double
+// (the FP64 weight formula loses up to ~5e-15 to cancellation).
+__device__ inline void legendre32(dd z, dd& p, dd& dp) {
+  constexpr int n = kGL;
+  dd p0 = ddv(1.0), p1 = z;
   for (int k = 2; k <= n; ++k) {
-    double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+    const dd p2 = dd_div(z * p1 * (2.0 * k - 1.0) - p0 * (k - 1.0), ddv((double)k));
     p0 = p1;
     p1 = p2;
   }
-  dp = n * (z * p1 - p0) / (z * z - 1.0);
+  p = p1;
+  dp = dd_div((z * p1 - p0) * (double)n, z * z - ddv(1.0));
+}
+__global__ void k_gauss_legendre(dd* x, dd* w) {
+  int i = threadIdx.x;
+  if (i >= kGL) return;
+  dd z = ddv(cos(kPi * (i + 0.75) / (kGL + 0.5)));
+  dd p, dp;
+  for (int it = 0; it < 100; ++it) {
+    legendre32(z, p, dp);
+    const dd dz = dd_div(p, dp);
+    z = z - dz;
+    if (fabs(dz.hi) < 1e-32) break;
+  }
+  legendre32(z, p, dp);
   x[i] = z;
-  w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  w[i] = dd_div(ddv(2.0), (ddv(1.0) - z * z) * dp * dp);
 }
 
-// Discretized weight: points xs and start vector vs = sqrt(w) e^{C - x^2/2}.
-__global__ void k_discretize(int npanel, const double* edges, const double* glx, const double* glw, double* xs,
-                             double* vs) {
+// Discretized weight, in double-double: points xs and start vector
+// vs = sqrt(w) e^{C - x^2/2} (the relative errors of FP64 points and weights,
+// ~1e-16 each, would move the recurrence coefficients by ~1e-16 and the
+// smallest nodes by ~1e-16 ||J|| / r_0 relative).
+__global__ void k_discretize(int npanel, const double* edges, const dd* glx, const dd* glw, dd* xs, dd* vs) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= npanel * kGL) return;
   int p = idx / kGL, q = idx % kGL;
-  double a = edges[p], b = edges[p + 1];
-  double h = b - a;
-  double xx = a + (glx[q] + 1.0) * 0.5 * h;
-  xs[idx] = xx;
-  vs[idx] = sqrt(glw[q] * 0.5 * h) * exp(kStartScale - 0.5 * xx * xx);
+  const double a = edges[p], b = edges[p + 1];
+  const dd hh = dd_scale(two_sum(b, -a), -1);  // half the panel width
+  const dd x = ddv(a) + (glx[q] + ddv(1.0)) * hh;
+  xs[idx] = x;
+  const dd arg = ddv(kStartScale) - dd_scale(x * x, -1);
+  vs[idx] = dd_sqrt(glw[q] * hh) * dd_exp(arg);
 }
 
 template <int NT>
-__device__ double block_sum(double v, double* red) {
-  // wave reduction then cross-wave through LDS
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x < NT / 64) t = red[threadIdx.x];
-  if (threadIdx.x < 64) {
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+__device__ dd block_sum_dd(dd v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const dd o{__shfl_down(v.hi, off, 64), __shfl_down(v.lo, off, 64)};
+    v = v + o;
   }
-  if (threadIdx.x == 0) red[16] = t;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
-  return red[16];
+  if (lane == 0) {
+    red[2 * wid] = v.hi;
+    red[2 * wid + 1] = v.lo;
+  }
+  __syncthreads();
+  dd t = ddv(0.0);
+  if (threadIdx.x < NT / 64) t = dd{red[2 * threadIdx.x], red[2 * threadIdx.x + 1]};
+  if (threadIdx.x < 64) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const dd o{__shfl_down(t.hi, off, 64), __shfl_down(t.lo, off, 64)};
+      t = t + o;
+    }
+  }
+  if (threadIdx.x == 0) {
+    red[64] = t.hi;
+    red[65] = t.lo;
+  }
+  __syncthreads();
+  return dd{red[64], red[65]};
 }
 
-// Lanczos on diag(xs) with start vector vs (one block).  Produces the monic
-// recurrence coefficients alpha_k, beta_k (k < N), beta_0 = mu_0 = sqrt(pi)/2.
+// Lanczos on diag(xs) with start vector vs (one block), in double-double.
+// Produces the monic recurrence coefficients alpha_k, beta_k (k < N) and
+// sqrt(beta_k), each as (hi, lo) pairs; beta_0 = mu_0 = sqrt(pi)/2.  qa, qb:
+// 2M doubles each (the Lanczos vectors as hi, lo pairs).
 constexpr int kLanczosThreads = 1024;
-__global__ void __launch_bounds__(kLanczosThreads) k_lanczos(int M, int N, const double* xs, const double* vs,
-                                                             double* qa, double* qb, double* alpha,
-                                                             double* beta) {
-  __shared__ double red[32];
+__global__ void __launch_bounds__(kLanczosThreads) k_lanczos(int M, int N, const dd* xs, const dd* vs, dd* qa,
+                                                             dd* qb, dd* alpha, dd* beta, dd* sbeta) {
+  __shared__ double red[66];
   const int t = threadIdx.x;
-  double ss = 0.0;
-  for (int i = t; i < M; i += kLanczosThreads) ss += vs[i] * vs[i];
-  double nrm = sqrt(block_sum<kLanczosThreads>(ss, red));
+  dd ss = ddv(0.0);
+  for (int i = t; i < M; i += kLanczosThreads) ss = ss + vs[i] * vs[i];
+  const dd inv = dd_div(ddv(1.0), dd_sqrt(block_sum_dd<kLanczosThreads>(ss, red)));
   for (int i = t; i < M; i += kLanczosThreads) {
-    qa[i] = vs[i] / nrm;  // q_0
-    qb[i] = 0.0;          // q_{-1}
+    qa[i] = inv * vs[i];  // q_0
+    qb[i] = ddv(0.0);     // q_{-1}
   }
-  if (t == 0) beta[0] = 0.88622692545275801364908374167057259;  // sqrt(pi)/2
+  if (t == 0) {
+    beta[0] = dd{0.886226925452758, -3.8332932499128993e-17};  // sqrt(pi) / 2 to 106 bits
+    sbeta[0] = dd_sqrt(beta[0]);
+  }
   __syncthreads();
-  double sb = 0.0;  // sqrt(beta_k)
-  double* qc = qa;
-  double* qp = qb;
+  dd sb = ddv(0.0);  // sqrt(beta_k)
+  dd* qc = qa;
+  dd* qp = qb;
   for (int k = 0; k < N; ++k) {
-    double part = 0.0;
-    for (int i = t; i < M; i += kLanczosThreads) part += xs[i] * qc[i] * qc[i];
-    const double a = block_sum<kLanczosThreads>(part, red);
-    double part2 = 0.0;
+    dd part = ddv(0.0);
+    for (int i = t; i < M; i += kLanczosThreads) part = part + (qc[i] * qc[i]) * xs[i];
+    const dd a = block_sum_dd<kLanczosThreads>(part, red);
+    dd part2 = ddv(0.0);
     for (int i = t; i < M; i += kLanczosThreads) {
-      double u = (xs[i] - a) * qc[i] - sb * qp[i];
+      const dd u = (xs[i] - a) * qc[i] - sb * qp[i];
       qp[i] = u;  // overwrite q_{k-1} with the unnormalized q_{k+1}
-      part2 += u * u;
+      part2 = part2 + u * u;
     }
-    const double nb = sqrt(block_sum<kLanczosThreads>(part2, red));
-    for (int i = t; i < M; i += kLanczosThreads) qp[i] /= nb;
+    const dd nb = dd_sqrt(block_sum_dd<kLanczosThreads>(part2, red));
+    const dd rn = dd_div(ddv(1.0), nb);
+    for (int i = t; i < M; i += kLanczosThreads) qp[i] = qp[i] * rn;
     if (t == 0) {
       alpha[k] = a;
-      if (k + 1 < N) beta[k + 1] = nb * nb;
+      if (k + 1 < N) {
+        beta[k + 1] = nb * nb;
+        sbeta[k + 1] = nb;
+      }
     }
     __syncthreads();
-    double* tmp = qc;
+    dd* tmp = qc;
     qc = qp;
     qp = tmp;
     sb = nb;
@@ -148,30 +244,31 @@ __global__ void __launch_bounds__(kLanczosThreads) k_lanczos(int M, int N, const
 }
 
 // Number of eigenvalues of the Jacobi matrix below x (Sturm sequence via LDL^T).
-__device__ int sturm_count(int N, const double* alpha, const double* beta, double x) {
+__device__ int sturm_count(int N, const dd* alpha, const dd* beta, double x) {
   int cnt = 0;
-  double d = alpha[0] - x;
+  double d = alpha[0].hi - x;
   if (d == 0.0) d = -1e-300;
   if (d < 0) ++cnt;
   for (int k = 1; k < N; ++k) {
-    d = (alpha[k] - x) - beta[k] / d;
+    d = (alpha[k].hi - x) - beta[k].hi / d;
     if (d == 0.0) d = -1e-300;
     if (d < 0) ++cnt;
   }
   return cnt;
 }
 
-// One thread per node: bisection + Newton, then the Christoffel weight in log form.
-__global__ void k_radial_nodes(int N, const double* alpha, const double* beta, double* r, double* log_a,
-                               int* status) {
+// One thread per node: FP64 bisection, Newton in double-double, then the
+// Christoffel weight in log form (double-double sums).
+__global__ void k_radial_nodes(int N, const dd* alpha, const dd* beta, const dd* sbeta, double* r, double* log_a,
+                               double* sig_m, double* sig_e, int* status) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   // Gershgorin bound
   double hi = 0.0;
   for (int k = 0; k < N; ++k) {
-    double e0 = k > 0 ? sqrt(beta[k]) : 0.0;
-    double e1 = k + 1 < N ? sqrt(beta[k + 1]) : 0.0;
-    hi = fmax(hi, alpha[k] + e0 + e1);
+    double e0 = k > 0 ? sbeta[k].hi : 0.0;
+    double e1 = k + 1 < N ? sbeta[k + 1].hi : 0.0;
+    hi = fmax(hi, alpha[k].hi + e0 + e1);
   }
   double lo = 0.0;  // the weight lives on [0, inf): all zeros are positive
   for (int it = 0; it < 200; ++it) {
@@ -182,62 +279,74 @@ __global__ void k_radial_nodes(int N, const double* alpha, const double* beta, d
     else
       lo = mid;
   }
-  // Newton on p_N / p_N' with running rescaling (the ratio is scale free).
-  double x = 0.5 * (lo + hi);
-  // The Sturm count is accurate to about eps * ||J|| in absolute terms, so the
-  // bisection value can be that far from the zero; Newton may move it within a
-  // window that is still far below the spacing of neighbouring zeros.
+  // Newton on p_N / p_N' with running rescaling by powers of two (exact; the
+  // ratio is scale free).  The Sturm count is accurate to about eps ||J|| in
+  // absolute terms, so the bisection value can be that far from the zero;
+  // Newton may move it within a window still far below the spacing of
+  // neighbouring zeros.
+  dd x = ddv(0.5 * (lo + hi));
   double gmax = 0.0;
-  for (int k = 0; k < N; ++k) gmax = fmax(gmax, fabs(alpha[k]) + 2.0 * sqrt(beta[k < N - 1 ? k + 1 : k]));
+  for (int k = 0; k < N; ++k) gmax = fmax(gmax, fabs(alpha[k].hi) + 2.0 * sbeta[k < N - 1 ? k + 1 : k].hi);
   const double win = 1e-9 * gmax + 4.0 * (hi - lo);
-  const double blo = x - win, bhi = x + win;
-  for (int it = 0; it < 6; ++it) {
-    double p0 = 0.0, p1 = 1.0, d0 = 0.0, d1 = 0.0;
+  const double blo = x.hi - win, bhi = x.hi + win;
+  for (int it = 0; it < 12; ++it) {
+    dd p0 = ddv(0.0), p1 = ddv(1.0), d0 = ddv(0.0), d1 = ddv(0.0);
     for (int k = 0; k < N; ++k) {
-      double p2 = (x - alpha[k]) * p1 - (k > 0 ? beta[k] * p0 : 0.0);
-      double d2 = p1 + (x - alpha[k]) * d1 - (k > 0 ? beta[k] * d0 : 0.0);
+      const dd xa = x - alpha[k];
+      dd p2 = xa * p1, d2 = p1 + xa * d1;
+      if (k > 0) {
+        p2 = p2 - beta[k] * p0;
+        d2 = d2 - beta[k] * d0;
+      }
       p0 = p1;
       p1 = p2;
       d0 = d1;
       d1 = d2;
-      double m = fmax(fabs(p1), fabs(d1));
-      if (m > 1e150) {
-        p0 *= 1e-150; p1 *= 1e-150; d0 *= 1e-150; d1 *= 1e-150;
+      if (fmax(fabs(p1.hi), fabs(d1.hi)) > 0x1p500) {
+        p0 = dd_scale(p0, -500); p1 = dd_scale(p1, -500); d0 = dd_scale(d0, -500); d1 = dd_scale(d1, -500);
       }
     }
-    if (d1 == 0.0) break;
-    double xn = x - p1 / d1;
-    if (!(xn > blo && xn < bhi)) break;  // keep the bracketed bisection value
-    if (xn == x) break;
+    if (d1.hi == 0.0) break;
+    const dd dx = dd_div(p1, d1);
+    const dd xn = x - dx;
+    if (!(xn.hi > blo && xn.hi < bhi)) break;  // keep the bracketed value
     x = xn;
+    if (fabs(dx.hi) <= 1e-31 * fabs(x.hi)) break;
   }
-  r[i] = x;
+  r[i] = x.hi;
   // a_i = 1 / sum_k phat_k(x)^2 with phat_0 = 1/sqrt(beta_0),
   // sqrt(beta_{k+1}) phat_{k+1} = (x - alpha_k) phat_k - sqrt(beta_k) phat_{k-1}.
-  double ph0 = 0.0, ph1 = 1.0 / sqrt(beta[0]);
-  double s = ph1 * ph1, lscale = 0.0;  // sum = s * e^{lscale}, phat = ph * e^{lscale/2}
+  dd ph0 = ddv(0.0), ph1 = dd_div(ddv(1.0), sbeta[0]);
+  dd sum = ph1 * ph1;
+  int lscale = 0;  // sum = s * 2^lscale, phat = ph * 2^(lscale / 2)
   for (int k = 0; k + 1 < N; ++k) {
-    double ph2 = ((x - alpha[k]) * ph1 - (k > 0 ? sqrt(beta[k]) * ph0 : 0.0)) / sqrt(beta[k + 1]);
+    dd num = (x - alpha[k]) * ph1;
+    if (k > 0) num = num - sbeta[k] * ph0;
+    const dd ph2 = dd_div(num, sbeta[k + 1]);
     ph0 = ph1;
     ph1 = ph2;
-    s += ph1 * ph1;
-    if (s > 1e200) {
-      s *= 1e-200;
-      ph0 *= 1e-100;
-      ph1 *= 1e-100;
-      lscale += 460.51701859880913680;  // ln 1e200
+    sum = sum + ph1 * ph1;
+    if (sum.hi > 0x1p600) {
+      sum = dd_scale(sum, -600);
+      ph0 = dd_scale(ph0, -300);
+      ph1 = dd_scale(ph1, -300);
+      lscale += 600;
     }
   }
-  log_a[i] = -(log(s) + lscale);
-  if (!(x > 0.0) || !isfinite(log_a[i])) atomicOr(status, 1);
+  log_a[i] = -(log(sum.hi) + log1p(sum.lo / sum.hi) + lscale * 0.69314718055994530942);
+  // sigma_i = sqrt(a_i) r_i = r_i / sqrt(sum) * 2^(-lscale/2) (lscale is even): its
+  // mantissa to double-double accuracy and its power-of-two exponent
+  sig_m[i] = (x * dd_div(ddv(1.0), dd_sqrt(sum))).hi;
+  sig_e[i] = -0.5 * lscale;
+  if (!(x.hi > 0.0) || !isfinite(log_a[i])) atomicOr(status, 1);
 }
 
-__global__ void k_radial_derived(int N, const double* r, const double* log_a, double* log_sig, double* sig) {
+// ln sigma_i and sigma_i (0 where it underflows) from its mantissa and exponent
+__global__ void k_radial_derived(int N, const double* sig_m, const double* sig_e, double* log_sig, double* sig) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  double ls = 0.5 * log_a[i] + log(r[i]);
-  log_sig[i] = ls;
-  sig[i] = exp(ls);
+  log_sig[i] = log(sig_m[i]) + sig_e[i] * 0.69314718055994530942;
+  sig[i] = ldexp(sig_m[i], (int)sig_e[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -272,6 +381,35 @@ __device__ Ext ext_start(double logv, double sign) {
   return e;
 }
 
+// A double-double mantissa times a power of two (start values that may leave
+// the FP64 range), renormalized so that the mantissa stays near 1.
+struct DdExp {
+  dd m;
+  int e;
+  __device__ void renorm() {
+    int k = 0;
+    (void)frexp(m.hi, &k);
+    m = dd_scale(m, -k);
+    e += k;
+  }
+  __device__ void mul(dd f) {
+    m = m * f;
+    renorm();
+  }
+};
+// Start of a recurrence from an exact-product value: stored directly when it is
+// above 1e-200, else as 1e-200 e^{es} like ext_start (only the tiny values, far
+// below every sum they enter, carry the log-space rounding).
+__device__ Ext ext_from(DdExp v, double sign) {
+  const double lv = log(fabs(v.m.hi)) + v.e * 0.69314718055994530942;
+  if (lv < -460.0) return ext_start(lv, sign);
+  Ext x;
+  x.prev = 0.0;
+  x.es = 0.0;
+  x.cur = sign * ldexp(v.m.hi, v.e);
+  return x;
+}
+
 // Pbar_lm(cos th_j) for l = m..B-1: normalized form of Eq. legendre_recurrence,
 //   Pbar_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)) sin^m th,
 //   Pbar_lm = a_lm (cos th Pbar_{l-1,m} - Pbar_{l-2,m} / a_{l-1,m}),
@@ -280,12 +418,22 @@ __global__ void k_legendre_table(int B, const double* theta, double* P) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= B * 2 * B) return;
   const int m = idx / (2 * B), j = idx % (2 * B);
-  const double th = theta[j];
-  const double t = cos(th);
-  double lp = 0.5 * log((2.0 * m + 1.0) / (4.0 * kPi));
-  for (int k = 1; k <= m; ++k) lp += 0.5 * log((2.0 * k - 1.0) / (2.0 * k));
-  lp += m * log(sin(th));
-  Ext e = ext_start(lp, (m & 1) ? -1.0 : 1.0);
+  // theta_j = pi q with q = (2j+1)/(4B): sine and cosine from q (theta[j] is its FP64 rounding)
+  const double q = (double)(2 * j + 1) / (4.0 * B);
+  const double t = cospi(q), st = sinpi(q);
+  (void)theta;
+  // Pbar_mm as exact products in double-double: (2m+1)/(4 pi) prod (2k-1)/(2k),
+  // square-rooted, times sin^m theta
+  DdExp c{dd{0.07957747154594767, -4.9196691687956215e-18} * (2.0 * m + 1.0), 0};  // (2m+1) / (4 pi)
+  c.renorm();
+  for (int k = 1; k <= m; ++k) c.mul(dd_div(ddv(2.0 * k - 1.0), ddv(2.0 * k)));
+  if (c.e & 1) {
+    c.m = dd_scale(c.m, 1);
+    c.e -= 1;
+  }
+  DdExp v{dd_sqrt(c.m), c.e / 2};
+  for (int k = 0; k < m; ++k) v.mul(ddv(st));
+  Ext e = ext_from(v, (m & 1) ? -1.0 : 1.0);
   double* blk = P + table_block(B, m);
   const int ld = 2 * B;
   blk[j] = e.value();
@@ -305,13 +453,28 @@ __global__ void k_legendre_table(int B, const double* theta, double* P) {
 //   Rhat_{l+1,l} = sqrt(2 / Gamma(l + 3/2)) r^l,  Rhat_{ll} = 0,
 //   Rhat_{n+1,l} = (2n - l - 1/2 - r^2) / sqrt((n + 1/2)(n - l)) Rhat_nl
 //                  - sqrt((n - 1/2)(n - l - 1) / ((n + 1/2)(n - l))) Rhat_{n-1,l}.
-__global__ void k_radial_table(int B, const double* r, const double* log_sig, double* R) {
+// The start is formed as exact products in double-double (the log-space form
+// rounds at the magnitude of l ln r and ln Gamma, ~1e-13 relative at B = 256):
+// sigma_i from the rule, sqrt(c_l) with c_l = 2 / Gamma(l + 3/2) =
+// c_{l-1} 2 / (2l + 1), c_0 = 4 / sqrt(pi), and r_i^l.
+__global__ void k_radial_table(int B, const double* r, const double* sig_m, const double* sig_e, double* R) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= B * 2 * B) return;
   const int l = idx / (2 * B), i = idx % (2 * B);
   const double x = r[i], t = x * x;
-  const double lv = 0.5 * log(2.0) - 0.5 * lgamma(l + 1.5) + l * log(x) + log_sig[i];
-  Ext e = ext_start(lv, 1.0);
+  DdExp c{dd{2.256758334191025, 3.067091922633176e-17}, 0};  // 4 / sqrt(pi)
+  c.renorm();
+  for (int k = 1; k <= l; ++k) c.mul(dd_div(ddv(2.0), ddv(2.0 * k + 1.0)));
+  if (c.e & 1) {
+    c.m = dd_scale(c.m, 1);
+    c.e -= 1;
+  }
+  DdExp v{dd_sqrt(c.m), c.e / 2};
+  v.renorm();
+  for (int k = 0; k < l; ++k) v.mul(ddv(x));
+  v.mul(ddv(sig_m[i]));
+  v.e += (int)sig_e[i];
+  Ext e = ext_from(v, 1.0);
   double* blk = R + table_block(B, l);
   const int ld = 2 * B;
   blk[i] = e.value();
@@ -459,7 +622,11 @@ sgl_status_t build_grid(GridBuild& g, hipStream_t s) {
   const int M = npanel * kGL;
 
   double* buf = nullptr;
-  const size_t nbuf = (size_t)edges.size() + 2 * kGL + 4 * (size_t)M + 2 * (size_t)N;
+  // edges (FP64), then double-double arrays from an even offset (16-byte
+  // aligned): GL nodes and weights, points xs and start vector vs, the two
+  // Lanczos vectors, alpha, beta, sqrt(beta)
+  const size_t off_dd = (edges.size() + 1) / 2 * 2;
+  const size_t nbuf = off_dd + 2 * (2 * (size_t)kGL + 4 * (size_t)M + 3 * (size_t)N);
   SGL_HIP_TRY(dev_malloc((void**)&buf, nbuf * sizeof(double)));
   int* d_status = nullptr;
   hipError_t e = dev_malloc((void**)&d_status, sizeof(int));
@@ -469,14 +636,15 @@ sgl_status_t build_grid(GridBuild& g, hipStream_t s) {
     return SGL_ERR_OOM;
   }
   double* d_edges = buf;
-  double* glx = d_edges + edges.size();
-  double* glw = glx + kGL;
-  double* xs = glw + kGL;
-  double* vs = xs + M;
-  double* qa = vs + M;
-  double* qb = qa + M;
-  double* alpha = qb + M;
-  double* beta = alpha + N;
+  dd* glx = reinterpret_cast<dd*>(buf + off_dd);
+  dd* glw = glx + kGL;
+  dd* xs = glw + kGL;
+  dd* vs = xs + M;
+  dd* qa = vs + M;
+  dd* qb = qa + M;
+  dd* alpha = qb + M;
+  dd* beta = alpha + N;
+  dd* sbeta = beta + N;
   sgl_status_t st = SGL_OK;
   int h_status = 0;
   auto fail = [&](hipError_t err, const char* what) {
@@ -489,10 +657,10 @@ sgl_status_t build_grid(GridBuild& g, hipStream_t s) {
     if ((e = hipMemsetAsync(d_status, 0, sizeof(int), s)) != hipSuccess) { fail(e, "memset"); break; }
     hipLaunchKernelGGL(k_gauss_legendre, dim3(1), dim3(64), 0, s, glx, glw);
     hipLaunchKernelGGL(k_discretize, dim3(nblk(M, 256)), dim3(256), 0, s, npanel, d_edges, glx, glw, xs, vs);
-    hipLaunchKernelGGL(k_lanczos, dim3(1), dim3(kLanczosThreads), 0, s, M, N, xs, vs, qa, qb, alpha, beta);
-    hipLaunchKernelGGL(k_radial_nodes, dim3(nblk(N, 64)), dim3(64), 0, s, N, alpha, beta, g.r, g.log_a,
-                       d_status);
-    hipLaunchKernelGGL(k_radial_derived, dim3(nblk(N, 64)), dim3(64), 0, s, N, g.r, g.log_a, g.log_sig, g.sig);
+    hipLaunchKernelGGL(k_lanczos, dim3(1), dim3(kLanczosThreads), 0, s, M, N, xs, vs, qa, qb, alpha, beta, sbeta);
+    hipLaunchKernelGGL(k_radial_nodes, dim3(nblk(N, 64)), dim3(64), 0, s, N, alpha, beta, sbeta, g.r, g.log_a,
+                       g.sig_m, g.sig_e, d_status);
+    hipLaunchKernelGGL(k_radial_derived, dim3(nblk(N, 64)), dim3(64), 0, s, N, g.sig_m, g.sig_e, g.log_sig, g.sig);
     if ((e = hipGetLastError()) != hipSuccess) { fail(e, "grid kernels"); break; }
     if ((e = hipMemcpyAsync(&h_status, d_status, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) {
       fail(e, "copy status"); break;
@@ -508,11 +676,10 @@ sgl_status_t build_grid(GridBuild& g, hipStream_t s) {
   return st;
 }
 
-hipError_t build_tables(int B, const double* r, const double* log_sig, const double* theta, double* P64,
-                        double* R64, hipStream_t s) {
+hipError_t build_tables(int B, const GridBuild& g, double* P64, double* R64, hipStream_t s) {
   const int n = B * 2 * B;
-  hipLaunchKernelGGL(k_legendre_table, dim3(nblk(n, 128)), dim3(128), 0, s, B, theta, P64);
-  hipLaunchKernelGGL(k_radial_table, dim3(nblk(n, 128)), dim3(128), 0, s, B, r, log_sig, R64);
+  hipLaunchKernelGGL(k_legendre_table, dim3(nblk(n, 128)), dim3(128), 0, s, B, g.theta, P64);
+  hipLaunchKernelGGL(k_radial_table, dim3(nblk(n, 128)), dim3(128), 0, s, B, g.r, g.sig_m, g.sig_e, R64);
   return hipGetLastError();
 }
 

@@ -36,16 +36,6 @@ __device__ inline void store_stream(SGL_G T2* p, T2 v) {
   __builtin_nontemporal_store(v.x, &p->x);
   __builtin_nontemporal_store(v.y, &p->y);
 }
-// Store of a spectrum value: streaming, except in the slab schedule (keep != 0),
-// where the next launch reads the slab back while it is still held by the
-// last-level (Infinity) cache, so the line is stored with the default policy.
-template <typename T2>
-__device__ inline void store_spectrum(SGL_G T2* p, T2 v, int keep) {
-  if (keep)
-    *p = v;
-  else
-    store_stream(p, v);
-}
 // Streaming load (non-temporal) of a value read once: the spectrum rows and the
 // samples are larger than the caches, and streaming them keeps the smaller
 // stage (b)/(c) intermediates cached between their launches.

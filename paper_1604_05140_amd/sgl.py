@@ -70,9 +70,6 @@ def _load():
         "sgl_launch_grids": ([P, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "sgl_launch_tiles": ([P, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "sgl_set_launch_tile": ([P, ctypes.c_int, ctypes.c_int], ctypes.c_int),
-        "sgl_launch_schedule": ([P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                 ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
-        "sgl_set_launch_schedule": ([P, ctypes.c_int], ctypes.c_int),
         "sgl_stage_times": ([P, dp, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "sgl_debug_gemm": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P], ctypes.c_int),
         "sgl_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -98,7 +95,7 @@ _HEADER_NAMES = [
     "sgl_set_timing", "sgl_stage_times", "sgl_debug_gemm", "sgl_status_string", "sgl_last_error",
     "sgl_launch_grids", "sgl_naive_forward", "sgl_naive_inverse", "sgl_plan_scaled",
     "sgl_midpoint_forward", "sgl_synthesize_points", "sgl_launch_tiles", "sgl_set_launch_tile",
-    "sgl_launch_schedule", "sgl_set_launch_schedule", "sgl_forward_noalloc",
+    "sgl_forward_noalloc",
 ]
 
 
@@ -187,16 +184,6 @@ class Plan:
 
     def set_launch_tile(self, slot: int, geometry: int):
         _check(_load().sgl_set_launch_tile(self._h, int(slot), int(geometry)), "sgl_set_launch_tile")
-
-    def launch_schedule(self):
-        """(slab schedule in use, number of slabs, widest slab in columns)."""
-        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(_load().sgl_launch_schedule(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
-               "sgl_launch_schedule")
-        return a.value, b.value, c.value
-
-    def set_launch_schedule(self, slabs: int):
-        _check(_load().sgl_set_launch_schedule(self._h, int(slabs)), "sgl_set_launch_schedule")
 
     def set_timing(self, enable: bool):
         _check(_load().sgl_set_timing(self._h, 1 if enable else 0), "sgl_set_timing")

@@ -76,18 +76,20 @@ def test_gemm_core(dtype, tol, M, K, N):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("B", [1, 2, 8, 17, 64, 128, 256])
 def test_grid_matches_oracle(B):
+    """The GPU rule (double-double Lanczos, Newton and Christoffel sums, rounded
+    once to FP64) against the oracle's 40-digit rule rounded to FP64: nodes to a
+    few units in the last place, ln a_i to a few ulps of its magnitude."""
     plan = sgl.sgl_plan(B, 1, "f64")
     g = plan.grid(B)
     o = Q.sgl_grid(B)
-    # FP64 recurrence coefficients are accurate to ~eps relative; the smallest
-    # zeros (r_0 ~ N^-1.5) are the worst conditioned: ~1e-12 relative there,
-    # ~1e-16 absolute, and ~1e-15 relative for all others.
     rel_r = np.abs(g["r"] / o["r"] - 1)
-    assert rel_r.max() < 2e-12, rel_r.max()
-    assert rel_r[4:].max() < 2e-13 if B > 4 else True
-    assert np.abs(g["r"] - o["r"]).max() < 1e-14 * o["r"].max()
-    assert np.abs(g["log_a"] - o["log_a"]).max() < 1e-11 * max(1.0, np.abs(o["log_a"]).max() / 100)
-    assert np.abs(g["log_sigma"] - o["log_sigma"]).max() < 1e-11 * max(1.0, np.abs(o["log_sigma"]).max() / 100)
+    d_la = np.abs(g["log_a"] - o["log_a"]) / np.maximum(1.0, np.abs(o["log_a"]))
+    d_ls = np.abs(g["log_sigma"] - o["log_sigma"]) / np.maximum(1.0, np.abs(o["log_sigma"]))
+    print(f"B={B}: nodes max rel {rel_r.max():.2e}, ln a max {d_la.max():.2e}, ln sigma max {d_ls.max():.2e}",
+          flush=True)
+    assert rel_r.max() < 4e-15, rel_r.max()
+    assert d_la.max() < 4e-15, d_la.max()
+    assert d_ls.max() < 4e-15, d_ls.max()
     assert np.abs(g["theta"] - o["theta"]).max() < 1e-15
     assert np.abs(g["btilde"] / o["btilde"] - 1).max() < 1e-13
     plan.destroy()
@@ -105,16 +107,18 @@ def _oracle_tables(B):
     return np.concatenate(Pt), np.concatenate(Rt)
 
 
-@pytest.mark.parametrize("B", [1, 3, 8, 64, 128])
+@pytest.mark.parametrize("B", [1, 3, 8, 64, 128, 256])
 def test_tables_match_oracle(B):
     plan = sgl.sgl_plan(B, 1, "f64")
     Pg, Rg = plan.table(B, 0), plan.table(B, 1)
     Po, Ro = _oracle_tables(B)
-    # both sides run FP64 recurrences of up to B steps on values up to
-    # sqrt((2B-1)/(4 pi)); rounding grows like B * eps * max|Pbar| (~1e-13 at B=128)
-    assert np.abs(Pg - Po).max() < 1e-12
-    # the radial table inherits the ~1e-12 relative error of the smallest nodes
-    assert np.abs(Rg - Ro).max() < 1e-12
+    dP, dR = np.abs(Pg - Po).max(), np.abs(Rg - Ro).max()
+    print(f"B={B}: Legendre table max abs diff {dP:.2e}, radial table {dR:.2e}", flush=True)
+    # both sides run FP64 three-term recurrences of up to B steps on values up
+    # to sqrt((2B-1)/(4 pi)) (Legendre) and 1 (radial, orthonormal rows), in a
+    # different order of operations; rounding grows like B * eps * max|value|
+    assert dP < 2e-15 * B * max(1.0, math.sqrt((2 * B - 1) / (4 * math.pi)))
+    assert dR < 2e-15 * B
     plan.destroy()
 
 
@@ -136,7 +140,7 @@ def test_gpu_radial_rule_is_exact(B):
     for l in range(B):
         blk = R[off:off + (B - l) * 2 * B].reshape(B - l, 2 * B)
         off += (B - l) * 2 * B
-        assert np.abs(blk @ blk.T - np.eye(B - l)).max() < 4e-13, l  # 2B-term FP64 sums
+        assert np.abs(blk @ blk.T - np.eye(B - l)).max() < 1e-13, l  # 2B-term FP64 sums
     plan.destroy()
 
 
