@@ -868,8 +868,12 @@ __device__ inline void bar_only() {
   asm volatile("s_barrier" ::: "memory");
 #endif
 }
-// Wait until at most N of the wave's vector-memory operations are outstanding
-// (they complete in issue order).
+// Wait until at most N of the wave's vector-memory operations are outstanding.
+// The vector-memory counter of the CDNA ISA (VM_CNT, waited on by s_waitcnt
+// vmcnt) counts a wave's vector-memory loads, stores and global-to-LDS loads
+// together and is decremented in the order they were issued (ISA reference,
+// data dependency resolution), so "at most N outstanding" means "all but the
+// last N issued have completed".
 __device__ inline void wait_vm(int n) {
 #if defined(__HIP_DEVICE_COMPILE__)
   if (n == 2)
@@ -1036,6 +1040,10 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
       copy_x(tn, xn, BK, ncn > 1 ? (run + nc + 1) % 3 : 3);
       copy_a(tn, 0, (run + nc) % 2);
     }
+    // The next item's first wait (vmcnt(16) in the inverse) relies on all 16
+    // epilogue stores being issued after these copies: no memory operation may
+    // move across this point.
+    asm volatile("" ::: "memory");
 
     // epilogue: each lane holds re (block 0) and im (block 1) of complex column
     // col0 + wc + lr for rows 4 lk + v of each 16-row block: one 8-byte store
