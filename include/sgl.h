@@ -150,11 +150,14 @@ sgl_status_t sgl_launch_grids(sgl_plan_t plan, int* grids);
  * of stage (c), and stage (b) in SGL_F64 and SGL_F32) have two tile geometries:
  *   geometry 0: 128 rows x 64 complex columns, 8 wavefronts (the default),
  *   geometry 1:  64 rows x 32 complex columns, 4 wavefronts,
- * and SGL_AUTOTUNE times both (with each persistent grid) and keeps the fastest.
+ * and the forward radial slot of SGL_SPLIT_BF16 a third,
+ *   geometry 2: 128 rows x 128 complex columns on the copy-fed kernel
+ *               (operands by global -> LDS copies, 16 wavefronts);
+ * SGL_AUTOTUNE times each (with each persistent grid) and keeps the fastest.
  * The split-form Legendre kernel has one tile, 128 rows x 128 complex columns. */
 sgl_status_t sgl_launch_tiles(sgl_plan_t plan, int* tiles);
 
-/* Select the tile geometry (0 or 1, see sgl_launch_tiles) of one launch slot.
+/* Select the tile geometry (0, 1 or 2, see sgl_launch_tiles) of one launch slot.
  * SGL_ERR_UNSUPPORTED for a geometry the slot does not have; SGL_ERR_INVALID_ARG
  * for a slot outside [0, SGL_NUM_SLOTS).  The slot keeps its persistent-grid
  * bound; graphs the plan captured earlier are dropped (the next call with each

@@ -43,7 +43,10 @@
 // FP32 accumulator per output, smallest products first.
 //
 // The split-form Legendre contractions (both directions) have a kernel of
-// their own, k_legendre_split below, fed by global -> LDS copies.
+// their own, k_legendre_split below, fed by global -> LDS copies; the forward
+// radial contraction of the split form runs on the same design as a third tile
+// geometry (k_radial_split), which the plan-time autotuner weighs against the
+// two of this kernel.
 #include "sgl_internal.h"
 
 namespace sgl {
@@ -773,10 +776,10 @@ k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwo
   }
 }
 
-// ---- split-form Legendre stages: operands by global -> LDS copies ----------
-// The Legendre contractions stream their data operand (the spectrum F forward,
-// the intermediate g inverse) and run at the rate at which the CUs keep bytes
-// in flight.  The register-staged kernel above holds one chunk ahead within
+// ---- split-form Legendre and forward radial stages: operands by global -> LDS
+// copies.  These contractions stream their data operand (the spectrum F and
+// the intermediate g forward, g inverse) and run at the rate at which the CUs
+// keep bytes in flight.  The register-staged kernel above holds one chunk ahead within
 // its register budget.  This kernel moves both operands with 16-byte global ->
 // LDS copies (no registers, no LDS stores): the table through two LDS stages,
 // the data through three, so that the data of the next two chunks are in
@@ -792,10 +795,18 @@ k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwo
 //   table chunk (3 planes x 128 rows x 32 k, 64 bytes a row and plane, in the
 //   swizzled slot order of swz): 24 copies of 1 KB (16 rows of one plane),
 //   copy q by wave q % 16 (waves 0..7 also take q = 16..23);
-//   data chunk (32 rows x 128 complex columns, 1 KB a row as in memory): wave
-//   w copies rows 2w and 2w + 1, lane l the complex column pair 2l, 2l + 1;
-//   rows sit kLRow = 1040 bytes apart, so that rows 8 apart (the k groups of
-//   an MFMA operand read) fall in opposite halves of the LDS banks.
+//   Legendre data chunk (32 rows x 128 complex columns, 1 KB a row as in
+//   memory): wave w copies rows 2w and 2w + 1, lane l the complex column pair
+//   2l, 2l + 1; rows sit kLRow = 1040 bytes apart, so that rows 8 apart (the k
+//   groups of an MFMA operand read) fall in opposite halves of the LDS banks.
+//   Radial data chunk (128 complex columns x 32 k; a column of g runs along k
+//   in memory): LDS row R = 128 s + c holds k = 8s..8s+7 of column c (64
+//   bytes, four 16-byte slots of two k each), slot q at position
+//   q ^ ((R >> 1) & 3) ^ s.  A copy fills 16 rows (16 columns of one s), four
+//   lanes a 64-byte run of a column; the MFMA operand read of lane (column lr,
+//   k group lk) takes the four slots of row 128 lk + c, so its 16-byte reads
+//   fall on the LDS positions of the table reads (row lr, slot lk, which are
+//   free of bank conflicts) up to a fixed relabelling (xor with q).
 // LDS: 2 x 24 KB + 3 x 32.5 KB + one spare row = 147 KB, one block per CU
 // (16 waves, as two 512-thread blocks of the kernel above).
 constexpr int LT = 1024;
@@ -848,6 +859,28 @@ __device__ inline void lds_x8(unsigned a, f2v (&r)[8]) {
       : "memory");
 #endif
 }
+// k 8g..8g+7 of one complex column of a radial data stage: its four 16-byte
+// slots, at the LDS addresses a ^ 16 q (a: row start + 16 x the slot position
+// of q = 0).
+__device__ inline void lds_x4q(unsigned a, f2v (&r)[8]) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const unsigned a1 = a ^ 16u, a2 = a ^ 32u, a3 = a ^ 48u;
+  f4 u0, u1, u2, u3;
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %5\n\t"
+      "ds_read_b128 %2, %6\n\t"
+      "ds_read_b128 %3, %7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(u0), "=&v"(u1), "=&v"(u2), "=&v"(u3)
+      : "v"(a), "v"(a1), "v"(a2), "v"(a3)
+      : "memory");
+  r[0] = f2v{u0[0], u0[1]}; r[1] = f2v{u0[2], u0[3]};
+  r[2] = f2v{u1[0], u1[1]}; r[3] = f2v{u1[2], u1[3]};
+  r[4] = f2v{u2[0], u2[1]}; r[5] = f2v{u2[2], u2[3]};
+  r[6] = f2v{u3[0], u3[1]}; r[7] = f2v{u3[2], u3[3]};
+#endif
+}
 // The three bf16 planes (8192 bytes apart) of one table fragment.
 __device__ inline void lds_a3(unsigned a, u4 (&r)[3]) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -888,13 +921,15 @@ __device__ inline void wait_vm(int n) {
 // target of the epilogue stores that fall outside the group (never read)
 __device__ f2v g_spare_out[64];
 
+// The body of both copy-fed kernels (KIND: K_B_FWD, K_B_INV or K_C_FWD; sm:
+// kLdsL bytes of LDS; coeffs: the coefficient output of K_C_FWD).
 template <int KIND>
-__global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_legendre_split(
-    const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork) {
-  static_assert(KIND == K_B_FWD || KIND == K_B_INV, "Legendre kinds only");
+__device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* __restrict__ cls,
+                                           const int4* __restrict__ work, int nwork, void* __restrict__ coeffs) {
+  static_assert(KIND == K_B_FWD || KIND == K_B_INV || KIND == K_C_FWD, "Legendre kinds and the forward radial kind");
+  constexpr bool RAD = KIND == K_C_FWD;
   constexpr int BK = Cfg<PREC_SPLIT>::BK, PS = Cfg<PREC_SPLIT>::PS;
   static_assert(BK == 32 && PS == 32, "one 16x16x32 MFMA step per chunk, 64-byte table rows");
-  __shared__ __align__(16) unsigned char sm[kLdsL];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 3) * 64, wc = (wave & 7) * 16;
@@ -910,9 +945,14 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
     tt.col0 = work[wi].w * LBNC;
     return tt;
   };
-  // the lane's complex column pair (clamped to the group's last pair, never stored)
+  // the lane's copy source: Legendre, its complex column pair; radial, its
+  // column (clamped to the group's last ones, never stored)
   auto col = [&](const Tile& tt) {
-    return x_col<KIND>(tt, min(tt.col0 + 2 * lane, tt.Ncc - 2), x_base<PREC_SPLIT, KIND>(tt, nullptr));
+    if constexpr (RAD)
+      return x_col<KIND>(tt, min(tt.col0 + (wave & 7) * 16 + (lane >> 2), tt.Ncc - 1),
+                         x_base<PREC_SPLIT, KIND>(tt, nullptr));
+    else
+      return x_col<KIND>(tt, min(tt.col0 + 2 * lane, tt.Ncc - 2), x_base<PREC_SPLIT, KIND>(tt, nullptr));
   };
   // table chunk k0 into stage st (2: the spare row); rows past the block clamp
   // to its last row (they feed outputs that are never stored)
@@ -934,11 +974,22 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
   auto copy_x = [&](const Tile& tt, const XCol<float>& x, int k0, int st) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      const int k = min(k0 + 2 * wave + s, tt.K - 1);
-      // the spectrum is read once: streaming copies keep g cached for stage (c);
-      // g (inverse) is read by both row tiles of a column tile
-      copy16_to_lds<KIND == K_B_FWD>(x.p + 2 * x_off<KIND>(tt, x, k),
-                          sm + (st == 3 ? kLSpare : 2 * kLA + st * kLX + (2 * wave + s) * kLRow));
+      if constexpr (RAD) {
+        // rows 128 sg + 16 (wave & 7) .. + 15 (sg = k group), lane: row + lane / 4, slot
+        // position lane & 3; K = 2B is even, so the clamped pair stays inside the column
+        const int sg = (wave >> 3) + 2 * s;
+        const int q = (lane & 3) ^ ((lane >> 3) & 3) ^ sg;
+        const int k = min(k0 + 8 * sg + 2 * q, tt.K - 2);
+        // g is read once here
+        copy16_to_lds<true>(x.p + 2 * k,
+                            sm + (st == 3 ? kLSpare : 2 * kLA + st * kLX + (128 * sg + 16 * (wave & 7)) * 64));
+      } else {
+        const int k = min(k0 + 2 * wave + s, tt.K - 1);
+        // the spectrum is read once: streaming copies keep g cached for stage (c);
+        // g (inverse) is read by both row tiles of a column tile
+        copy16_to_lds<KIND == K_B_FWD>(x.p + 2 * x_off<KIND>(tt, x, k),
+                            sm + (st == 3 ? kLSpare : 2 * kLA + st * kLX + (2 * wave + s) * kLRow));
+      }
     }
   };
 
@@ -969,7 +1020,7 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
     const int cc = wc + lr;  // the lane's complex column in the tile
     const ClassDesc& C = *t.C;
     // (-1)^m of the -m segment: the contraction is linear, so it is applied to the outputs
-    const float sg = ((t.q & 1) && t.col0 + cc >= C.nf * C.L) ? -1.0f : 1.0f;
+    const float sg = (!RAD && (t.q & 1) && t.col0 + cc >= C.nf * C.L) ? -1.0f : 1.0f;
 
     // Chunk c: the wave waits for its copies of chunk c; one barrier then both
     // publishes every wave's copies and frees the stages of chunk c - 1, into
@@ -986,7 +1037,12 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
       copy_x(t, xc, min(c + 2, nc - 1) * BK, c + 2 < nc ? (run + c + 2) % 3 : 3);
       if (nbj == 0 || nbi == 0) continue;
       f2v r[8];
-      lds_x8(lds_u32(sm + 2 * kLA + ((run + c) % 3) * kLX) + 8 * lk * kLRow + cc * 8, r);
+      if constexpr (RAD) {
+        const int R = 128 * lk + cc;
+        lds_x4q(lds_u32(sm + 2 * kLA + ((run + c) % 3) * kLX) + R * 64 + 16 * (((cc >> 1) & 3) ^ lk), r);
+      } else {
+        lds_x8(lds_u32(sm + 2 * kLA + ((run + c) % 3) * kLX) + 8 * lk * kLRow + cc * 8, r);
+      }
       bf8 b[2][3];
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
@@ -1049,7 +1105,8 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
     // col0 + wc + lr for rows 4 lk + v of each 16-row block: one 8-byte store
     // per value, 16 lanes covering 128 contiguous bytes of an output row.
     constexpr int DUAL = KIND ^ 1;
-    float* obase = KIND == K_B_FWD ? reinterpret_cast<float*>(t.C->g) : reinterpret_cast<float*>(t.C->F);
+    float* obase = KIND == K_B_FWD ? reinterpret_cast<float*>(t.C->g)
+                                   : (RAD ? reinterpret_cast<float*>(coeffs) : reinterpret_cast<float*>(t.C->F));
     const int c = t.col0 + cc;
     const bool okc = nbj && c < t.Ncc;
     const XCol<float> oc = x_col<DUAL>(t, min(c, t.Ncc - 1), obase);
@@ -1070,8 +1127,8 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
         }
       }
     } else if (okc) {
-      // forward: items with few rows (high orders) leave whole waves idle,
-      // whose stores are skipped
+      // forward: items with few rows (high orders or degrees) leave whole waves
+      // idle, whose stores are skipped
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (i >= nbi) continue;
@@ -1093,6 +1150,21 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
     t = tn;
     xc = xn;
   }
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_legendre_split(
+    const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork) {
+  __shared__ __align__(16) unsigned char sm[kLdsL];
+  copy_split<KIND>(sm, cls, work, nwork, nullptr);
+}
+
+// Forward radial contraction (Eq. DRT) of the split form on the copy-fed
+// design: 128 x 128 tiles, writing the coefficients.
+__global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_radial_split(
+    const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork, void* __restrict__ coeffs) {
+  __shared__ __align__(16) unsigned char sm[kLdsL];
+  copy_split<K_C_FWD>(sm, cls, work, nwork, coeffs);
 }
 
 inline int grid_for(int nwork, int max_grid) {
@@ -1128,6 +1200,10 @@ hipError_t launch_kind(int kind, int tg, const ClassDesc* d_cls, const int4* d_w
   if (nwork == 0) return hipSuccess;
   dim3 grid(grid_for(nwork, max_grid));
   if constexpr (PREC == PREC_SPLIT) {
+    if (kind == K_C_FWD && tg == kNumGeo) {
+      hipLaunchKernelGGL(k_radial_split, grid, dim3(LT), 0, s, d_cls, d_work, nwork, cout);
+      return hipGetLastError();
+    }
     if (kind == K_B_FWD) {
       hipLaunchKernelGGL((k_legendre_split<K_B_FWD>), grid, dim3(LT), 0, s, d_cls, d_work, nwork);
       return hipGetLastError();
@@ -1156,6 +1232,9 @@ int gemm_tile_n_complex(int tg) { return tg == 0 ? Geo<0>::BNC : Geo<1>::BNC; }
 bool gemm_legendre_has_geometries(int prec) { return prec != PREC_SPLIT; }
 int gemm_tile_n_complex_legendre(int prec, int tg) { return prec == PREC_SPLIT ? LBNC : gemm_tile_n_complex(tg); }
 int gemm_tile_m_legendre(int prec, int tg) { return prec == PREC_SPLIT ? BM : gemm_tile_m(tg); }
+int gemm_radial_geometries(int prec, bool inverse) { return prec == PREC_SPLIT && !inverse ? kNumGeo + 1 : kNumGeo; }
+int gemm_tile_m_radial(int tg) { return tg == kNumGeo ? BM : gemm_tile_m(tg); }
+int gemm_tile_n_complex_radial(int tg) { return tg == kNumGeo ? LBNC : gemm_tile_n_complex(tg); }
 int gemm_k_chunk(int prec) {
   return prec == PREC_F64 ? Cfg<PREC_F64>::BK : (prec == PREC_F32 ? Cfg<PREC_F32>::BK : Cfg<PREC_SPLIT>::BK);
 }

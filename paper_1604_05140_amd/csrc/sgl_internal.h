@@ -209,6 +209,12 @@ int gemm_tile_n_complex(int tg);                   // complex columns per tile o
 bool gemm_legendre_has_geometries(int prec);       // false: the split-form Legendre kernel has one tile
 int gemm_tile_m_legendre(int prec, int tg);        // tile of the stage (b) work items
 int gemm_tile_n_complex_legendre(int prec, int tg);
+// Stage (c) slots: the two register-staged geometries, and for the split form's
+// forward contraction a third, the copy-fed kernel (128 x 128 tiles).
+constexpr int kMaxTileGeo = 3;
+int gemm_radial_geometries(int prec, bool inverse);
+int gemm_tile_m_radial(int tg);
+int gemm_tile_n_complex_radial(int tg);
 int gemm_k_chunk(int prec);  // contraction chunk (table K padding) of a precision
 
 // Plan-time FP64 kernels (sgl_tables.hip)

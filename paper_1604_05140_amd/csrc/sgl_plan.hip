@@ -131,8 +131,8 @@ struct sgl_plan_s {
   int64_t n_naive_f = 0, n_naive_i = 0;
   // stage (b)/(c) work lists per GEMM tile geometry (index tg): Legendre forward /
   // inverse, radial forward / inverse
-  int off_bf[2] = {0, 0}, n_bf[2] = {0, 0}, off_bi[2] = {0, 0}, n_bi[2] = {0, 0};
-  int off_cf[2] = {0, 0}, n_cf[2] = {0, 0}, off_ci[2] = {0, 0}, n_ci[2] = {0, 0};
+  int off_bf[kMaxTileGeo] = {}, n_bf[kMaxTileGeo] = {}, off_bi[kMaxTileGeo] = {}, n_bi[kMaxTileGeo] = {};
+  int off_cf[kMaxTileGeo] = {}, n_cf[kMaxTileGeo] = {}, off_ci[kMaxTileGeo] = {}, n_ci[kMaxTileGeo] = {};
   // seminaive Legendre step: DCT work items {class, m + B - 1, column tile, columns per tile}
   int off_dct = 0, n_dct = 0, dct_cols = 16, dct_lds = 0;
   bool seminaive() const { return (flags & SGL_SEMINAIVE) != 0; }
@@ -334,7 +334,7 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
   struct Item { int cost; int4 w; };
   const int precb = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
   const int ngeo = gemm_num_geometries();
-  std::vector<Item> bf[2], bi[2], cf[2], ci[2];
+  std::vector<Item> bf[kMaxTileGeo], bi[kMaxTileGeo], cf[kMaxTileGeo], ci[kMaxTileGeo];
   int ldsm[3] = {0, 0, 0};
   for (int ci_ = 0; ci_ < (int)p->classes.size(); ++ci_) {
     const ClassHost& c = p->classes[ci_];
@@ -346,9 +346,9 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
       for (int cb = 0; cb < ncb; ++cb) wam[mode].push_back(make_int4(ci_, j, cb, c.rpb));
     ldsm[mode] = std::max(ldsm[mode], (int)fft_lds_bytes_for(p->dtype == SGL_F64 ? PREC_F64 : PREC_F32, c.rpb, L));
     const int kb = p->seminaive() ? B : L;  // polar-side contraction length
-    for (int tg = 0; tg < ngeo; ++tg) {
+    for (int tg = 0; tg < kMaxTileGeo; ++tg) {
       // stage (b): the split-form Legendre kernel has one tile (geometry 0)
-      if (tg == 0 || gemm_legendre_has_geometries(precb)) {
+      if (tg == 0 || (tg < ngeo && gemm_legendre_has_geometries(precb))) {
         const int BMb = gemm_tile_m_legendre(precb, tg), BNb = gemm_tile_n_complex_legendre(precb, tg);
         for (int m = 0; m < B; ++m) {
           const int rows = B - m;
@@ -360,15 +360,18 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
             for (int t = 0; t < nt; ++t) bi[tg].push_back({rows, make_int4(ci_, m, mt, t)});
         }
       }
-      const int BM = gemm_tile_m(tg), BNC = gemm_tile_n_complex(tg);
+      const int BM = gemm_tile_m_radial(tg), BNC = gemm_tile_n_complex_radial(tg);
+      const bool fwd_c = tg < gemm_radial_geometries(precb, false), inv_c = tg < gemm_radial_geometries(precb, true);
       for (int l = 0; l < B; ++l) {
         const int rows = B - l;
         const int ncc = (2 * l + 1) * nf;
         const int nt = (ncc + BNC - 1) / BNC;
-        for (int mt = 0; mt < (rows + BM - 1) / BM; ++mt)
-          for (int t = 0; t < nt; ++t) cf[tg].push_back({L, make_int4(ci_, l, mt, t)});
-        for (int mt = 0; mt < (L + BM - 1) / BM; ++mt)
-          for (int t = 0; t < nt; ++t) ci[tg].push_back({rows, make_int4(ci_, l, mt, t)});
+        if (fwd_c)
+          for (int mt = 0; mt < (rows + BM - 1) / BM; ++mt)
+            for (int t = 0; t < nt; ++t) cf[tg].push_back({L, make_int4(ci_, l, mt, t)});
+        if (inv_c)
+          for (int mt = 0; mt < (L + BM - 1) / BM; ++mt)
+            for (int t = 0; t < nt; ++t) ci[tg].push_back({rows, make_int4(ci_, l, mt, t)});
       }
     }
     if (p->seminaive()) {
@@ -436,7 +439,7 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
     n = (int)w.size();
     all.insert(all.end(), w.begin(), w.end());
   };
-  for (int tg = 0; tg < ngeo; ++tg) {
+  for (int tg = 0; tg < kMaxTileGeo; ++tg) {
     append(bf[tg], p->off_bf[tg], p->n_bf[tg]);
     append(bi[tg], p->off_bi[tg], p->n_bi[tg]);
     append(cf[tg], p->off_cf[tg], p->n_cf[tg]);
@@ -723,10 +726,11 @@ sgl_status_t run_direction(sgl_plan_s* p, int dir, const void* in, void* out, hi
 }
 
 // Tile geometries a launch slot can run with: the stage (b)/(c) slots of the
-// register-staged GEMM have two (see gemm_tile_m), the FFT slots and the
-// split-form Legendre kernel one.
+// register-staged GEMM have two (see gemm_tile_m), the split form's forward
+// radial slot a third (the copy-fed kernel), the FFT slots and the split-form
+// Legendre kernel one.
 int slot_geometries(const sgl_plan_s* p, int slot) {
-  if (slot == S_RAD_F || slot == S_RAD_I) return gemm_num_geometries();
+  if (slot == S_RAD_F || slot == S_RAD_I) return gemm_radial_geometries(prec_of(p->dtype), slot == S_RAD_I);
   if (slot == S_LEG_F || slot == S_LEG_I)
     return gemm_legendre_has_geometries(prec_of(p->dtype)) ? gemm_num_geometries() : 1;
   return 1;
@@ -1105,8 +1109,8 @@ sgl_status_t sgl_launch_tiles(sgl_plan_t plan, int* tiles) {
       rows = gemm_tile_m_legendre(prec, tg);
       cols = gemm_tile_n_complex_legendre(prec, tg);
     } else if (q == S_RAD_F || q == S_RAD_I) {
-      rows = gemm_tile_m(tg);
-      cols = gemm_tile_n_complex(tg);
+      rows = gemm_tile_m_radial(tg);
+      cols = gemm_tile_n_complex_radial(tg);
     }
     tiles[2 * q] = rows;
     tiles[2 * q + 1] = cols;

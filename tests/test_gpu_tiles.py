@@ -1,7 +1,8 @@
 """GEMM tile geometries of the stage (b)/(c) launch slots (the per-order and
 per-degree grouped contractions of Alg. 3 / Alg. 4, Eq. DLT and Eq. DRT).
 
-The register-staged MFMA GEMM runs with a 128 x 64 (complex) or a 64 x 32 tile;
+The register-staged MFMA GEMM runs with a 128 x 64 (complex) or a 64 x 32 tile,
+and the split form's forward radial slot also on the copy-fed kernel (128 x 128);
 the plan-time autotuner picks one per launch slot.  Every geometry must give the
 default plan's results (same per-element accumulation order, so equal up to
 rounding), hold the oracle's quadrature sums on small ragged plans, and survive
@@ -47,7 +48,7 @@ def einf(ref, got):
 
 def slot_geometries(plan, slot):
     out = []
-    for g in (0, 1):
+    for g in (0, 1, 2):
         try:
             plan.set_launch_tile(slot, g)
             out.append(g)
@@ -73,14 +74,17 @@ def test_every_geometry_matches_default(dtype):
     assert tiles0[0] == (0, 0) and tiles0[7] == (0, 0)
     assert tiles0[4] == (128, 64) and tiles0[5] == (128, 64)
     geos = {q: slot_geometries(base, q) for q in GEMM_SLOTS}
-    assert geos[4] == geos[5] == [0, 1]
-    # split-form Legendre: one tile (the copy-fed kernel); other forms: two
+    assert geos[5] == [0, 1]
+    # split form: the forward radial slot also runs the copy-fed kernel, the
+    # Legendre slots only it; other forms: the two register-staged tiles
+    assert geos[4] == ([0, 1, 2] if dtype == "split_bf16" else [0, 1])
     assert geos[3] == geos[6] == ([0] if dtype == "split_bf16" else [0, 1])
     p = sgl.sgl_plan_ex(Bs, dtype)
     for q in GEMM_SLOTS:
         for g in geos[q]:
             p.set_launch_tile(q, g)
-            want = (64, 32) if g == 1 else ((128, 128) if dtype == "split_bf16" and q in (3, 6) else (128, 64))
+            copy_fed = dtype == "split_bf16" and (q in (3, 6) or g == 2)
+            want = (64, 32) if g == 1 else ((128, 128) if copy_fed else (128, 64))
             assert p.launch_tiles()[q] == want
             f1, i1 = run(p, sgl.sgl_forward, s), run(p, sgl.sgl_inverse, c)
             assert torch.isfinite(f1).all() and torch.isfinite(i1).all()
@@ -140,7 +144,8 @@ def test_tile_change_recaptures_graphs():
 
 def test_bad_tile_requests():
     p = sgl.sgl_plan(8, 1, "f32")
-    for slot, g, status in ((0, 1, 2), (7, 1, 2), (4, 2, 2), (10, 0, 1), (-1, 0, 1), (4, -1, 1)):
+    for slot, g, status in ((0, 1, 2), (7, 1, 2), (4, 2, 2), (5, 2, 2), (4, 3, 2), (10, 0, 1), (-1, 0, 1),
+                            (4, -1, 1)):
         with pytest.raises(sgl.SglError) as ei:
             p.set_launch_tile(slot, g)
         assert ei.value.status == status, (slot, g)
@@ -154,4 +159,31 @@ def test_autotuner_reports_its_tiles():
     print(f"autotuned tiles {tiles}", flush=True)
     for q in GEMM_SLOTS:
         assert tiles[q] in ((128, 64), (64, 32)), (q, tiles[q])
+    p.destroy()
+
+
+def test_copy_fed_radial_against_oracle():
+    """Split plan with the forward radial contraction on the copy-fed kernel
+    (Eq. DRT, 128 x 128 tiles) against the oracle's quadrature sums of
+    non-bandlimited samples (Thm. 3.4): bandlimits whose K = 2B ends mid-chunk
+    (B = 9, 21) and whose degree groups span several column tiles (B = 40,
+    batch 2: up to 316 columns)."""
+    Bs = [9, 21, 40, 40]
+    p = sgl.sgl_plan_ex(Bs, "split_bf16")
+    p.set_launch_tile(4, 2)
+    assert p.launch_tiles()[4] == (128, 128)
+    so, co = p.offsets()
+    ss = [synth.complex_normal_samples(B, 1, seed=SEED + 60 + q)[0] for q, B in enumerate(Bs)]
+    f = run(p, sgl.sgl_forward, dev(np.concatenate(ss), torch.complex64)).cpu().numpy()
+    for q, B in enumerate(Bs):
+        n = D.num_coeffs(B)
+        # the highest degrees (the widest column groups, their last tiles), the
+        # lowest, and a stride through the rest
+        om = np.unique(np.concatenate([np.arange(min(n, 40)), np.arange(max(0, n - 200), n),
+                                       np.arange(0, n, 1 if B < 10 else 53)]))
+        ref = D.forward(ss[q].astype(np.complex128), B, omegas=om)
+        got = f[co[q]:co[q] + n][om]
+        e = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"copy-fed radial B={B}: e_inf {e:.2e}", flush=True)
+        assert e <= 2e-6, (B, e)
     p.destroy()
