@@ -119,18 +119,21 @@ __device__ inline int xrow(int cc, int part) {
 __device__ inline int swz(int r, int g) { return g ^ ((r >> 1) & 3); }
 
 // Thread -> (complex column cc, k group kg of 8) of the data-operand staging.
-// In the split form 32 lanes cover 16 columns x 2 k groups.
+// In the split form each 16 consecutive lanes hold the 8 k groups of two
+// columns (lanes 4a..4a+3: column a & 1, k groups 4 (a >> 1) .. + 3), so their
+// 8-byte LDS stores fill two whole 64-byte rows.  Measured on gfx950 with a
+// one-wave probe and the bank-conflict counter: LDS writes serve 128 bytes a
+// cycle (8-byte writes: 16 consecutive lanes, conflict-free when byte-address
+// bits 3..6 differ between them; 16-byte writes: 8 lanes, bits 4..6), reads
+// 256 bytes; 16 lanes over 16 columns (or 4 rows of 32 bytes) cost one extra
+// cycle per group.  Loads of a column that runs along k come in 128-byte runs.
+// (8 lanes per column, k groups in lane order, is as free of conflicts but
+// took the forward radial kernel 6 more registers, one wave less per SIMD.)
 template <int PREC, int TG>
 __device__ inline void x_thread(int tid, int& cc, int& kg) {
   if constexpr (PREC == PREC_SPLIT) {
-    const int lane = tid & 63, wave = tid >> 6;
-    if constexpr (TG == 0) {
-      cc = (lane & 15) | ((lane >> 5) << 4) | ((wave & 1) << 5);
-      kg = ((wave >> 1) << 1) | ((lane >> 4) & 1);
-    } else {
-      cc = (lane & 15) | ((lane >> 5) << 4);
-      kg = (wave << 1) | ((lane >> 4) & 1);
-    }
+    cc = ((tid >> 4) << 1) | ((tid >> 2) & 1);
+    kg = (tid & 3) | ((tid >> 1) & 4);
   } else {
     cc = tid & (Geo<TG>::BNC - 1);
     kg = tid / Geo<TG>::BNC;
