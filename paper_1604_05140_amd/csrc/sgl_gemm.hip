@@ -83,7 +83,9 @@ typedef unsigned int u4 __attribute__((ext_vector_type(4)));  // 16-byte operand
 template <int PREC, int TG = 0> struct Cfg {
   static constexpr int BK = PREC == PREC_F64 ? 64 : 32;
   static constexpr int PS = BK;      // bf16 LDS row (elements): unpadded, 16-byte slots swizzled (swz)
-  static constexpr int PF = BK + 4;  // f32/f64 LDS pitch (elements)
+  // f32/f64 LDS pitch (elements): 36 floats, 66 doubles (the FP64 operand reads,
+  // 8 bytes by 32 lanes a cycle, then fall on 32 distinct bank pairs)
+  static constexpr int PF = PREC == PREC_F64 ? BK + 2 : BK + 4;
   static constexpr int XN = BK / 8;  // k per thread in the data-operand staging (8 k groups)
   // 16-byte table vectors per row and per thread
   static constexpr int VR = PREC == PREC_SPLIT ? BK / 8 : (PREC == PREC_F32 ? BK / 4 : BK / 2);
@@ -95,16 +97,20 @@ template <int PREC, int TG = 0> struct Cfg {
   static constexpr int NS = PREC == PREC_F32 ? 2 : 1;
   // waves per SIMD the register allocation is held to
   static constexpr int WAVES = PREC == PREC_F64 ? 2 : 4;
-  // Data-operand LDS rows per plane: the split form keeps real and imaginary
-  // parts in two halves 8 rows apart; FP32 and FP64 interleave them.
-  static constexpr int XPAD = PREC == PREC_SPLIT ? 4 : 0;
+  // Data-operand LDS rows: real and imaginary parts in two halves, the
+  // imaginary half XPAD rows after the real one ends (split: 4; FP32, FP64: 8,
+  // which puts the rows an MFMA operand read takes from the two halves on
+  // disjoint banks; with interleaved halves the 16-byte staging stores of 8
+  // consecutive columns, 2 rows apart, fell 2-way (FP32) and 4-way (FP64) on
+  // the same banks).
+  static constexpr int XPAD = PREC == PREC_SPLIT ? 4 : 8;
   static constexpr int XROWS = 2 * Geo<TG>::BNC + XPAD;
 };
 
 // LDS row of real column (complex column cc, part re 0 / im 1) of the data operand
 template <int PREC, int TG>
 __device__ inline int xrow(int cc, int part) {
-  return PREC == PREC_SPLIT ? part * (Geo<TG>::BNC + Cfg<PREC, TG>::XPAD) + cc : 2 * cc + part;
+  return part * (Geo<TG>::BNC + Cfg<PREC, TG>::XPAD) + cc;
 }
 
 // Split-form LDS rows are 64 bytes (32 bf16) of four 16-byte slots; slot g of
