@@ -82,6 +82,22 @@ __device__ void stockham_stage(const T2* in, T2* out, const SGL_G T2* tw, int L,
 // one contiguous run per (m, j).
 // ---------------------------------------------------------------------------
 
+// Exchange pitch (complex values per [k1][n2] row of the [k1][n2][ring] layout)
+// of the register four-step FFT.  In single precision it is chosen per ring
+// length and direction so that both passes' 8-byte LDS accesses are free of
+// bank conflicts under the measured gfx950 rules (reads: 32 consecutive lanes
+// over 64 banks; writes: 16 consecutive lanes over 32 banks): the forward
+// writes with the n2 index fastest and reads with the ring fastest, the inverse
+// the other way round.  FP64 (16-byte values) keeps rpb + 1.
+__host__ __device__ constexpr int pow2_pitch_extra(int L, bool f64, bool inv) {
+  return f64 ? 1 : (inv ? (L >= 256 ? 2 : (L >= 64 ? 4 : 8)) : (L >= 256 ? 1 : (L >= 64 ? 2 : 4)));
+}
+// the larger of the two directions' pitches (the twiddle table follows the buffer)
+__host__ __device__ constexpr int pow2_pitch_max_extra(int L, bool f64) {
+  return pow2_pitch_extra(L, f64, true) > pow2_pitch_extra(L, f64, false) ? pow2_pitch_extra(L, f64, true)
+                                                                         : pow2_pitch_extra(L, f64, false);
+}
+
 template <typename T, int R1, int R2, bool RAW>
 __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int rpb,
                                 const SGL_G typename C2<T>::t* __restrict__ samples, typename C2<T>::t* lds,
@@ -89,7 +105,7 @@ __device__ inline void fwd_pow2(const ClassDesc& C, int j, int col0, int nr, int
   using T2 = typename C2<T>::t;
   constexpr int L = R1 * R2, B = L / 2;
   const int t = threadIdx.x;
-  const int P = rpb + 1;
+  const int P = rpb + pow2_pitch_extra(L, sizeof(T) == 8, false);
   if (t < rpb * R2) {
     const int r = t / R2, n2 = t % R2;
     if (r < nr) {
@@ -148,7 +164,7 @@ __device__ inline void inv_pow2(const ClassDesc& C, int j, int col0, int nr, int
   using T2 = typename C2<T>::t;
   constexpr int L = R1 * R2, B = L / 2;
   const int t = threadIdx.x;
-  const int P = rpb + 1;
+  const int P = rpb + pow2_pitch_extra(L, sizeof(T) == 8, true);
   if (t < rpb * R1) {
     const int r = t % rpb, k1 = t / rpb;
     if (r < nr) {
@@ -646,7 +662,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       continue;
     }
     if (MODE == 0 && fft_pow2_path(L)) {
-      T2* twl = smem + L * (rpb + 1);
+      T2* twl = smem + L * (rpb + pow2_pitch_max_extra(L, sizeof(T) == 8));
       if (it.x != tw_cls) {
         const SGL_G T2* tw = gmem(reinterpret_cast<const T2*>(C.tw));
         for (int q = threadIdx.x; q < L; q += blockDim.x) twl[q] = tw[q];
@@ -762,7 +778,7 @@ __global__ void __launch_bounds__(fft_threads(MODE, sizeof(T) == 8), fft_min_wav
       continue;
     }
     if (MODE == 0 && fft_pow2_path(L)) {
-      T2* twl = smem + L * (rpb + 1);
+      T2* twl = smem + L * (rpb + pow2_pitch_max_extra(L, sizeof(T) == 8));
       if (it.x != tw_cls) {
         const SGL_G T2* tw = gmem(reinterpret_cast<const T2*>(C.tw));
         for (int q = threadIdx.x; q < L; q += blockDim.x) twl[q] = tw[q];
@@ -868,7 +884,8 @@ static size_t fft_lds_bytes(int prec, int rpb, int L) {
   const size_t es = prec == PREC_F64 ? sizeof(double2) : sizeof(float2);
   if (fft_mode(L) == 1)  // ring areas + tables
     return ((size_t)kRings512 * (prec == PREC_F64 ? area_pitch<double2>() : area_pitch<float2>()) + kTab512) * es;
-  if (fft_pow2_path(L)) return (size_t)L * (rpb + 2) * es;  // exchange buffer + twiddle table
+  if (fft_pow2_path(L))  // exchange buffer + twiddle table
+    return (size_t)L * (rpb + pow2_pitch_max_extra(L, prec == PREC_F64) + 1) * es;
   if (const int M = fft_bluestein_m(L)) return ((size_t)M * (rpb + 3) + L) * es;  // buffer + tw, kernel, chirp
   return (size_t)2 * rpb * L * es;
 }
