@@ -61,6 +61,24 @@ def test_noalloc_matches_forward_twice():
         p.destroy()
 
 
+def test_noalloc_copy_fed_radial_kernel():
+    """The split form's forward radial slot on the copy-fed kernel (tile
+    geometry 2) reads the class descriptors of the static workspace too."""
+    Bs = [40, 24]
+    print(f"sgl_forward_noalloc B={Bs} split_bf16, copy-fed radial kernel", flush=True)
+    p = sgl.sgl_plan_ex(Bs, "split_bf16")
+    p.set_launch_tile(4, 2)
+    ct = p.complex_dtype
+    s = samples(Bs, ct, SEED + 50)
+    ref = torch.empty(p.total_coeffs, dtype=ct, device=DEV)
+    sgl.sgl_forward(p, s, ref)
+    got = torch.full((p.total_coeffs,), float("nan"), dtype=ct, device=DEV)
+    assert noalloc(p, s, got) == 0, sgl._load().sgl_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    p.destroy()
+
+
 def test_noalloc_refuses_oversized_plans():
     p = sgl.sgl_plan(128, 1, "f32")  # F alone is 134 MB
     s = torch.zeros(p.total_samples, dtype=p.complex_dtype, device=DEV)
