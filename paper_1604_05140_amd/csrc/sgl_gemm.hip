@@ -989,7 +989,8 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
         const int sg = (wave >> 3) + 2 * s;
         const int q = (lane & 3) ^ ((lane >> 3) & 3) ^ sg;
         const int k = min(k0 + 8 * sg + 2 * q, tt.K - 2);
-        // g is read once here
+        // streaming reads of g: each row tile of a degree reads it once (one tile
+        // up to B = 128)
         copy16_to_lds<true>(x.p + 2 * k,
                             sm + (st == 3 ? kLSpare : 2 * kLA + st * kLX + (128 * sg + 16 * (wave & 7)) * 64));
       } else {
