@@ -309,7 +309,8 @@ template <int KIND, typename T>
 __device__ inline XCol<T> x_col(const Tile& t, int c, T* base) {
   XCol<T> x{gmem(base), 0, 0, (T)1};
   const ClassDesc& C = *t.C;
-  const int B = C.B, L = C.L, nf = C.nf;
+  // class fields through the scalar cache (t.C is wave-uniform)
+  const int B = load_uniform(&C.B), L = load_uniform(&C.L), nf = load_uniform(&C.nf);
   if constexpr (KIND == K_B_FWD || KIND == K_B_INV) {
     const int ncf = nf * L;
     const int seg = c >= ncf;
@@ -469,10 +470,10 @@ __device__ inline void store_x(const Stage<PREC, TG>& st, typename DT<PREC>::t s
 template <int PREC, int KIND>
 __device__ inline typename DT<PREC>::t* x_base(const Tile& t, const void* cin) {
   using T = typename DT<PREC>::t;
-  if constexpr (KIND == K_B_FWD) return reinterpret_cast<T*>(t.C->F);
+  if constexpr (KIND == K_B_FWD) return reinterpret_cast<T*>(load_uniform(&t.C->F));
   else if constexpr (KIND == K_C_INV) return const_cast<T*>(reinterpret_cast<const T*>(cin));
   else if constexpr (KIND == K_DEBUG) return nullptr;
-  else return reinterpret_cast<T*>(t.C->g);
+  else return reinterpret_cast<T*>(load_uniform(&t.C->g));
 }
 
 // ---- the kernel ------------------------------------------------------------
@@ -792,12 +793,12 @@ k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwo
 // its register budget.  This kernel moves both operands with 16-byte global ->
 // LDS copies (no registers, no LDS stores): the table through two LDS stages,
 // the data through three, so that the data of the next two chunks are in
-// flight while a chunk is used.  All its vector-memory loads are such copies,
-// so the waits are its own (the compiler makes any use of a loaded register
-// wait for every outstanding copy).  The inverse writes 128 KB per item: its
-// stores are issued by every lane in a fixed number, so that the next item's
-// first wait can leave them outstanding (with one block per CU nothing else
-// would hide their drain).
+// flight while a chunk is used, across the boundaries of a block's items.
+// All its vector-memory loads are such copies, so the waits are its own (the
+// compiler makes any use of a loaded register wait for every outstanding
+// copy).  The inverse writes 128 KB per item: its stores are issued by every
+// lane in a fixed number, so that the next item's first wait can leave them
+// outstanding (with one block per CU nothing else would hide their drain).
 //   block: 1024 threads, 16 waves in a 2 x 8 layout; tile 128 rows x 128
 //   complex columns; wave (wr, wc) computes rows wr..wr+63 of complex columns
 //   wc..wc+15 as two 16-column MFMA blocks, real and imaginary parts;
@@ -920,8 +921,8 @@ __device__ inline void wait_vm(int n) {
 #if defined(__HIP_DEVICE_COMPILE__)
   if (n == 2)
     asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
-  else if (n == 16)
-    asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+  else if (n == 18)
+    asm volatile("s_waitcnt vmcnt(18)" ::: "memory");
   else
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #endif
@@ -949,9 +950,13 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
   int w = blockIdx.x;
   if (w >= nwork) return;
 
+  // (the item index is wave-uniform; saying so keeps the work-list and class
+  // reads on the scalar unit: a vector load here would make its first use
+  // wait for every outstanding copy)
   auto tile = [&](int wi) {
+    wi = __builtin_amdgcn_readfirstlane(wi);
     Tile tt = make_tile<PREC_SPLIT, KIND, 0>(cls, work, wi, nodbg);
-    tt.col0 = work[wi].w * LBNC;
+    tt.col0 = load_uniform(&work[wi].w) * LBNC;
     return tt;
   };
   // the lane's copy source: Legendre, its complex column pair; radial, its
@@ -1003,19 +1008,56 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
     }
   };
 
+  // The chunks of the block's items (w, w + G, w + 2G, ...) form one stream:
+  // data copies run two chunks ahead of the chunk in use and table copies one,
+  // across item boundaries, so the first chunks of the next item (of the next
+  // two when the next has one chunk) are in flight while this item's last ones
+  // are used.  Stream chunk g sits in data stage g % 3 and table stage g % 2;
+  // past the block's last item the copies go to the spare row.
+  const int G = gridDim.x;
+  auto nchunks = [&](const Tile& tt) { return (tt.K + BK - 1) / BK; };
   Tile t = tile(w);
-  XCol<float> xc = col(t);
-  int run = 0;  // chunks of earlier items of this block: stage of chunk c is (run + c) % 3 (data), % 2 (table)
-  bool first = true;  // no stores of an earlier item are outstanding
-  {
-    const int nc = (t.K + BK - 1) / BK;
-    copy_x(t, xc, 0, 0);
-    copy_x(t, xc, BK, nc > 1 ? 1 : 3);
-    copy_a(t, 0, 0);
+  int nc = nchunks(t);
+  Tile t1 = t, t2 = t;  // the next two items (nc1, nc2 = 0: none or not needed)
+  int nc1 = 0, nc2 = 0;
+  if (w + G < nwork) {
+    t1 = tile(w + G);
+    nc1 = nchunks(t1);
+    if (nc1 == 1 && w + 2 * G < nwork) {
+      t2 = tile(w + 2 * G);
+      nc2 = nchunks(t2);
+    }
   }
+  XCol<float> xc = col(t);
+  int run = 0;  // stream index of this item's first chunk, mod 6
+  bool first = true;  // no stores of an earlier item are outstanding
+  // data chunk at stream position pos of this item (pos >= nc: the next items')
+  auto copy_x_at = [&](int pos) {
+    const int st = (run + pos) % 3;
+    if (pos < nc) {
+      copy_x(t, xc, pos * BK, st);
+    } else if (pos - nc < nc1) {
+      copy_x(t1, col(t1), (pos - nc) * BK, st);
+    } else if (pos - nc - nc1 < nc2) {
+      copy_x(t2, col(t2), (pos - nc - nc1) * BK, st);
+    } else {
+      copy_x(t, xc, (nc - 1) * BK, 3);
+    }
+  };
+  // table chunk at stream position pos <= nc of this item
+  auto copy_a_at = [&](int pos) {
+    if (pos < nc)
+      copy_a(t, pos * BK, (run + pos) % 2);
+    else if (nc1 > 0)
+      copy_a(t1, 0, (run + pos) % 2);
+    else
+      copy_a(t, (nc - 1) * BK, 2);
+  };
+  copy_a_at(0);
+  copy_x_at(0);
+  copy_x_at(1);
 
   for (;;) {
-    const int nc = (t.K + BK - 1) / BK;
     f4 acc[4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -1028,23 +1070,24 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
       nbj = t.Ncc - (t.col0 + wc) <= 0 ? 0 : 2;
     }
     const int cc = wc + lr;  // the lane's complex column in the tile
-    const ClassDesc& C = *t.C;
     // (-1)^m of the -m segment: the contraction is linear, so it is applied to the outputs
-    const float sg = (!RAD && (t.q & 1) && t.col0 + cc >= C.nf * C.L) ? -1.0f : 1.0f;
+    const float sg =
+        (!RAD && (t.q & 1) && t.col0 + cc >= load_uniform(&t.C->nf) * load_uniform(&t.C->L)) ? -1.0f : 1.0f;
 
     // Chunk c: the wave waits for its copies of chunk c; one barrier then both
     // publishes every wave's copies and frees the stages of chunk c - 1, into
-    // which the copies of table chunk c + 1 and data chunk c + 2 go (past the
-    // item's end: to the spare row, so that every iteration issues the same).
-    // Issue order: ... X(c), A(c), X(c+1), A(c+1), X(c+2): at chunk c the two
-    // copies of X(c+1) may stay outstanding.  Chunk 0's copies were issued at
-    // the item's start, followed by the previous item's stores; in the inverse
-    // (every lane issues all 16 of them) those may stay outstanding.
+    // which the copies of table chunk c + 1 and data chunk c + 2 of the stream
+    // go (every iteration issues the same copies).  Issue order: ... X(g),
+    // A(g), X(g+1), A(g+1), X(g+2) for stream chunks g: at chunk g the two
+    // copies of X(g+1) may stay outstanding, and at an item's first chunk also
+    // the previous item's stores, which in the inverse every lane issues all
+    // 16 of (after A(g) and X(g+1)); the forward's stores are conditional, so
+    // its first chunk waits for everything.
     for (int c = 0; c < nc; ++c) {
-      wait_vm(c > 0 ? 2 : (KIND == K_B_INV && !first ? 16 : 0));
+      wait_vm(c > 0 || first ? 2 : (KIND == K_B_INV ? 18 : 0));
       bar_only();  // chunk c is in LDS; every wave is done with chunk c - 1
-      copy_a(t, min(c + 1, nc - 1) * BK, c + 1 < nc ? (run + c + 1) % 2 : 2);
-      copy_x(t, xc, min(c + 2, nc - 1) * BK, c + 2 < nc ? (run + c + 2) % 3 : 3);
+      copy_a_at(c + 1);
+      copy_x_at(c + 2);
       if (nbj == 0 || nbi == 0) continue;
       f2v r[8];
       if constexpr (RAD) {
@@ -1090,33 +1133,18 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
       }
     }
 
-    // the block's next item: its first chunks are copied while this one is
-    // written, into the stages after this item's last chunk (those held chunks
-    // nc - 3 and nc - 2, or the previous item's, which every wave finished
-    // before the last chunk's barrier)
-    const int wn = w + gridDim.x;
-    const bool more = wn < nwork;
-    Tile tn = t;
-    XCol<float> xn = xc;
-    if (more) {
-      tn = tile(wn);
-      xn = col(tn);
-      const int ncn = (tn.K + BK - 1) / BK;
-      copy_x(tn, xn, 0, (run + nc) % 3);
-      copy_x(tn, xn, BK, ncn > 1 ? (run + nc + 1) % 3 : 3);
-      copy_a(tn, 0, (run + nc) % 2);
-    }
-    // The next item's first wait (vmcnt(16) in the inverse) relies on all 16
-    // epilogue stores being issued after these copies: no memory operation may
-    // move across this point.
+    // The next item's first wait (vmcnt(18) in the inverse) relies on all 16
+    // epilogue stores being issued after the copies of the last chunk: no
+    // memory operation may move across this point.
     asm volatile("" ::: "memory");
 
     // epilogue: each lane holds re (block 0) and im (block 1) of complex column
     // col0 + wc + lr for rows 4 lk + v of each 16-row block: one 8-byte store
     // per value, 16 lanes covering 128 contiguous bytes of an output row.
     constexpr int DUAL = KIND ^ 1;
-    float* obase = KIND == K_B_FWD ? reinterpret_cast<float*>(t.C->g)
-                                   : (RAD ? reinterpret_cast<float*>(coeffs) : reinterpret_cast<float*>(t.C->F));
+    float* obase = KIND == K_B_FWD ? reinterpret_cast<float*>(load_uniform(&t.C->g))
+                                   : (RAD ? reinterpret_cast<float*>(coeffs)
+                                          : reinterpret_cast<float*>(load_uniform(&t.C->F)));
     const int c = t.col0 + cc;
     const bool okc = nbj && c < t.Ncc;
     const XCol<float> oc = x_col<DUAL>(t, min(c, t.Ncc - 1), obase);
@@ -1150,15 +1178,31 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
         }
       }
     }
-    if (!more) {
+    if (nc1 == 0) {
       wait_vm(0);  // no copy into this block's LDS outlives the block
       break;
     }
     run = (run + nc) % 6;
     first = false;
-    w = wn;
-    t = tn;
-    xc = xn;
+    w += G;
+    t = t1;
+    nc = nc1;
+    xc = col(t);
+    if (nc2 > 0) {
+      t1 = t2;
+      nc1 = nc2;
+    } else {
+      nc1 = 0;
+      if (w + G < nwork) {
+        t1 = tile(w + G);
+        nc1 = nchunks(t1);
+      }
+    }
+    nc2 = 0;
+    if (nc1 == 1 && w + 2 * G < nwork) {
+      t2 = tile(w + 2 * G);
+      nc2 = nchunks(t2);
+    }
   }
 }
 

@@ -10,7 +10,11 @@ The kernels rely on properties the source can only request:
   * the copy-fed inverse Legendre kernel waits for its copies with a vector
     memory count that assumes exactly 16 epilogue stores per lane and item (the
     vector-memory counter of the CDNA ISA counts loads, stores and LDS copies of
-    one wave and retires them in issue order), so its code must hold 16 stores.
+    one wave and retires them in issue order), so its code must hold 16 stores;
+  * the copy-fed Legendre kernels keep their copies in flight across items, so
+    they must load nothing else through the vector-memory path: any register
+    load (a class or work-list field read as a vector load) would make its
+    first use wait for every outstanding copy.
 """
 
 import os
@@ -78,3 +82,9 @@ def test_copy_fed_inverse_legendre_has_sixteen_stores(asm):
     (name, body), = kernels(asm["gemm"], r"k_legendre_splitILi1E")
     n, _ = stores(body)
     assert n == 16, n
+
+
+def test_copy_fed_legendre_kernels_load_only_by_copies(asm):
+    for name, body in kernels(asm["gemm"], r"k_legendre_split"):
+        loads = re.findall(r"^\s+((?:global|flat|buffer)_load\w*)", body, re.M)
+        assert loads and all(l == "global_load_lds_dwordx4" for l in loads), (name, sorted(set(loads)))
