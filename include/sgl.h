@@ -71,7 +71,7 @@ typedef struct sgl_plan_s* sgl_plan_t;
 typedef enum {
   SGL_OK = 0,
   SGL_ERR_INVALID_ARG = 1, /* bad size, null pointer, aliasing, unknown flag   */
-  SGL_ERR_UNSUPPORTED = 2, /* valid request this build does not support        */
+  SGL_ERR_UNSUPPORTED = 2, /* valid request the library does not support       */
   SGL_ERR_HIP = 3,         /* a HIP runtime call failed (see sgl_last_error)  */
   SGL_ERR_OOM = 4,         /* device allocation failed                         */
   SGL_ERR_NUMERIC = 5      /* plan-time FP64 quadrature failed a self-check    */

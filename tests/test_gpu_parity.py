@@ -1,7 +1,7 @@
 """GPU parity: libsgl (HIP, through the C ABI) against the CPU oracle.
 
-Error metric (reading of Sect. 4's relative error): e_inf =
-max|delta| / max|reference| per function.  Bars: FP64 1e-12 against the
+Error metric (a reading of Sect. 4's relative error, which the paper does not
+define further): e_inf = max|delta| / max|reference| per function.  Bars: FP64 1e-12 against the
 oracle; FP32 1e-5 and split-bf16 1e-6 against the plain FP64 GPU path on the
 same inputs (which is itself held to 1e-12 against the oracle).
 """
