@@ -44,9 +44,10 @@
 //
 // The split-form Legendre contractions (both directions) have a kernel of
 // their own, k_legendre_split below, fed by global -> LDS copies; the forward
-// radial contraction of the split form runs on the same design as a third tile
-// geometry (k_radial_split), which the plan-time autotuner weighs against the
-// two of this kernel.
+// radial contraction of the split form and the FP32 Legendre contractions run
+// on the same design as a third tile geometry of their slots (k_radial_split,
+// k_legendre_f32), which the plan-time autotuner weighs against the two of
+// this kernel.
 #include "sgl_internal.h"
 
 namespace sgl {
@@ -819,13 +820,37 @@ k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwo
 //   free of bank conflicts) up to a fixed relabelling (xor with q).
 // LDS: 2 x 24 KB + 3 x 32.5 KB + one spare row = 147 KB, one block per CU
 // (16 waves, as two 512-thread blocks of the kernel above).
+//
+// The FP32 Legendre contractions run on the same design (k_legendre_f32, a
+// third tile geometry of their launch slots): the data chunk and its copies
+// are the split form's; the table chunk is one FP32 plane (128 rows x 32 k,
+// 128 bytes a row: 16 copies of 1 KB, copy q by wave q, eight rows of it),
+// with the row's eight 16-byte slots in swizzled order (swz32); each lane
+// takes k 8 lk .. 8 lk + 7 of the chunk, so that its data operand is the
+// split form's eight rows of one complex column and its table fragment two
+// 16-byte reads per row block, and runs eight 16 x 16 x 4 FP32 MFMA steps per
+// block (the pairing of k with the MFMA's k slot is the same on both operands,
+// so the sum over the chunk is complete).  LDS: 2 x 16 KB + 3 x 32.5 KB + one
+// spare row = 130 KB.
 constexpr int LT = 1024;
 constexpr int LBNC = 128;
-constexpr int kLA = 3 * BM * 64;  // one table stage
 constexpr int kLRow = 1040;
-constexpr int kLX = 32 * kLRow;   // one data stage
-constexpr int kLSpare = 2 * kLA + 3 * kLX;
-constexpr int kLdsL = kLSpare + kLRow;
+constexpr int kLX = 32 * kLRow;  // one data stage
+// one table stage, the spare row's offset and the LDS size per precision
+template <int PREC> struct CopyLds {
+  static constexpr int a = PREC == PREC_SPLIT ? 3 * BM * 64 : BM * 128;
+  static constexpr int spare = 2 * a + 3 * kLX;
+  static constexpr int total = spare + kLRow;
+};
+
+// Position of logical 16-byte slot L (k 4L .. 4L + 3) of row r of an FP32
+// table stage: L ^ swz32(r).  An operand read (16 rows r0 + lr, slot 2 lk + h,
+// r0 a multiple of 16) meets the 16-byte read rule above: the 16 lanes of a
+// cycle take 16 distinct (row parity, position) pairs, i.e. 16 distinct
+// 16-byte bank groups, because swz32 takes values with bit 1 clear that
+// differ within each of the lane-quad sets lr >> 1 in {0, 1, 6, 7} and
+// {2, 3, 4, 5} that share a cycle with lk of one parity.
+__device__ inline int swz32(int r) { return ((r >> 1) & 1) | (r & 4); }
 
 #if defined(__HIP_DEVICE_COMPILE__)
 #define SGL_L __attribute__((address_space(3)))
@@ -904,6 +929,18 @@ __device__ inline void lds_a3(unsigned a, u4 (&r)[3]) {
       : "memory");
 #endif
 }
+// The two 16-byte slots (k 8 lk .. 8 lk + 7) of one FP32 table row.
+__device__ inline void lds_a2(unsigned a0, unsigned a1, f4 (&r)[2]) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile(
+      "ds_read_b128 %0, %2\n\t"
+      "ds_read_b128 %1, %3\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(r[0]), "=&v"(r[1])
+      : "v"(a0), "v"(a1)
+      : "memory");
+#endif
+}
 // Workgroup barrier without the fence of __syncthreads (which waits for every
 // outstanding vector-memory operation); also a compiler barrier for memory.
 __device__ inline void bar_only() {
@@ -931,20 +968,24 @@ __device__ inline void wait_vm(int n) {
 // target of the epilogue stores that fall outside the group (never read)
 __device__ f2v g_spare_out[64];
 
-// The body of both copy-fed kernels (KIND: K_B_FWD, K_B_INV or K_C_FWD; sm:
-// kLdsL bytes of LDS; coeffs: the coefficient output of K_C_FWD).
-template <int KIND>
-__device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* __restrict__ cls,
-                                           const int4* __restrict__ work, int nwork, void* __restrict__ coeffs) {
+// The body of the copy-fed kernels (PREC_SPLIT with KIND K_B_FWD, K_B_INV or
+// K_C_FWD; PREC_F32 with K_B_FWD or K_B_INV; sm: CopyLds<PREC>::total bytes of
+// LDS; coeffs: the coefficient output of K_C_FWD).
+template <int PREC, int KIND>
+__device__ __forceinline__ void copy_fed(unsigned char* sm, const ClassDesc* __restrict__ cls,
+                                         const int4* __restrict__ work, int nwork, void* __restrict__ coeffs) {
   static_assert(KIND == K_B_FWD || KIND == K_B_INV || KIND == K_C_FWD, "Legendre kinds and the forward radial kind");
+  static_assert(PREC == PREC_SPLIT || (PREC == PREC_F32 && KIND != K_C_FWD), "split form, or FP32 Legendre");
   constexpr bool RAD = KIND == K_C_FWD;
-  constexpr int BK = Cfg<PREC_SPLIT>::BK, PS = Cfg<PREC_SPLIT>::PS;
-  static_assert(BK == 32 && PS == 32, "one 16x16x32 MFMA step per chunk, 64-byte table rows");
+  constexpr int BK = Cfg<PREC>::BK, PS = Cfg<PREC_SPLIT>::PS;
+  static_assert(BK == 32 && PS == 32, "32-deep chunks; split form: 64-byte table rows");
+  constexpr int LA = CopyLds<PREC>::a, SPARE = CopyLds<PREC>::spare;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 3) * 64, wc = (wave & 7) * 16;
   const int lr = lane & 15, lk = lane >> 4;
-  const int nac = wave < 8 ? 2 : 1;  // table copies per chunk of this wave
+  // table copies per chunk of this wave (split: 24 of 1 KB, FP32: 16)
+  const int nac = PREC == PREC_SPLIT && wave < 8 ? 2 : 1;
   DebugArgs nodbg{0, 0, 0, nullptr, nullptr, nullptr};
 
   int w = blockIdx.x;
@@ -955,7 +996,7 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
   // wait for every outstanding copy)
   auto tile = [&](int wi) {
     wi = __builtin_amdgcn_readfirstlane(wi);
-    Tile tt = make_tile<PREC_SPLIT, KIND, 0>(cls, work, wi, nodbg);
+    Tile tt = make_tile<PREC, KIND, 0>(cls, work, wi, nodbg);
     tt.col0 = load_uniform(&work[wi].w) * LBNC;
     return tt;
   };
@@ -964,23 +1005,32 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
   auto col = [&](const Tile& tt) {
     if constexpr (RAD)
       return x_col<KIND>(tt, min(tt.col0 + (wave & 7) * 16 + (lane >> 2), tt.Ncc - 1),
-                         x_base<PREC_SPLIT, KIND>(tt, nullptr));
+                         x_base<PREC, KIND>(tt, nullptr));
     else
-      return x_col<KIND>(tt, min(tt.col0 + 2 * lane, tt.Ncc - 2), x_base<PREC_SPLIT, KIND>(tt, nullptr));
+      return x_col<KIND>(tt, min(tt.col0 + 2 * lane, tt.Ncc - 2), x_base<PREC, KIND>(tt, nullptr));
   };
   // table chunk k0 into stage st (2: the spare row); rows past the block clamp
   // to its last row (they feed outputs that are never stored)
   auto copy_a = [&](const Tile& tt, int k0, int st) {
     const SGL_G unsigned char* tab = gmem(reinterpret_cast<const unsigned char*>(tt.tab));
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      if (s >= nac) break;
-      const int q = wave + 16 * s;
-      const int p = q >> 3, r = 16 * (q & 7) + (lane >> 2);
-      const int g = (lane & 3) ^ ((r >> 1) & 3);
+    if constexpr (PREC == PREC_F32) {
+      // rows 8 wave .. + 7, lane: row + lane / 8, slot position lane & 7
+      const int r = 8 * wave + (lane >> 3);
+      const int g = (lane & 7) ^ swz32(r);
       const int gr = min(tt.row0 + r, tt.M - 1);
-      const int64_t off = p * tt.plane + (int64_t)gr * tt.pitch + k0 + g * 8;
-      copy16_to_lds<false>(tab + 2 * off, sm + (st == 2 ? kLSpare : st * kLA + q * 1024));
+      const int64_t off = (int64_t)gr * tt.pitch + k0 + g * 4;
+      copy16_to_lds<false>(tab + 4 * off, sm + (st == 2 ? SPARE : st * LA + wave * 1024));
+    } else {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        if (s >= nac) break;
+        const int q = wave + 16 * s;
+        const int p = q >> 3, r = 16 * (q & 7) + (lane >> 2);
+        const int g = (lane & 3) ^ ((r >> 1) & 3);
+        const int gr = min(tt.row0 + r, tt.M - 1);
+        const int64_t off = p * tt.plane + (int64_t)gr * tt.pitch + k0 + g * 8;
+        copy16_to_lds<false>(tab + 2 * off, sm + (st == 2 ? SPARE : st * LA + q * 1024));
+      }
     }
   };
   // data chunk k0 into stage st (3: the spare row); rows past K clamp to the
@@ -997,13 +1047,13 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
         // streaming reads of g: each row tile of a degree reads it once (one tile
         // up to B = 128)
         copy16_to_lds<true>(x.p + 2 * k,
-                            sm + (st == 3 ? kLSpare : 2 * kLA + st * kLX + (128 * sg + 16 * (wave & 7)) * 64));
+                            sm + (st == 3 ? SPARE : 2 * LA + st * kLX + (128 * sg + 16 * (wave & 7)) * 64));
       } else {
         const int k = min(k0 + 2 * wave + s, tt.K - 1);
         // the spectrum is read once: streaming copies keep g cached for stage (c);
         // g (inverse) is read by both row tiles of a column tile
         copy16_to_lds<KIND == K_B_FWD>(x.p + 2 * x_off<KIND>(tt, x, k),
-                            sm + (st == 3 ? kLSpare : 2 * kLA + st * kLX + (2 * wave + s) * kLRow));
+                            sm + (st == 3 ? SPARE : 2 * LA + st * kLX + (2 * wave + s) * kLRow));
       }
     }
   };
@@ -1092,9 +1142,28 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
       f2v r[8];
       if constexpr (RAD) {
         const int R = 128 * lk + cc;
-        lds_x4q(lds_u32(sm + 2 * kLA + ((run + c) % 3) * kLX) + R * 64 + 16 * (((cc >> 1) & 3) ^ lk), r);
+        lds_x4q(lds_u32(sm + 2 * LA + ((run + c) % 3) * kLX) + R * 64 + 16 * (((cc >> 1) & 3) ^ lk), r);
       } else {
-        lds_x8(lds_u32(sm + 2 * kLA + ((run + c) % 3) * kLX) + 8 * lk * kLRow + cc * 8, r);
+        lds_x8(lds_u32(sm + 2 * LA + ((run + c) % 3) * kLX) + 8 * lk * kLRow + cc * 8, r);
+      }
+      const unsigned ab = lds_u32(sm + ((run + c) % 2) * LA);
+      if constexpr (PREC == PREC_F32) {
+        // r[u]: (re, im) of column cc at k 8 lk + u, the lane's k in MFMA step u
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (i >= nbi) continue;
+          const int row = wr + i * 16 + lr;
+          const unsigned a0 = ab + row * 128, f = swz32(row);
+          f4 av[2];
+          lds_a2(a0 + 16 * ((2 * lk) ^ f), a0 + 16 * ((2 * lk + 1) ^ f), av);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const float a = av[u >> 2][u & 3];
+            acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, r[u][0], acc[i][0], 0, 0, 0);
+            acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, r[u][1], acc[i][1], 0, 0, 0);
+          }
+        }
+        continue;
       }
       bf8 b[2][3];
 #pragma unroll
@@ -1109,7 +1178,6 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
           b[part][p] = __builtin_bit_cast(bf8, v);
         }
       }
-      const unsigned ab = lds_u32(sm + ((run + c) % 2) * kLA);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (i >= nbi) continue;
@@ -1209,16 +1277,25 @@ __device__ __forceinline__ void copy_split(unsigned char* sm, const ClassDesc* _
 template <int KIND>
 __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_legendre_split(
     const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork) {
-  __shared__ __align__(16) unsigned char sm[kLdsL];
-  copy_split<KIND>(sm, cls, work, nwork, nullptr);
+  __shared__ __align__(16) unsigned char sm[CopyLds<PREC_SPLIT>::total];
+  copy_fed<PREC_SPLIT, KIND>(sm, cls, work, nwork, nullptr);
 }
 
 // Forward radial contraction (Eq. DRT) of the split form on the copy-fed
 // design: 128 x 128 tiles, writing the coefficients.
 __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_radial_split(
     const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork, void* __restrict__ coeffs) {
-  __shared__ __align__(16) unsigned char sm[kLdsL];
-  copy_split<K_C_FWD>(sm, cls, work, nwork, coeffs);
+  __shared__ __align__(16) unsigned char sm[CopyLds<PREC_SPLIT>::total];
+  copy_fed<PREC_SPLIT, K_C_FWD>(sm, cls, work, nwork, coeffs);
+}
+
+// FP32 Legendre contractions (Eq. DLT and its inverse) on the copy-fed design:
+// 128 x 128 tiles, a tile geometry of their launch slots.
+template <int KIND>
+__global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_legendre_f32(
+    const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork) {
+  __shared__ __align__(16) unsigned char sm[CopyLds<PREC_F32>::total];
+  copy_fed<PREC_F32, KIND>(sm, cls, work, nwork, nullptr);
 }
 
 inline int grid_for(int nwork, int max_grid) {
@@ -1253,6 +1330,16 @@ hipError_t launch_kind(int kind, int tg, const ClassDesc* d_cls, const int4* d_w
                        void* cout, int max_grid, hipStream_t s) {
   if (nwork == 0) return hipSuccess;
   dim3 grid(grid_for(nwork, max_grid));
+  if constexpr (PREC == PREC_F32) {
+    if (tg == kNumGeo && kind == K_B_FWD) {
+      hipLaunchKernelGGL((k_legendre_f32<K_B_FWD>), grid, dim3(LT), 0, s, d_cls, d_work, nwork);
+      return hipGetLastError();
+    }
+    if (tg == kNumGeo && kind == K_B_INV) {
+      hipLaunchKernelGGL((k_legendre_f32<K_B_INV>), grid, dim3(LT), 0, s, d_cls, d_work, nwork);
+      return hipGetLastError();
+    }
+  }
   if constexpr (PREC == PREC_SPLIT) {
     if (kind == K_C_FWD && tg == kNumGeo) {
       hipLaunchKernelGGL(k_radial_split, grid, dim3(LT), 0, s, d_cls, d_work, nwork, cout);
@@ -1280,12 +1367,13 @@ hipError_t launch_any(int prec, int kind, int tg, const ClassDesc* d_cls, const 
 
 }  // namespace
 
-int gemm_num_geometries() { return kNumGeo; }
 int gemm_tile_m(int tg) { return tg == 0 ? Geo<0>::BM : Geo<1>::BM; }
 int gemm_tile_n_complex(int tg) { return tg == 0 ? Geo<0>::BNC : Geo<1>::BNC; }
-bool gemm_legendre_has_geometries(int prec) { return prec != PREC_SPLIT; }
-int gemm_tile_n_complex_legendre(int prec, int tg) { return prec == PREC_SPLIT ? LBNC : gemm_tile_n_complex(tg); }
-int gemm_tile_m_legendre(int prec, int tg) { return prec == PREC_SPLIT ? BM : gemm_tile_m(tg); }
+int gemm_legendre_geometries(int prec) { return prec == PREC_SPLIT ? 1 : (prec == PREC_F32 ? kNumGeo + 1 : kNumGeo); }
+int gemm_tile_n_complex_legendre(int prec, int tg) {
+  return prec == PREC_SPLIT || tg == kNumGeo ? LBNC : gemm_tile_n_complex(tg);
+}
+int gemm_tile_m_legendre(int prec, int tg) { return prec == PREC_SPLIT || tg == kNumGeo ? BM : gemm_tile_m(tg); }
 int gemm_radial_geometries(int prec, bool inverse) { return prec == PREC_SPLIT && !inverse ? kNumGeo + 1 : kNumGeo; }
 int gemm_tile_m_radial(int tg) { return tg == kNumGeo ? BM : gemm_tile_m(tg); }
 int gemm_tile_n_complex_radial(int tg) { return tg == kNumGeo ? LBNC : gemm_tile_n_complex(tg); }

@@ -203,10 +203,12 @@ hipError_t launch_synthesize_points(const ClassDesc* d_cls, const int64_t* d_pre
                                     const void* coeffs, int npts, const double* xyz, void* values, hipStream_t s);
 hipError_t launch_debug_gemm(int prec, int M, int N, int K, const double* A, const double* X, double* C,
                              hipStream_t s);
-int gemm_num_geometries();                         // tile geometries of the register-staged GEMM
 int gemm_tile_m(int tg);                           // rows per tile of geometry tg
 int gemm_tile_n_complex(int tg);                   // complex columns per tile of geometry tg
-bool gemm_legendre_has_geometries(int prec);       // false: the split-form Legendre kernel has one tile
+// Stage (b) slots: the split form's copy-fed kernel alone (one geometry); FP32:
+// the two register-staged geometries and a third, the copy-fed FP32 kernel
+// (128 x 128 tiles); FP64: the two register-staged ones.
+int gemm_legendre_geometries(int prec);
 int gemm_tile_m_legendre(int prec, int tg);        // tile of the stage (b) work items
 int gemm_tile_n_complex_legendre(int prec, int tg);
 // Stage (c) slots: the two register-staged geometries, and for the split form's

@@ -333,7 +333,6 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
   }
   struct Item { int cost; int4 w; };
   const int precb = p->dtype == SGL_F64 ? PREC_F64 : (p->dtype == SGL_F32 ? PREC_F32 : PREC_SPLIT);
-  const int ngeo = gemm_num_geometries();
   std::vector<Item> bf[kMaxTileGeo], bi[kMaxTileGeo], cf[kMaxTileGeo], ci[kMaxTileGeo];
   int ldsm[3] = {0, 0, 0};
   for (int ci_ = 0; ci_ < (int)p->classes.size(); ++ci_) {
@@ -348,7 +347,7 @@ sgl_status_t build_work(sgl_plan_s* p, hipStream_t /*s*/) {
     const int kb = p->seminaive() ? B : L;  // polar-side contraction length
     for (int tg = 0; tg < kMaxTileGeo; ++tg) {
       // stage (b): the split-form Legendre kernel has one tile (geometry 0)
-      if (tg == 0 || (tg < ngeo && gemm_legendre_has_geometries(precb))) {
+      if (tg < gemm_legendre_geometries(precb)) {
         const int BMb = gemm_tile_m_legendre(precb, tg), BNb = gemm_tile_n_complex_legendre(precb, tg);
         for (int m = 0; m < B; ++m) {
           const int rows = B - m;
@@ -727,12 +726,11 @@ sgl_status_t run_direction(sgl_plan_s* p, int dir, const void* in, void* out, hi
 
 // Tile geometries a launch slot can run with: the stage (b)/(c) slots of the
 // register-staged GEMM have two (see gemm_tile_m), the split form's forward
-// radial slot a third (the copy-fed kernel), the FFT slots and the split-form
-// Legendre kernel one.
+// radial slot and the FP32 Legendre slots a third (a copy-fed kernel), the FFT
+// slots and the split-form Legendre kernel one.
 int slot_geometries(const sgl_plan_s* p, int slot) {
   if (slot == S_RAD_F || slot == S_RAD_I) return gemm_radial_geometries(prec_of(p->dtype), slot == S_RAD_I);
-  if (slot == S_LEG_F || slot == S_LEG_I)
-    return gemm_legendre_has_geometries(prec_of(p->dtype)) ? gemm_num_geometries() : 1;
+  if (slot == S_LEG_F || slot == S_LEG_I) return gemm_legendre_geometries(prec_of(p->dtype));
   return 1;
 }
 

@@ -7,10 +7,11 @@ The kernels rely on properties the source can only request:
     cached; a compiler that merges a streaming store with an ordinary one drops
     the hint silently (this happened once), so every store of the forward and
     inverse FFT kernels and of the inverse Legendre kernels must carry it;
-  * the copy-fed inverse Legendre kernel waits for its copies with a vector
-    memory count that assumes exactly 16 epilogue stores per lane and item (the
-    vector-memory counter of the CDNA ISA counts loads, stores and LDS copies of
-    one wave and retires them in issue order), so its code must hold 16 stores;
+  * the copy-fed inverse Legendre kernels (split and FP32) wait for their
+    copies with a vector memory count that assumes exactly 16 epilogue stores
+    per lane and item (the vector-memory counter of the CDNA ISA counts loads,
+    stores and LDS copies of one wave and retires them in issue order), so
+    their code must hold 16 stores;
   * the copy-fed Legendre kernels keep their copies in flight across items, so
     they must load nothing else through the vector-memory path: any register
     load (a class or work-list field read as a vector load) would make its
@@ -73,18 +74,20 @@ def test_fft_kernels_stream_every_store(asm):
 
 
 def test_inverse_legendre_kernels_stream_the_spectrum(asm):
-    for name, body in kernels(asm["gemm"], r"k_legendre_splitILi1E") + kernels(asm["gemm"], r"k_gemmILi\dELi1ELi\dE"):
+    for name, body in kernels(asm["gemm"], r"k_legendre_(?:split|f32)ILi1E") + kernels(asm["gemm"], r"k_gemmILi\dELi1ELi\dE"):
         n, nt = stores(body)
         assert n > 0 and nt == n, (name, n, nt)
 
 
 def test_copy_fed_inverse_legendre_has_sixteen_stores(asm):
-    (name, body), = kernels(asm["gemm"], r"k_legendre_splitILi1E")
-    n, _ = stores(body)
-    assert n == 16, n
+    found = kernels(asm["gemm"], r"k_legendre_(?:split|f32)ILi1E")
+    assert len(found) == 2
+    for name, body in found:
+        n, _ = stores(body)
+        assert n == 16, (name, n)
 
 
 def test_copy_fed_legendre_kernels_load_only_by_copies(asm):
-    for name, body in kernels(asm["gemm"], r"k_legendre_split"):
+    for name, body in kernels(asm["gemm"], r"k_legendre_(?:split|f32)"):
         loads = re.findall(r"^\s+((?:global|flat|buffer)_load\w*)", body, re.M)
         assert loads and all(l == "global_load_lds_dwordx4" for l in loads), (name, sorted(set(loads)))

@@ -5,7 +5,7 @@ For each bandlimit, seeded CN(0,1)/n coefficients are synthesized and
 analysed again by the FP64 plan (the reference), and by the FP32 and
 split-bf16 plans twice: with the default tiles and with every contraction slot
 on its last geometry (the 64 x 32 register-staged tile, and for the split
-form's forward radial slot the copy-fed kernel).  Reduced forms must stay
+form's forward radial slot and the FP32 Legendre slots a copy-fed kernel).  Reduced forms must stay
 within their bars against FP64 (1e-5 FP32, 1e-6 split), FP64 on the small tile
 must equal FP64 on the default one to rounding, and at small bandlimits the
 FP64 results must equal the oracle's synthesis and quadrature sums.  The

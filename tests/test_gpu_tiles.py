@@ -2,11 +2,11 @@
 per-degree grouped contractions of Alg. 3 / Alg. 4, Eq. DLT and Eq. DRT).
 
 The register-staged MFMA GEMM runs with a 128 x 64 (complex) or a 64 x 32 tile,
-and the split form's forward radial slot also on the copy-fed kernel (128 x 128);
-the plan-time autotuner picks one per launch slot.  Every geometry must give the
-default plan's results (same per-element accumulation order, so equal up to
-rounding), hold the oracle's quadrature sums on small ragged plans, and survive
-graph capture.
+and the split form's forward radial slot and the FP32 Legendre slots also on a
+copy-fed kernel (128 x 128); the plan-time autotuner picks one per launch slot.
+Every geometry must give the default plan's results to the form's tolerance,
+hold the oracle's quadrature and synthesis sums on small ragged plans, and
+survive graph capture.
 """
 
 import numpy as np
@@ -76,14 +76,15 @@ def test_every_geometry_matches_default(dtype):
     geos = {q: slot_geometries(base, q) for q in GEMM_SLOTS}
     assert geos[5] == [0, 1]
     # split form: the forward radial slot also runs the copy-fed kernel, the
-    # Legendre slots only it; other forms: the two register-staged tiles
+    # Legendre slots only it; FP32: the Legendre slots also run theirs; other
+    # slots: the two register-staged tiles
     assert geos[4] == ([0, 1, 2] if dtype == "split_bf16" else [0, 1])
-    assert geos[3] == geos[6] == ([0] if dtype == "split_bf16" else [0, 1])
+    assert geos[3] == geos[6] == {"split_bf16": [0], "f32": [0, 1, 2], "f64": [0, 1]}[dtype]
     p = sgl.sgl_plan_ex(Bs, dtype)
     for q in GEMM_SLOTS:
         for g in geos[q]:
             p.set_launch_tile(q, g)
-            copy_fed = dtype == "split_bf16" and (q in (3, 6) or g == 2)
+            copy_fed = g == 2 or (dtype == "split_bf16" and q in (3, 6))
             want = (64, 32) if g == 1 else ((128, 128) if copy_fed else (128, 64))
             assert p.launch_tiles()[q] == want
             f1, i1 = run(p, sgl.sgl_forward, s), run(p, sgl.sgl_inverse, c)
@@ -92,7 +93,7 @@ def test_every_geometry_matches_default(dtype):
             print(f"  slot {q} geometry {g}: forward {ef:.1e}, inverse {ei:.1e}", flush=True)
             assert ef <= TOL[dtype] and ei <= TOL[dtype], (q, g, ef, ei)
         p.set_launch_tile(q, 0)
-    # all slots on the small tile at once
+    # all slots on their last geometry at once
     for q in GEMM_SLOTS:
         p.set_launch_tile(q, geos[q][-1])
     assert einf(f0, run(p, sgl.sgl_forward, s)) <= TOL[dtype]
@@ -144,8 +145,8 @@ def test_tile_change_recaptures_graphs():
 
 def test_bad_tile_requests():
     p = sgl.sgl_plan(8, 1, "f32")
-    for slot, g, status in ((0, 1, 2), (7, 1, 2), (4, 2, 2), (5, 2, 2), (4, 3, 2), (10, 0, 1), (-1, 0, 1),
-                            (4, -1, 1)):
+    for slot, g, status in ((0, 1, 2), (7, 1, 2), (4, 2, 2), (5, 2, 2), (4, 3, 2), (3, 3, 2), (6, 3, 2),
+                            (10, 0, 1), (-1, 0, 1), (4, -1, 1)):
         with pytest.raises(sgl.SglError) as ei:
             p.set_launch_tile(slot, g)
         assert ei.value.status == status, (slot, g)
@@ -158,7 +159,8 @@ def test_autotuner_reports_its_tiles():
     tiles = p.launch_tiles()
     print(f"autotuned tiles {tiles}", flush=True)
     for q in GEMM_SLOTS:
-        assert tiles[q] in ((128, 64), (64, 32)), (q, tiles[q])
+        legendre = q in (3, 6)
+        assert tiles[q] in (((128, 64), (64, 32)) + (((128, 128),) if legendre else ())), (q, tiles[q])
     p.destroy()
 
 
@@ -186,4 +188,40 @@ def test_copy_fed_radial_against_oracle():
         e = np.abs(got - ref).max() / np.abs(ref).max()
         print(f"copy-fed radial B={B}: e_inf {e:.2e}", flush=True)
         assert e <= 2e-6, (B, e)
+    p.destroy()
+
+
+def test_copy_fed_f32_legendre_against_oracle():
+    """FP32 plan with both Legendre contractions on the copy-fed kernel (Eq. DLT
+    and its inverse, 128 x 128 tiles) against the oracle: quadrature sums of
+    non-bandlimited samples (Thm. 3.4) and synthesis sums (Alg. 2) at grid
+    points on every polar row.  Bandlimits whose polar contraction ends
+    mid-chunk (2B = 18, 42; inverse K = B - m of every length up to B), order
+    groups over several column tiles (B = 40, batch 2: 320 columns) and an
+    inverse with two row tiles (2B = 140, the second ragged)."""
+    Bs = [9, 21, 40, 40, 70]
+    p = sgl.sgl_plan_ex(Bs, "f32")
+    for q in (3, 6):
+        p.set_launch_tile(q, 2)
+        assert p.launch_tiles()[q] == (128, 128)
+    so, co = p.offsets()
+    ss = [synth.complex_normal_samples(B, 1, seed=SEED + 70 + q)[0] for q, B in enumerate(Bs)]
+    cs = [synth.complex_normal_coeffs(B, 1, seed=SEED + 80 + q, decay=1.0)[0] for q, B in enumerate(Bs)]
+    f = run(p, sgl.sgl_forward, dev(np.concatenate(ss), torch.complex64)).cpu().numpy()
+    s = run(p, sgl.sgl_inverse, dev(np.concatenate(cs), torch.complex64)).cpu().numpy()
+    rng = np.random.default_rng(SEED + 90)
+    for q, B in enumerate(Bs):
+        n, L = D.num_coeffs(B), 2 * B
+        om = np.unique(np.concatenate([np.arange(min(n, 40)), np.arange(max(0, n - 200), n),
+                                       np.arange(0, n, 1 if B < 10 else 53)]))
+        ref = D.forward(ss[q].astype(np.complex128), B, omegas=om)
+        ef = np.abs(f[co[q]:co[q] + n][om] - ref).max() / np.abs(ref).max()
+        # every polar row j at a few (radius, azimuth) pairs
+        ik = rng.integers(0, L, size=(3 if B > 40 else 6, 2))
+        pts = np.array([(i, j, k) for i, k in ik for j in range(L)])
+        sref = D.inverse(cs[q], B, points=pts)
+        flat = (pts[:, 0] * L + pts[:, 1]) * L + pts[:, 2]
+        ei = np.abs(s[so[q]:so[q] + D.num_samples(B)][flat] - sref).max() / np.abs(sref).max()
+        print(f"copy-fed FP32 Legendre B={B}: forward e_inf {ef:.2e}, inverse e_inf {ei:.2e}", flush=True)
+        assert ef <= 1e-5 and ei <= 1e-5, (B, ef, ei)
     p.destroy()
