@@ -981,7 +981,8 @@ __device__ __forceinline__ void copy_fed(unsigned char* sm, const ClassDesc* __r
   static_assert(BK == 32 && PS == 32, "32-deep chunks; split form: 64-byte table rows");
   constexpr int LA = CopyLds<PREC>::a, SPARE = CopyLds<PREC>::spare;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  // (the wave index is uniform; saying so keeps the row-block tests scalar)
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = (wave >> 3) * 64, wc = (wave & 7) * 16;
   const int lr = lane & 15, lk = lane >> 4;
   // table copies per chunk of this wave (split: 24 of 1 KB, FP32: 16)
@@ -1078,7 +1079,9 @@ __device__ __forceinline__ void copy_fed(unsigned char* sm, const ClassDesc* __r
       nc2 = nchunks(t2);
     }
   }
-  XCol<float> xc = col(t);
+  // copy sources of this item's and the next item's data columns (the next
+  // item's is computed once, when it becomes the next, not at every copy)
+  XCol<float> xc = col(t), xc1 = nc1 > 0 ? col(t1) : xc;
   int run = 0;  // stream index of this item's first chunk, mod 6
   bool first = true;  // no stores of an earlier item are outstanding
   // data chunk at stream position pos of this item (pos >= nc: the next items')
@@ -1087,7 +1090,7 @@ __device__ __forceinline__ void copy_fed(unsigned char* sm, const ClassDesc* __r
     if (pos < nc) {
       copy_x(t, xc, pos * BK, st);
     } else if (pos - nc < nc1) {
-      copy_x(t1, col(t1), (pos - nc) * BK, st);
+      copy_x(t1, xc1, (pos - nc) * BK, st);
     } else if (pos - nc - nc1 < nc2) {
       copy_x(t2, col(t2), (pos - nc - nc1) * BK, st);
     } else {
@@ -1255,7 +1258,7 @@ __device__ __forceinline__ void copy_fed(unsigned char* sm, const ClassDesc* __r
     w += G;
     t = t1;
     nc = nc1;
-    xc = col(t);
+    xc = xc1;
     if (nc2 > 0) {
       t1 = t2;
       nc1 = nc2;
@@ -1266,6 +1269,7 @@ __device__ __forceinline__ void copy_fed(unsigned char* sm, const ClassDesc* __r
         nc1 = nchunks(t1);
       }
     }
+    if (nc1 > 0) xc1 = col(t1);
     nc2 = 0;
     if (nc1 == 1 && w + 2 * G < nwork) {
       t2 = tile(w + 2 * G);
