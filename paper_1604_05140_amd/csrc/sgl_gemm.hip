@@ -789,9 +789,9 @@ k_gemm(const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwo
 
 // ---- split-form Legendre and forward radial stages: operands by global -> LDS
 // copies.  These contractions stream their data operand (the spectrum F and
-// the intermediate g forward, g inverse) and run at the rate at which the CUs
-// keep bytes in flight.  The register-staged kernel above holds one chunk ahead within
-// its register budget.  This kernel moves both operands with 16-byte global ->
+// the intermediate g forward, g inverse).  The register-staged kernel above
+// holds one chunk ahead within its register budget.  This kernel moves both
+// operands with 16-byte global ->
 // LDS copies (no registers, no LDS stores): the table through two LDS stages,
 // the data through three, so that the data of the next two chunks are in
 // flight while a chunk is used, across the boundaries of a block's items.
