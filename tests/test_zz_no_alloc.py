@@ -61,13 +61,15 @@ def test_noalloc_matches_forward_twice():
         p.destroy()
 
 
-def test_noalloc_copy_fed_radial_kernel():
-    """The split form's forward radial slot on the copy-fed kernel (tile
-    geometry 2) reads the class descriptors of the static workspace too."""
+@pytest.mark.parametrize("dtype,slot", [("split_bf16", 4), ("f32", 3)])
+def test_noalloc_copy_fed_kernels(dtype, slot):
+    """A slot on a copy-fed kernel (tile geometry 2: the split form's forward
+    radial slot, the FP32 forward Legendre slot) reads the class descriptors of
+    the static workspace too."""
     Bs = [40, 24]
-    print(f"sgl_forward_noalloc B={Bs} split_bf16, copy-fed radial kernel", flush=True)
-    p = sgl.sgl_plan_ex(Bs, "split_bf16")
-    p.set_launch_tile(4, 2)
+    print(f"sgl_forward_noalloc B={Bs} {dtype}, slot {slot} on the copy-fed kernel", flush=True)
+    p = sgl.sgl_plan_ex(Bs, dtype)
+    p.set_launch_tile(slot, 2)
     ct = p.complex_dtype
     s = samples(Bs, ct, SEED + 50)
     ref = torch.empty(p.total_coeffs, dtype=ct, device=DEV)
