@@ -333,7 +333,20 @@ __device__ inline XCol<T> x_col(const Tile& t, int c, T* base) {
     const int l = t.q;
     const int b = c / (2 * l + 1);
     const int m = c - b * (2 * l + 1) - l;
-    x.p = gmem(base) + 2 * (C.coff[b] + (int64_t)l * (l + 1) + m);
+    // the function's coefficient offset: in closed form when the class's
+    // functions are stored one after another (no per-lane load, which would
+    // wait for every outstanding copy in the copy-fed kernels); a loaded one
+    // is consumed in its own branch, so that the wait stays there and not
+    // after the two paths join
+    const int64_t cstep = load_uniform(&C.cstep);
+    int64_t cb;
+    if (cstep) {
+      cb = load_uniform(&C.cbase) + b * cstep;
+    } else {
+      cb = gmem(load_uniform(&C.coff))[b];
+      asm volatile("" ::"v"(cb));
+    }
+    x.p = gmem(base) + 2 * (cb + (int64_t)l * (l + 1) + m);
   }
   return x;
 }
@@ -978,7 +991,7 @@ template <int PREC, int KIND>
 __device__ __forceinline__ void copy_fed(unsigned char* sm, const ClassDesc* __restrict__ cls,
                                          const int4* __restrict__ work, int nwork, void* __restrict__ coeffs) {
   static_assert(KIND == K_B_FWD || KIND == K_B_INV || KIND == K_C_FWD, "Legendre kinds and the forward radial kind");
-  static_assert(PREC == PREC_SPLIT || (PREC == PREC_F32 && KIND != K_C_FWD), "split form, or FP32 Legendre");
+  static_assert(PREC == PREC_SPLIT || PREC == PREC_F32, "split or FP32 form");
   constexpr bool RAD = KIND == K_C_FWD;
   constexpr int BK = Cfg<PREC>::BK, PS = Cfg<PREC_SPLIT>::PS;
   static_assert(BK == 32 && PS == 32, "32-deep chunks; split form: 64-byte table rows");
@@ -1305,6 +1318,14 @@ __global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_
   copy_fed<PREC_F32, KIND>(sm, cls, work, nwork, nullptr);
 }
 
+// FP32 forward radial contraction (Eq. DRT) on the copy-fed design: the split
+// form's radial data path with the FP32 table stage and MFMA steps.
+__global__ void __launch_bounds__(LT) __attribute__((amdgpu_waves_per_eu(4))) k_radial_f32(
+    const ClassDesc* __restrict__ cls, const int4* __restrict__ work, int nwork, void* __restrict__ coeffs) {
+  __shared__ __align__(16) unsigned char sm[CopyLds<PREC_F32>::total];
+  copy_fed<PREC_F32, K_C_FWD>(sm, cls, work, nwork, coeffs);
+}
+
 inline int grid_for(int nwork, int max_grid) {
   const int g = max_grid > 0 ? max_grid : 8192;
   return nwork < g ? nwork : g;
@@ -1338,6 +1359,10 @@ hipError_t launch_kind(int kind, int tg, const ClassDesc* d_cls, const int4* d_w
   if (nwork == 0) return hipSuccess;
   dim3 grid(grid_for(nwork, max_grid));
   if constexpr (PREC == PREC_F32) {
+    if (tg == kNumGeo && kind == K_C_FWD) {
+      hipLaunchKernelGGL(k_radial_f32, grid, dim3(LT), 0, s, d_cls, d_work, nwork, cout);
+      return hipGetLastError();
+    }
     if (tg == kNumGeo && kind == K_B_FWD) {
       hipLaunchKernelGGL((k_legendre_f32<K_B_FWD>), grid, dim3(LT), 0, s, d_cls, d_work, nwork);
       return hipGetLastError();
@@ -1381,7 +1406,7 @@ int gemm_tile_n_complex_legendre(int prec, int tg) {
   return prec == PREC_SPLIT || tg == kNumGeo ? LBNC : gemm_tile_n_complex(tg);
 }
 int gemm_tile_m_legendre(int prec, int tg) { return prec == PREC_SPLIT || tg == kNumGeo ? BM : gemm_tile_m(tg); }
-int gemm_radial_geometries(int prec, bool inverse) { return prec == PREC_SPLIT && !inverse ? kNumGeo + 1 : kNumGeo; }
+int gemm_radial_geometries(int prec, bool inverse) { return prec != PREC_F64 && !inverse ? kNumGeo + 1 : kNumGeo; }
 int gemm_tile_m_radial(int tg) { return tg == kNumGeo ? BM : gemm_tile_m(tg); }
 int gemm_tile_n_complex_radial(int tg) { return tg == kNumGeo ? LBNC : gemm_tile_n_complex(tg); }
 int gemm_k_chunk(int prec) {

@@ -124,6 +124,10 @@ struct ClassDesc {
   // (seminaive step: cosine-domain sums over k < B, Sect. 3.3.1)
   int kb;
   const void* dct;  // DCT constants of the seminaive step (dct_const_count(B) complex), else null
+  // coefficient offsets in closed form: coff[b] = cbase + b * cstep when the
+  // class's functions are stored one after another (cstep = the coefficient
+  // count of B); cstep = 0 when coff must be read
+  int64_t cbase, cstep;
 };
 // naive / midpoint forward items group this many consecutive degrees n
 constexpr int kNaiveGroup = 8;

@@ -482,6 +482,13 @@ sgl_status_t make_plan(sgl_plan_s* p, hipStream_t s) {
     for (int q = 0; q < d.nrad; ++q) d.rad[q] = c.radices[q];
     d.soff = c.soff;
     d.coff = c.coff;
+    {
+      const int64_t om = (int64_t)c.B * (c.B + 1) * (2 * c.B + 1) / 6;
+      bool affine = true;
+      for (size_t q = 0; q < c.funcs.size(); ++q) affine = affine && p->coff[c.funcs[q]] == p->coff[c.funcs[0]] + (int64_t)q * om;
+      d.cbase = p->coff[c.funcs[0]];
+      d.cstep = affine ? om : 0;
+    }
     for (int k = 0; k < 4; ++k) {
       d.A[k] = c.A[k];
       d.Aoff[k] = c.Aoff[k];

@@ -2,8 +2,8 @@
 per-degree grouped contractions of Alg. 3 / Alg. 4, Eq. DLT and Eq. DRT).
 
 The register-staged MFMA GEMM runs with a 128 x 64 (complex) or a 64 x 32 tile,
-and the split form's forward radial slot and the FP32 Legendre slots also on a
-copy-fed kernel (128 x 128); the plan-time autotuner picks one per launch slot.
+and the forward radial slot (split and FP32 forms) and the FP32 Legendre slots
+also on a copy-fed kernel (128 x 128); the plan-time autotuner picks one per launch slot.
 Every geometry must give the default plan's results to the form's tolerance,
 hold the oracle's quadrature and synthesis sums on small ragged plans, and
 survive graph capture.
@@ -76,9 +76,9 @@ def test_every_geometry_matches_default(dtype):
     geos = {q: slot_geometries(base, q) for q in GEMM_SLOTS}
     assert geos[5] == [0, 1]
     # split form: the forward radial slot also runs the copy-fed kernel, the
-    # Legendre slots only it; FP32: the Legendre slots also run theirs; other
-    # slots: the two register-staged tiles
-    assert geos[4] == ([0, 1, 2] if dtype == "split_bf16" else [0, 1])
+    # Legendre slots only it; FP32: the Legendre slots and the forward radial
+    # slot also run theirs; other slots: the two register-staged tiles
+    assert geos[4] == ([0, 1] if dtype == "f64" else [0, 1, 2])
     assert geos[3] == geos[6] == {"split_bf16": [0], "f32": [0, 1, 2], "f64": [0, 1]}[dtype]
     p = sgl.sgl_plan_ex(Bs, dtype)
     for q in GEMM_SLOTS:
@@ -145,7 +145,7 @@ def test_tile_change_recaptures_graphs():
 
 def test_bad_tile_requests():
     p = sgl.sgl_plan(8, 1, "f32")
-    for slot, g, status in ((0, 1, 2), (7, 1, 2), (4, 2, 2), (5, 2, 2), (4, 3, 2), (3, 3, 2), (6, 3, 2),
+    for slot, g, status in ((0, 1, 2), (7, 1, 2), (5, 2, 2), (4, 3, 2), (3, 3, 2), (6, 3, 2),
                             (10, 0, 1), (-1, 0, 1), (4, -1, 1)):
         with pytest.raises(sgl.SglError) as ei:
             p.set_launch_tile(slot, g)
@@ -159,19 +159,20 @@ def test_autotuner_reports_its_tiles():
     tiles = p.launch_tiles()
     print(f"autotuned tiles {tiles}", flush=True)
     for q in GEMM_SLOTS:
-        legendre = q in (3, 6)
-        assert tiles[q] in (((128, 64), (64, 32)) + (((128, 128),) if legendre else ())), (q, tiles[q])
+        copy_fed = q in (3, 4, 6)  # FP32 slots with a copy-fed geometry
+        assert tiles[q] in (((128, 64), (64, 32)) + (((128, 128),) if copy_fed else ())), (q, tiles[q])
     p.destroy()
 
 
-def test_copy_fed_radial_against_oracle():
-    """Split plan with the forward radial contraction on the copy-fed kernel
-    (Eq. DRT, 128 x 128 tiles) against the oracle's quadrature sums of
+@pytest.mark.parametrize("dtype", ["split_bf16", "f32"])
+def test_copy_fed_radial_against_oracle(dtype):
+    """Split and FP32 plans with the forward radial contraction on the copy-fed
+    kernel (Eq. DRT, 128 x 128 tiles) against the oracle's quadrature sums of
     non-bandlimited samples (Thm. 3.4): bandlimits whose K = 2B ends mid-chunk
     (B = 9, 21) and whose degree groups span several column tiles (B = 40,
     batch 2: up to 316 columns)."""
     Bs = [9, 21, 40, 40]
-    p = sgl.sgl_plan_ex(Bs, "split_bf16")
+    p = sgl.sgl_plan_ex(Bs, dtype)
     p.set_launch_tile(4, 2)
     assert p.launch_tiles()[4] == (128, 128)
     so, co = p.offsets()
@@ -186,7 +187,7 @@ def test_copy_fed_radial_against_oracle():
         ref = D.forward(ss[q].astype(np.complex128), B, omegas=om)
         got = f[co[q]:co[q] + n][om]
         e = np.abs(got - ref).max() / np.abs(ref).max()
-        print(f"copy-fed radial B={B}: e_inf {e:.2e}", flush=True)
+        print(f"copy-fed radial {dtype} B={B}: e_inf {e:.2e}", flush=True)
         assert e <= 2e-6, (B, e)
     p.destroy()
 

@@ -61,11 +61,11 @@ def test_noalloc_matches_forward_twice():
         p.destroy()
 
 
-@pytest.mark.parametrize("dtype,slot", [("split_bf16", 4), ("f32", 3)])
+@pytest.mark.parametrize("dtype,slot", [("split_bf16", 4), ("f32", 3), ("f32", 4)])
 def test_noalloc_copy_fed_kernels(dtype, slot):
-    """A slot on a copy-fed kernel (tile geometry 2: the split form's forward
-    radial slot, the FP32 forward Legendre slot) reads the class descriptors of
-    the static workspace too."""
+    """A slot on a copy-fed kernel (tile geometry 2: the forward radial slot of
+    the split and FP32 forms, the FP32 forward Legendre slot) reads the class
+    descriptors of the static workspace too."""
     Bs = [40, 24]
     print(f"sgl_forward_noalloc B={Bs} {dtype}, slot {slot} on the copy-fed kernel", flush=True)
     p = sgl.sgl_plan_ex(Bs, dtype)
