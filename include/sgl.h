@@ -150,8 +150,8 @@ sgl_status_t sgl_launch_grids(sgl_plan_t plan, int* grids);
  * of stage (c), and stage (b) in SGL_F64 and SGL_F32) have two tile geometries:
  *   geometry 0: 128 rows x 64 complex columns, 8 wavefronts (the default),
  *   geometry 1:  64 rows x 32 complex columns, 4 wavefronts,
- * and the forward radial slot of SGL_SPLIT_BF16 and both Legendre slots of
- * SGL_F32 a third,
+ * and the forward radial slot of SGL_SPLIT_BF16 and SGL_F32 and both Legendre
+ * slots of SGL_F32 a third,
  *   geometry 2: 128 rows x 128 complex columns on a copy-fed kernel
  *               (operands by global -> LDS copies, 16 wavefronts);
  * SGL_AUTOTUNE times each (with each persistent grid) and keeps the fastest.

@@ -44,10 +44,10 @@
 //
 // The split-form Legendre contractions (both directions) have a kernel of
 // their own, k_legendre_split below, fed by global -> LDS copies; the forward
-// radial contraction of the split form and the FP32 Legendre contractions run
-// on the same design as a third tile geometry of their slots (k_radial_split,
-// k_legendre_f32), which the plan-time autotuner weighs against the two of
-// this kernel.
+// radial contractions of the split and FP32 forms and the FP32 Legendre
+// contractions run on the same design as a third tile geometry of their slots
+// (k_radial_split, k_radial_f32, k_legendre_f32), which the plan-time
+// autotuner weighs against the two of this kernel.
 #include "sgl_internal.h"
 
 namespace sgl {

@@ -215,8 +215,9 @@ int gemm_tile_n_complex(int tg);                   // complex columns per tile o
 int gemm_legendre_geometries(int prec);
 int gemm_tile_m_legendre(int prec, int tg);        // tile of the stage (b) work items
 int gemm_tile_n_complex_legendre(int prec, int tg);
-// Stage (c) slots: the two register-staged geometries, and for the split form's
-// forward contraction a third, the copy-fed kernel (128 x 128 tiles).
+// Stage (c) slots: the two register-staged geometries, and for the forward
+// contraction of the split and FP32 forms a third, the copy-fed kernel (128 x
+// 128 tiles).
 constexpr int kMaxTileGeo = 3;
 int gemm_radial_geometries(int prec, bool inverse);
 int gemm_tile_m_radial(int tg);

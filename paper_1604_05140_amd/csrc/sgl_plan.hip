@@ -732,9 +732,9 @@ sgl_status_t run_direction(sgl_plan_s* p, int dir, const void* in, void* out, hi
 }
 
 // Tile geometries a launch slot can run with: the stage (b)/(c) slots of the
-// register-staged GEMM have two (see gemm_tile_m), the split form's forward
-// radial slot and the FP32 Legendre slots a third (a copy-fed kernel), the FFT
-// slots and the split-form Legendre kernel one.
+// register-staged GEMM have two (see gemm_tile_m), the forward radial slot of
+// the split and FP32 forms and the FP32 Legendre slots a third (a copy-fed
+// kernel), the FFT slots and the split-form Legendre kernel one.
 int slot_geometries(const sgl_plan_s* p, int slot) {
   if (slot == S_RAD_F || slot == S_RAD_I) return gemm_radial_geometries(prec_of(p->dtype), slot == S_RAD_I);
   if (slot == S_LEG_F || slot == S_LEG_I) return gemm_legendre_geometries(prec_of(p->dtype));
