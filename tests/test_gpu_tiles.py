@@ -170,8 +170,10 @@ def test_copy_fed_radial_against_oracle(dtype):
     kernel (Eq. DRT, 128 x 128 tiles) against the oracle's quadrature sums of
     non-bandlimited samples (Thm. 3.4): bandlimits whose K = 2B ends mid-chunk
     (B = 9, 21) and whose degree groups span several column tiles (B = 40,
-    batch 2: up to 316 columns)."""
-    Bs = [9, 21, 40, 40]
+    batch 2: up to 316 columns).  The two B = 40 functions are not stored one
+    after another, so the kernel reads their coefficient offsets (the other
+    tests' classes take the closed form)."""
+    Bs = [40, 9, 21, 40]
     p = sgl.sgl_plan_ex(Bs, dtype)
     p.set_launch_tile(4, 2)
     assert p.launch_tiles()[4] == (128, 128)
