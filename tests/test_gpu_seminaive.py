@@ -116,10 +116,12 @@ def test_fp64_seminaive_large_b(B, batch):
     direct.destroy()
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("split_bf16", 1e-6)])
-def test_seminaive_precision_forms(dtype, tol):
+@pytest.mark.parametrize("dtype,tol,copy_fed", [("f32", 1e-5, False), ("f32", 1e-5, True), ("split_bf16", 1e-6, False)])
+def test_seminaive_precision_forms(dtype, tol, copy_fed):
     """B = 128, batch 2, CN(0,1)/n: the FP32 and split-bf16 seminaive forms
-    against the FP64 direct path (the bars of the direct forms)."""
+    against the FP64 direct path (the bars of the direct forms); FP32 also with
+    its Legendre slots (cosine-domain contraction length B) and forward radial
+    slot on the copy-fed kernels."""
     B, batch = 128, 2
     c = synth.complex_normal_coeffs(B, batch, seed=SEED + 400, decay=1.0)
     c_dev = dev(c, torch.complex128)
@@ -127,12 +129,16 @@ def test_seminaive_precision_forms(dtype, tol):
     s64 = run(p64, c_dev, False)
     c64 = run(p64, s64, True)
     p = sgl.sgl_plan_ex([B] * batch, dtype, sgl.SGL_SEMINAIVE)
+    if copy_fed:
+        for slot in (3, 4, 6):
+            p.set_launch_tile(slot, 2)
+            assert p.launch_tiles()[slot] == (128, 128)
     cf = run(p, s64.to(torch.complex64), True)
     sf = run(p, c_dev.to(torch.complex64), False)
     nc, ns = D.num_coeffs(B), D.num_samples(B)
     ef = max(einf_dev(c64[b * nc:(b + 1) * nc], cf[b * nc:(b + 1) * nc]) for b in range(batch))
     ei = max(einf_dev(s64[b * ns:(b + 1) * ns], sf[b * ns:(b + 1) * ns]) for b in range(batch))
-    print(f"seminaive {dtype}: forward e_inf {ef:.2e}, inverse e_inf {ei:.2e}", flush=True)
+    print(f"seminaive {dtype} copy_fed={copy_fed}: forward e_inf {ef:.2e}, inverse e_inf {ei:.2e}", flush=True)
     assert ef <= tol and ei <= tol
     p.destroy()
     p64.destroy()
