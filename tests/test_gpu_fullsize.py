@@ -64,10 +64,17 @@ def run(plan, fn, x):
     return out
 
 
-def check_forward(B, dtype, tol, flags=0):
-    z, s, _ = fixture(B)
-    print(f"full-size forward B={B} {dtype} flags={flags}", flush=True)
+def make_plan(B, dtype, flags, tiles):
     plan = sgl.sgl_plan_ex([B], dtype, flags)
+    for slot, g in (tiles or {}).items():
+        plan.set_launch_tile(slot, g)
+    return plan
+
+
+def check_forward(B, dtype, tol, flags=0, tiles=None):
+    z, s, _ = fixture(B)
+    print(f"full-size forward B={B} {dtype} flags={flags} tiles={tiles}", flush=True)
+    plan = make_plan(B, dtype, flags, tiles)
     got = run(plan, sgl.sgl_forward, s).cpu().numpy()
     plan.destroy()
     ref = z["forward"]
@@ -86,12 +93,12 @@ def check_forward(B, dtype, tol, flags=0):
     assert e <= tol, (B, dtype, e, worst)
 
 
-def check_inverse(B, dtype, tol, flags=0):
+def check_inverse(B, dtype, tol, flags=0, tiles=None):
     z, _, c = fixture(B)
-    print(f"full-size inverse B={B} {dtype} flags={flags}", flush=True)
+    print(f"full-size inverse B={B} {dtype} flags={flags} tiles={tiles}", flush=True)
     pts = z["points"]
     ref = z["inverse"]
-    plan = sgl.sgl_plan_ex([B], dtype, flags)
+    plan = make_plan(B, dtype, flags, tiles)
     got_t = run(plan, sgl.sgl_inverse, c)
     plan.destroy()
     got = got_t[torch.from_numpy(psi_of(pts, B)).to(DEV)].cpu().numpy()
@@ -123,6 +130,15 @@ def test_forward_against_stored_oracle_sums(B, dtype, tol):
 @pytest.mark.parametrize("dtype,tol", FORMS)
 def test_inverse_against_stored_oracle_sums(B, dtype, tol):
     check_inverse(B, dtype, tol)
+
+
+@pytest.mark.parametrize("B", [128, 256])
+def test_fp32_copy_fed_kernels_against_stored_oracle_sums(B):
+    """The FP32 form with both Legendre slots and the forward radial slot on
+    the copy-fed kernels (tile geometry 2), at the full sizes."""
+    tiles = {3: 2, 4: 2, 6: 2}
+    check_forward(B, "f32", 1e-5, tiles=tiles)
+    check_inverse(B, "f32", 1e-5, tiles=tiles)
 
 
 @pytest.mark.parametrize("B,dtype,tol", [(128, "f64", 1e-12), (256, "f64", 1e-12), (128, "split_bf16", 1e-6),
