@@ -672,6 +672,8 @@ def main():
             "launch_grids": plan.launch_grids(),
             "launch_tiles": plan.launch_tiles(),
         }
+        # every stage of this form against HBM and against its own dtype's MFMA peak
+        forms[key]["stage_roofline"] = stage_rooflines(forms[key], key.replace("_eager", ""), B, nf)
         print(f"[bench] {key}: {ms:.3f} ms/step, {nf * 1000.0 / ms:.1f} transforms/s "
               f"(stage-timed pass {ms_inst:.3f} ms/step)", file=sys.stderr, flush=True)
         del cout, sout
