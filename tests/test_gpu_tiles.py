@@ -143,6 +143,36 @@ def test_tile_change_recaptures_graphs():
     p.destroy()
 
 
+def test_copy_fed_geometries_in_graph_replays():
+    """FP32 plan with the Legendre slots and the forward radial slot on the
+    copy-fed kernels, captured in hipGraphs: several replays of the forward and
+    the inverse, with eager work and synchronizations between them, each equal
+    to the eager plan's results on the same tiles."""
+    Bs = [40, 24, 40]
+    eager = sgl.sgl_plan_ex(Bs, "f32")
+    graph = sgl.sgl_plan_ex(Bs, "f32", sgl.SGL_GRAPHS)
+    for p in (eager, graph):
+        for q in (3, 4, 6):
+            p.set_launch_tile(q, 2)
+    s = dev(np.concatenate([synth.complex_normal_samples(B, 1, seed=SEED + 100 + q)[0] for q, B in enumerate(Bs)]),
+            torch.complex64)
+    c = dev(np.concatenate([synth.complex_normal_coeffs(B, 1, seed=SEED + 110 + q, decay=1.0)[0]
+                            for q, B in enumerate(Bs)]), torch.complex64)
+    f0, i0 = run(eager, sgl.sgl_forward, s), run(eager, sgl.sgl_inverse, c)
+    fo = torch.empty_like(f0)
+    io = torch.empty_like(i0)
+    for rep in range(4):
+        fo.fill_(float("nan"))
+        io.fill_(float("nan"))
+        sgl.sgl_forward(graph, s, fo)
+        sgl.sgl_inverse(graph, c, io)
+        torch.cuda.synchronize()
+        assert torch.equal(fo, f0) and torch.equal(io, i0), rep
+        _ = (s.abs() * 2).sum().item()  # eager work between replays
+    eager.destroy()
+    graph.destroy()
+
+
 def test_bad_tile_requests():
     p = sgl.sgl_plan(8, 1, "f32")
     for slot, g, status in ((0, 1, 2), (7, 1, 2), (5, 2, 2), (4, 3, 2), (3, 3, 2), (6, 3, 2),
